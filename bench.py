@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 4th-order stencil hot path on one MI355X.
+
+Headline: classical RK4 of the 3-D scalar wave equation (first-order form)
+on one 256^3 periodic box with 2 ghost zones, h = 1/256, dt = h/4, inputs
+u = U + Gaussian pulse (sigma 0.1), rho = U with U uniform in [-1, 1)
+(seeded splitmix64).  A step is one RK4 step: four fused stage kernels
+(Laplacian + stage update + running sum, periodic addressing), captured
+once in a hipGraph and replayed.  value = interior points x RK4 steps / s.
+
+The same JSON line also reports, each on its own workload:
+  rhs      one 4th-order Laplacian RHS on the 256^3 box (ghosts read), with
+           four rotating buffer sets so no pass finds its data in the
+           256 MB last-level cache
+  copy     a streaming copy of 1 GiB (achievable HBM bandwidth)
+  batched  one RK4 step over a 60-box, 3-level bboxset (sides 16..96, 3
+           ghosts) in per-box launches, one persistent batched launch per
+           stage, and the batched step replayed as a hipGraph
+  adjoint  loss and gradient through 50 RK4 steps on a 128^3 box with
+           variable c^2, checkpoint every 10 steps
+and, on rank 0 at N=1, the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections ...]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoint-updates/s + % HBM peak, 4th-order 3D stencil RHS; batched & adjoint"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("s4_kernels.hip", "s4_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1308_1343_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_key, launches_bytes):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel_key)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sections", default="rk4,rhs,copy,batched,adjoint,cpu")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    sections = set(args.sections.split(","))
+
+    import numpy as np
+    import torch
+
+    import paper_1308_1343_amd as S
+    import workload as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = S.Context(0)
+    K, WU = args.steps, args.warmup
+    out = {}
+
+    # ------------------------------------------------------------------ RK4 256^3 (headline)
+    d = W.wave256()
+    g = d["ghost"]
+    n = d["n"]
+    npts = n[0] * n[1] * n[2]
+
+    def to_dev(a):
+        t = S.alloc_field(n, g, fill=0.0)
+        S.interior(t, g).copy_(torch.from_numpy(a))
+        return t
+
+    u, rho = to_dev(d["u"]), to_dev(d["rho"])
+    box = S.box_of(u, g, d["dx"])
+    ws = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
+    choice = S.s4_get_choice(ctx, S.S4_OP_RK4, box)
+    stream = torch.cuda.current_stream()
+    log(f"[bench] rk4 256^3: warmup {WU} steps, tile {choice}")
+    S.s4_rk4(ctx, box, [u], [rho], None, d["dt"], WU, "graph", ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    S.s4_rk4(ctx, box, [u], [rho], None, d["dt"], K, "graph", ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    finite = bool(torch.isfinite(S.interior(u, g)).all().item())
+    log(f"[bench] rk4 256^3: {K} steps in {wall * 1e3:.2f} ms wall, {ev_ms:.2f} ms events, finite={finite}")
+    value = npts * K / wall / 1e9
+    # dominant kernel: the fused stage kernel, 4 launches per step, nothing else in the timed region
+    stage_bytes = [6, 10, 10, 6]  # 8-byte accesses per point: reads + writes of stages 1..4
+    bytes_per_launch = npts * 8 * sum(stage_bytes) / 4
+    launch_s = ev_ms / 1e3 / (4 * K)
+    achieved = bytes_per_launch / launch_s / 1e9
+    kname = f"k_tiles_single<{choice['tile_x']},{choice['threads'] // 64},periodic,stage>"
+    traffic = traffic_from_profile("stage_wave256", bytes_per_launch)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kname, "avg_launch_us": round(launch_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "bytes_per_point_step": 8 * sum(stage_bytes)}
+    del u, rho, ws
+
+    # ------------------------------------------------------------------ RHS 256^3, rotating buffers
+    if "rhs" in sections:
+        nset = 4
+        us = [to_dev(d["u"]) for _ in range(nset)]
+        for t in us:
+            S.s4_fill_ghosts_periodic(ctx, box, [t])
+        outs = [S.alloc_field(n, g, fill=0.0) for _ in range(nset)]
+        reps = max(20, K // 2)
+        for i in range(8):
+            S.s4_wave_rhs(ctx, box, [us[i % nset]], None, [outs[i % nset]])
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            S.s4_wave_rhs(ctx, box, [us[i % nset]], None, [outs[i % nset]])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = npts * 16 / (ms / 1e3) / 1e9
+        ch = S.s4_get_choice(ctx, S.S4_OP_WAVE_RHS, box)
+        out["rhs"] = {"workload": "wave256 single RHS (ghosts read, c=1)", "us_per_rhs": round(ms * 1e3, 2),
+                      "gpoint_per_s": round(npts / (ms / 1e3) / 1e9, 1), "achieved_GBs": round(gbs, 1),
+                      "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": 16,
+                      "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                      "traffic": traffic_from_profile("rhs_wave256", npts * 16)}
+        log(f"[bench] rhs: {out['rhs']}")
+        del us, outs
+
+    # ------------------------------------------------------------------ copy probe
+    if "copy" in sections:
+        nb = 1 << 30
+        a = torch.empty(nb // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            S.s4_copy(ctx, b, a)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(10):
+            S.s4_copy(ctx, b, a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out["copy"] = {"bytes": 2 * nb, "us": round(ms * 1e3, 1), "GBs": round(2 * nb / (ms / 1e3) / 1e9, 1)}
+        log(f"[bench] copy: {out['copy']}")
+        del a, b
+
+    # ------------------------------------------------------------------ batched bboxset
+    if "batched" in sections:
+        bd = W.bboxset()
+        gb = bd["ghost"]
+        fields, boxes = [], []
+        for i, bx in enumerate(bd["boxes"]):
+            fu = S.alloc_field(bx["n"], gb, fill=0.0)
+            fr = S.alloc_field(bx["n"], gb, fill=0.0)
+            S.interior(fu, gb).copy_(torch.from_numpy(bd["u"][i]))
+            S.interior(fr, gb).copy_(torch.from_numpy(bd["rho"][i]))
+            fields.append((fu, fr))
+            boxes.append(S.box_of(fu, gb, bx["dx"], bx["level"]))
+        bpts = sum(int(np.prod(bx["n"])) for bx in bd["boxes"])
+        wsb = S.workspace(S.s4_workspace_size(boxes, S.S4_OP_RK4, S.S4_GRAPH))
+        us_ = [f[0] for f in fields]
+        rs_ = [f[1] for f in fields]
+        res = {}
+        kb = max(10, K // 5)
+        for mode in ("perbox", "batched", "graph"):
+            S.s4_rk4(ctx, boxes, us_, rs_, None, bd["dt"], 3, mode, ws=wsb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            S.s4_rk4(ctx, boxes, us_, rs_, None, bd["dt"], kb, mode, ws=wsb)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            w_ = time.perf_counter() - t0
+            res[mode] = {"ms_per_step": round(w_ * 1e3 / kb, 4), "gpoint_steps_per_s": round(bpts * kb / w_ / 1e9, 2),
+                         "event_ms_per_step": round(e0.elapsed_time(e1) / kb, 4)}
+        ch = S.s4_get_choice(ctx, S.S4_OP_RK4, boxes)
+        out["batched"] = {"workload": "bboxset60: 3 levels x 20 boxes, sides U[16,96], g=3, 1 RK4 step",
+                          "interior_points": bpts, "steps": kb, "modes": res,
+                          "speedup_batched_vs_perbox": round(res["perbox"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
+                          "speedup_graph_vs_perbox": round(res["perbox"]["ms_per_step"] / res["graph"]["ms_per_step"], 3),
+                          "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                          "launches_per_step": {"perbox": 4 * len(boxes), "batched": 4, "graph": 1}}
+        log(f"[bench] batched: {out['batched']}")
+        del fields, us_, rs_, wsb
+
+    # ------------------------------------------------------------------ adjoint
+    if "adjoint" in sections:
+        from paper_1308_1343_amd.autograd import wave_rk4
+        ad = W.adjoint_case()
+        ga = ad["ghost"]
+        na = ad["n"]
+        apts = na[0] * na[1] * na[2]
+
+        def compact(a, fill=0.0):
+            t = torch.full((na[2] + 2 * ga, na[1] + 2 * ga, na[0] + 2 * ga), fill, dtype=torch.float64, device=dev)
+            S.interior(t, ga).copy_(torch.from_numpy(a))
+            return t
+
+        u0, r0, c2, ut = compact(ad["u0"]), compact(ad["rho0"]), compact(ad["c2"], 1.0), compact(ad["u_target"])
+        times = []
+        for rep in range(2):
+            u0.requires_grad_(True)
+            r0.requires_grad_(True)
+            c2.requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uT, rT = wave_rk4(u0, r0, c2, ga, ad["dx"], ad["dt"], ad["nsteps"], ad["checkpoint"], ctx)
+            diff = S.interior(uT, ga) - S.interior(ut, ga)
+            J = 0.5 * (diff * diff).sum()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            J.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append((t1 - t0, t2 - t1))
+            gu = u0.grad
+            u0.grad = r0.grad = c2.grad = None
+            u0, r0, c2 = u0.detach(), r0.detach(), c2.detach()
+        tf, tb = times[-1]
+        out["adjoint"] = {"workload": "adjoint128: 128^3, variable c^2, 50 RK4 steps, checkpoint every 10",
+                          "forward_s": round(tf, 4), "backward_s": round(tb, 4),
+                          "forward_gpoint_steps_per_s": round(apts * ad["nsteps"] / tf / 1e9, 2),
+                          "backward_gpoint_steps_per_s": round(apts * ad["nsteps"] / tb / 1e9, 2),
+                          "backward_over_forward": round(tb / tf, 2), "loss": float(J.item()),
+                          "grad_finite": bool(torch.isfinite(gu).all().item())}
+        log(f"[bench] adjoint: {out['adjoint']}")
+
+    # ------------------------------------------------------------------ CPU oracle baseline
+    cpu = None
+    if "cpu" in sections:
+        import oracle as O
+        u0 = O.embed(d["u"], g)
+        r0 = O.embed(d["rho"], g)
+        O.rk4(u0, r0, g, d["dx"], d["dt"], 1)  # untimed: first touch of the oracle's scratch
+        t0 = time.perf_counter()
+        O.rk4(u0, r0, g, d["dx"], d["dt"], 1)
+        one = time.perf_counter() - t0
+        m = int(min(100, max(2, math.ceil(12.0 / max(one, 1e-3)))))
+        t0 = time.perf_counter()
+        O.rk4(u0, r0, g, d["dx"], d["dt"], m)
+        el = time.perf_counter() - t0
+        cpu = {"value": round(npts * m / el / 1e9, 5), "unit": "Gpoint-updates/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"{m} RK4 steps of the 256^3 wave workload (after one untimed warm-up step), "
+                         f"plain C FP64 oracle with OpenMP, {el:.1f} s"}
+        log(f"[bench] cpu: {cpu}")
+
+    rec = {"metric": METRIC, "value": round(value, 3), "unit": "Gpoint-updates/s", "n_gpus": 1, "steps": K,
+           "warmup": WU, "ms_per_step": round(wall * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "wave256_rk4: 256^3 interior + 2 ghosts, periodic, FP64, h=1/256, dt=h/4, "
+                                  "u=U+Gaussian(0.1), rho=U, RK4 steps (hipGraph of 4 fused stage kernels)",
+                      "points": npts, "seed": d["seed"], "tile": [choice["tile_x"], choice["tile_y"],
+                                                                   choice["z_chunk"], choice["threads"]]},
+           "roofline": roof, "cpu_baseline": cpu}
+    rec.update(out)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * sten4.h -- C ABI of libsten4.so: FP64 4th-order finite-difference stencils,
+ * classical RK4 and its discrete adjoint over the boxes of one refinement
+ * level of a block-structured AMR grid, as hand-written HIP kernels for
+ * gfx950 (MI355X).
+ *
+ * What the library models (Schnetter, "Performance and Optimization
+ * Abstractions for Large Scale Heterogeneous Systems in the Cactus/Chemora
+ * Framework"):
+ *   - a refinement level is a set of non-overlapping boxes ("bboxset") on a
+ *     uniform grid, each point at x0 + n*dx with integer n, and each box maps
+ *     directly to an array in memory (Sec. II);
+ *   - stencil loop kernels run over every box, reading ghost zones that hold
+ *     copies of neighbouring points (Sec. II, II-A);
+ *   - the loop over a box's index space declares its array alignment and
+ *     padding, and is split into tiles, threads and vector lanes, with edge
+ *     masks only at the box boundary (Sec. III-A, Sec. IV-C4 "Iterators").
+ * The discrete operators are the textbook ones the paper leaves to the
+ * application: 4th-order centred five-point differences, the classical RK4
+ * tableau, and reverse-mode differentiation of that RK4 step.
+ *
+ * ---------------------------------------------------------------------------
+ * Layout.  A field of a box is FP64, C order [z][y][x], x unit stride.  The
+ * field pointer points at the ghost corner (-g,-g,-g); interior point
+ * (i,j,k), 0 <= i < n[0] etc., lives at
+ *     ptr + (i+g) + (j+g)*stride[1] + (k+g)*stride[2].
+ * stride[0] must be 1, stride[1] >= n[0]+2g, stride[2] >= stride[1]*(n[1]+2g)
+ * (padding allowed).  All fields of one box share its strides.  A row whose
+ * interior start (ptr + g) is 128-byte aligned and whose stride[1] is a
+ * multiple of 16 gives the fastest loads; any 8-byte aligned layout is valid.
+ *
+ * Memory ownership.  Every field, output and workspace buffer is device
+ * memory owned by the caller; the library never allocates device memory for
+ * data and never frees caller memory.  s4_box arrays and the 3x3 matrix A are
+ * host memory, read during the call.  A context owns host-side tuning and
+ * graph caches only.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every call
+ * is asynchronous and ordered on that stream, except that an s4_rk4 call on
+ * more than one box in S4_BATCHED or S4_GRAPH mode copies its box table into
+ * the caller's workspace and synchronises `stream` once before launching.
+ *
+ * Errors.  Each call returns S4_OK (0) or a negative code; the message of the
+ * last failure on the calling thread is in s4_last_error().  Arguments are
+ * validated on the host before anything is launched, so a failed call has
+ * not touched device memory.  Device faults surface as S4_EDEVICE on a later
+ * call.  No C++ exception crosses this ABI.
+ * ---------------------------------------------------------------------------
+ */
+#ifndef STEN4_H
+#define STEN4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define S4_OK 0
+#define S4_EINVAL (-1)  /* null pointer, nbox <= 0, n < 1, dx <= 0, dt <= 0, nsteps < 0, bad op/mode */
+#define S4_EGHOST (-2)  /* ghost width < 2 (the stencil radius), or periodic fill with n < g */
+#define S4_ELAYOUT (-3) /* stride[0] != 1, strides too small, pointer not 8-byte aligned */
+#define S4_EALIAS (-4)  /* an output overlaps an input that is read by a stencil */
+#define S4_EDEVICE (-5) /* HIP runtime error (message in s4_last_error) */
+#define S4_ENOMEM (-6)  /* workspace too small */
+#define S4_ENOTSUP (-7) /* unsupported combination */
+
+/* RK4 execution modes */
+#define S4_PERBOX 0  /* per box and stage: one stage-kernel launch over that box's tiles */
+#define S4_BATCHED 1 /* per stage: one persistent stage kernel over a (box, tile) queue of all boxes */
+#define S4_GRAPH 2   /* S4_BATCHED with one RK4 step captured in a hipGraph, replayed nsteps times */
+
+/* operation ids (workspace sizing, tuning, tile choice) */
+#define S4_OP_FILL 1
+#define S4_OP_WAVE_RHS 2
+#define S4_OP_RK4 3
+#define S4_OP_DERIV_MIXED 4
+#define S4_OP_ADJOINT_RHS 5
+#define S4_OP_ADJOINT_STEP 6
+
+typedef struct s4_ctx s4_ctx;
+
+/* One box: a bbox of one refinement level with its ghost zones (Sec. II). */
+typedef struct {
+    int32_t n[3];      /* interior points along x, y, z (>= 1) */
+    int32_t ghost;     /* ghost width g on every face (>= 2) */
+    int64_t stride[3]; /* element strides along x, y, z; stride[0] == 1 */
+    double dx[3];      /* grid spacing along x, y, z (> 0) */
+    int32_t level;     /* refinement level (informational only) */
+    int32_t reserved;  /* set to 0 */
+} s4_box;
+
+/* Create a context bound to HIP device `device`.  Reads the device's
+ * properties (CU count, XCD count, name), which seed the default tile
+ * choice.  The environment variable S4_TUNE_CACHE names a JSON file of tuned
+ * choices that is read here and rewritten by s4_tune. */
+int s4_create(int device, s4_ctx **out);
+
+/* Free the context's host caches and captured graphs.  NULL is ignored. */
+void s4_destroy(s4_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *s4_last_error(void);
+
+/* Validate box descriptors for `op` on the host; no device call is made.
+ * Returns S4_OK or the code the corresponding entry point would return. */
+int s4_check_boxes(const s4_box *b, int nbox, int op);
+
+/* Bytes of workspace that `op` (S4_OP_RK4 or S4_OP_ADJOINT_STEP) in `mode`
+ * needs for these boxes; 0 for operations that need none. */
+int s4_workspace_size(const s4_box *b, int nbox, int op, int mode, size_t *bytes);
+
+/* Periodic ghost fill (each box is its own periodic neighbour).  For every
+ * ghost point (i,j,k) of box b, f = f(i mod n0, j mod n1, k mod n2): the
+ * result of copying faces along x, then y (over the full x extent), then z
+ * (over the full x and y extents), so edges and corners are filled.  The
+ * paper fills ghost zones by communication between the boxes of a level
+ * (Sec. II); one self-periodic box is the degenerate case.  f[i] is the
+ * field of box i; requires n >= g on every axis (S4_EGHOST otherwise). */
+int s4_fill_ghosts_periodic(s4_ctx *ctx, const s4_box *b, int nbox, double *const *f, void *stream);
+
+/* Wave-equation right-hand side in first-order form, y = (u, rho):
+ *   u_t = rho (returned as an alias: nothing is written),
+ *   rho_t = c^2 (L u),  L = D2_x + D2_y + D2_z,
+ *   D2 f_i = (-f_{i-2} + 16 f_{i-1} - 30 f_i + 16 f_{i+1} - f_{i+2}) / (12 h^2).
+ * u's ghosts must be filled (they are read, never written).  c2 == NULL, or
+ * c2[i] == NULL, means c = 1 for that box; c2 is read at interior points only
+ * and uses the box layout.  rho_t[i] is written at interior points only and
+ * must not overlap u[i] (S4_EALIAS).  The stencil follows the paper's loop
+ * kernels over a box with ghost zones (Sec. III-A, IV-C4). */
+int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u,
+                const double *const *c2, double *const *rho_t, void *stream);
+
+/* Multi-field derivative kernel on one box, for each field f = g[k]:
+ *   out[k] = sum_a D2_a f + sum_{a<b} D_ab f + sum_{a,b} A[3a+b] (D1_a f)(D1_b f),
+ *   D1 f_i = (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 h),
+ *   D_ab f = sum_{p,q=-2..2} w_p w_q f(x + p e_a + q e_b) / (144 h_a h_b),
+ *   w = (1, -8, 0, 8, -1)  (the tensor product of two D1 stencils).
+ * Axes a, b in {x, y, z} = {0, 1, 2}; A is host memory, row major, used as
+ * given.  Ghosts of every g[k] must be filled including edges (the mixed
+ * terms read them).  out[k] is written at interior points only and must not
+ * overlap any g[j]. */
+int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const *g,
+                   const double A[9], double *const *out, void *stream);
+
+/* Advance the wave equation on every box by nsteps classical RK4 steps:
+ *   k1 = F(y_n), k2 = F(y_n + dt/2 k1), k3 = F(y_n + dt/2 k2), k4 = F(y_n + dt k3),
+ *   y_{n+1} = y_n + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+ * with F the RHS above and a periodic ghost fill of the stage u before every
+ * F.  The box is its own periodic neighbour: the stage kernels read stencil
+ * neighbours at wrapped indices, which equals a periodic ghost fill before
+ * every F without the fill's launches.  u[i], rho[i] are updated in place at
+ * interior points; their ghosts are neither read nor written.
+ * c2 as in s4_wave_rhs.  `workspace` is device memory of at least
+ * s4_workspace_size(b, nbox, S4_OP_RK4, mode) bytes, 256-byte aligned, owned
+ * by the caller and not used by anything else while the call's work runs.
+ * mode: S4_PERBOX, S4_BATCHED or S4_GRAPH.  S4_GRAPH caches one captured
+ * step per (boxes, pointers, dt, workspace) in the context; the cache entry
+ * is invalid once any of those buffers is freed (s4_destroy drops it). */
+int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho,
+           const double *const *c2, double dt, int nsteps, int mode, void *workspace,
+           size_t ws_bytes, void *stream);
+
+/* Adjoint (transpose) of the wave RHS as a linear map of interior values,
+ * for periodic boxes:
+ *   F^T(lu, lrho) = (L_p(c^2 lrho), lu),
+ * where L_p is "periodic ghost fill, then L", a symmetric operator.  out_u
+ * receives L_p(c^2 lrho): the kernel forms c^2*lrho at each interior point and
+ * reads lrho (and c2) at periodically wrapped indices, so lrho's ghosts are
+ * not read.  out_rho receives a copy of lu.  Interior points only. */
+int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *lu,
+                        const double *const *lrho, const double *const *c2,
+                        double *const *out_u, double *const *out_rho, void *stream);
+
+/* One backward RK4 step on one periodic box (reverse-mode differentiation
+ * of s4_rk4's step):
+ *   kb4 = dt/6 ybar;              yb4 = F^T kb4
+ *   kb3 = dt/3 ybar + dt   yb4;   yb3 = F^T kb3
+ *   kb2 = dt/3 ybar + dt/2 yb3;   yb2 = F^T kb2
+ *   kb1 = dt/6 ybar + dt/2 yb2;   yb1 = F^T kb1
+ *   ybar_n = ybar + yb1 + yb2 + yb3 + yb4
+ *   c2_bar += sum_s (kb_s)_rho * (L_p u_s)
+ * u_n, rho_n: the forward state at the start of the step (the stage states
+ * u_2..u_4 are recomputed from it with periodic addressing; ghosts of u_n
+ * are not read and u_n, rho_n are not modified).  lam_u, lam_rho: on entry
+ * ybar = dJ/dy_{n+1}, on return dJ/dy_n (interior).  c2_bar, if not NULL,
+ * is accumulated into at interior points; c2 == NULL means c = 1.
+ * Workspace as for s4_rk4 with S4_OP_ADJOINT_STEP. */
+int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
+                        const double *c2, double dt, double *lam_u, double *lam_rho,
+                        double *c2_bar, void *workspace, size_t ws_bytes, void *stream);
+
+/* Time the candidate tile shapes and kernel variants of `op` on these boxes
+ * (median of hipEvent timings after warm-up, ties to the lowest candidate
+ * index) and keep the fastest for this "loop setup": the op, box sizes,
+ * ghost width, strides and alignment, and device (the key the paper's
+ * LoopControl tunes per loop setup, Sec. III-B).  Scratch buffers are
+ * taken from `scratch` (device memory of at least s4_tune_scratch_size
+ * bytes); the caller's data are not touched.  flags: 0 = quick sweep,
+ * 1 = full sweep.  Persists to S4_TUNE_CACHE when set. */
+int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scratch,
+            size_t scratch_bytes, void *stream);
+
+/* Scratch bytes s4_tune needs for these boxes. */
+int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
+
+/* The tile choice the library would use for `op` on box b (or on the set):
+ * out[0] variant id, out[1] tile x, out[2] tile y, out[3] z chunk,
+ * out[4] threads per workgroup, out[5] 1 if it came from tuning,
+ * out[6] candidate index, out[7] number of candidates. */
+int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
+
+/* Force a candidate (index into the op's candidate list) for this loop
+ * setup, or -1 to drop the forced choice.  For tests that compare
+ * candidates bit for bit, and for benchmark sweeps. */
+int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate);
+
+/* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned):
+ * the streaming-copy probe that calibrates achievable HBM bandwidth and the
+ * byte counters against a kernel of known traffic. */
+int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEN4_H */

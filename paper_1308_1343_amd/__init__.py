@@ -1,0 +1,304 @@
+"""Python binding of libsten4 (include/sten4.h): FP64 4th-order stencils, RK4
+and its adjoint over the boxes of an AMR level, as HIP kernels for gfx950.
+
+The functions named s4_* mirror the C ABI one to one and only marshal
+arguments (torch tensors become device pointers, the current torch stream
+becomes the hipStream_t).  Every arithmetic step runs in libsten4's kernels;
+there is no fallback: importing this package fails loudly when the library
+is not built.
+
+A field of a box is a 3-D torch view (z, y, x) of float64 device memory
+whose [0, 0, 0] element is the ghost corner (-g, -g, -g); `box_of` derives
+the s4_box descriptor from such a view and `alloc_field` makes one with the
+rows padded so that every interior row starts on a 128-byte boundary.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first: libsten4 then binds to the HIP runtime torch already loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsten4.so")
+
+S4_OK, S4_EINVAL, S4_EGHOST, S4_ELAYOUT, S4_EALIAS, S4_EDEVICE, S4_ENOMEM, S4_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+S4_PERBOX, S4_BATCHED, S4_GRAPH = 0, 1, 2
+S4_OP_FILL, S4_OP_WAVE_RHS, S4_OP_RK4, S4_OP_DERIV_MIXED, S4_OP_ADJOINT_RHS, S4_OP_ADJOINT_STEP = 1, 2, 3, 4, 5, 6
+MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
+
+# the entry points include/sten4.h declares
+EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
+           "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
+           "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
+           "s4_copy")
+
+
+class S4Box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ghost", ctypes.c_int32), ("stride", ctypes.c_int64 * 3),
+                ("dx", ctypes.c_double * 3), ("level", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def __repr__(self):
+        return (f"S4Box(n={tuple(self.n)}, ghost={self.ghost}, stride={tuple(self.stride)}, "
+                f"dx={tuple(self.dx)}, level={self.level})")
+
+
+class Sten4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sten4 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1308_1343_amd/build.py` "
+                          "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    BP = ctypes.POINTER(S4Box)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.s4_create.argtypes = [i, ctypes.POINTER(vp)]
+    L.s4_destroy.argtypes = [vp]
+    L.s4_destroy.restype = None
+    L.s4_last_error.restype = ctypes.c_char_p
+    L.s4_check_boxes.argtypes = [BP, i, i]
+    L.s4_workspace_size.argtypes = [BP, i, i, i, ctypes.POINTER(sz)]
+    L.s4_tune_scratch_size.argtypes = [BP, i, i, ctypes.POINTER(sz)]
+    L.s4_fill_ghosts_periodic.argtypes = [vp, BP, i, PP, vp]
+    L.s4_wave_rhs.argtypes = [vp, BP, i, PP, PP, PP, vp]
+    L.s4_deriv_mixed.argtypes = [vp, BP, i, PP, ctypes.POINTER(d), PP, vp]
+    L.s4_rk4.argtypes = [vp, BP, i, PP, PP, PP, d, i, i, vp, sz, vp]
+    L.s4_wave_adjoint_rhs.argtypes = [vp, BP, i, PP, PP, PP, PP, PP, vp]
+    L.s4_rk4_adjoint_step.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
+    L.s4_tune.argtypes = [vp, i, BP, i, i, vp, sz, vp]
+    L.s4_get_choice.argtypes = [vp, i, BP, i, ctypes.POINTER(i)]
+    L.s4_set_choice.argtypes = [vp, i, BP, i, i]
+    L.s4_copy.argtypes = [vp, vp, vp, sz, vp]
+    for name in EXPORTS:
+        if name not in ("s4_destroy", "s4_last_error"):
+            getattr(L, name).restype = i
+    _lib = L
+    return L
+
+
+def s4_last_error() -> str:
+    return lib().s4_last_error().decode()
+
+
+def _check(rc):
+    if rc != S4_OK:
+        raise Sten4Error(rc, s4_last_error())
+    return rc
+
+
+# --------------------------------------------------------------------------- layout helpers
+
+def make_box(n, ghost, stride, dx, level=0) -> S4Box:
+    b = S4Box()
+    b.n[:] = [int(v) for v in n]
+    b.ghost = int(ghost)
+    b.stride[:] = [int(v) for v in stride]
+    dx = (dx, dx, dx) if isinstance(dx, (int, float)) else dx
+    b.dx[:] = [float(v) for v in dx]
+    b.level = int(level)
+    b.reserved = 0
+    return b
+
+
+def box_of(t: torch.Tensor, ghost: int, dx, level: int = 0) -> S4Box:
+    """Descriptor of a (z, y, x) view whose [0,0,0] element is the ghost corner."""
+    if t.dim() != 3:
+        raise ValueError("a box field is a 3-D (z, y, x) view")
+    nz, ny, nx = (s - 2 * ghost for s in t.shape)
+    sz, sy, sx = t.stride()
+    return make_box((nx, ny, nz), ghost, (sx, sy, sz), dx, level)
+
+
+def alloc_field(n, ghost, device="cuda", pad=True, fill=None) -> torch.Tensor:
+    """Ghosted (z, y, x) float64 view of fresh device memory.  With pad=True the
+    row stride is a multiple of 16 elements and the buffer is offset so that
+    (i=0, j, k) starts a 128-byte line for every row (the aligned, padded
+    layout of the paper's LoopControl, Sec. III-A)."""
+    nx, ny, nz = (int(v) for v in n)
+    g = int(ghost)
+    sy = nx + 2 * g
+    off = 0
+    if pad:
+        sy = (sy + 15) // 16 * 16
+        off = (16 - g % 16) % 16
+    sz = sy * (ny + 2 * g)
+    buf = torch.empty(off + sz * (nz + 2 * g), dtype=torch.float64, device=device)
+    if fill is not None:
+        buf.fill_(fill)
+    return buf[off:].as_strided((nz + 2 * g, ny + 2 * g, nx + 2 * g), (sz, sy, 1))
+
+
+def interior(t: torch.Tensor, ghost: int) -> torch.Tensor:
+    g = ghost
+    return t[g:t.shape[0] - g, g:t.shape[1] - g, g:t.shape[2] - g]
+
+
+def _boxes(boxes):
+    if isinstance(boxes, S4Box):
+        boxes = [boxes]
+    arr = (S4Box * len(boxes))(*boxes)
+    return arr, len(boxes)
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[0 if t is None else _ptr(t) for t in ts])
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if t.dtype != torch.float64 and t.dtype != torch.uint8:
+        raise TypeError("fields must be float64")
+    if not t.is_cuda:
+        raise TypeError("fields must be device tensors")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# --------------------------------------------------------------------------- context
+
+class Context:
+    """An s4_ctx bound to one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().s4_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().s4_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def s4_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def s4_destroy(ctx: Context):
+    ctx.close()
+
+
+# --------------------------------------------------------------------------- entry points
+
+def s4_check_boxes(boxes, op) -> int:
+    arr, n = _boxes(boxes)
+    return lib().s4_check_boxes(arr, n, op)
+
+
+def s4_workspace_size(boxes, op, mode=S4_GRAPH) -> int:
+    arr, n = _boxes(boxes)
+    out = ctypes.c_size_t()
+    _check(lib().s4_workspace_size(arr, n, op, mode, ctypes.byref(out)))
+    return out.value
+
+
+def s4_tune_scratch_size(boxes, op) -> int:
+    arr, n = _boxes(boxes)
+    out = ctypes.c_size_t()
+    _check(lib().s4_tune_scratch_size(arr, n, op, ctypes.byref(out)))
+    return out.value
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """A 256-byte aligned device buffer (torch's allocator aligns blocks to 512 bytes)."""
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def s4_fill_ghosts_periodic(ctx, boxes, f, stream=None):
+    arr, n = _boxes(boxes)
+    _check(lib().s4_fill_ghosts_periodic(ctx.handle, arr, n, _ptrs(f), _stream(stream)))
+
+
+def s4_wave_rhs(ctx, boxes, u, c2, rho_t, stream=None):
+    arr, n = _boxes(boxes)
+    _check(lib().s4_wave_rhs(ctx.handle, arr, n, _ptrs(u), None if c2 is None else _ptrs(c2),
+                             _ptrs(rho_t), _stream(stream)))
+
+
+def s4_deriv_mixed(ctx, box, g, A, out, stream=None):
+    arr, _ = _boxes(box)
+    A9 = (ctypes.c_double * 9)(*[float(v) for v in torch.as_tensor(A, dtype=torch.float64).reshape(9).tolist()])
+    _check(lib().s4_deriv_mixed(ctx.handle, arr, len(g), _ptrs(g), A9, _ptrs(out), _stream(stream)))
+
+
+def s4_rk4(ctx, boxes, u, rho, c2, dt, nsteps, mode=S4_GRAPH, ws=None, stream=None):
+    arr, n = _boxes(boxes)
+    mode = MODES.get(mode, mode)
+    if ws is None:
+        ws = workspace(s4_workspace_size(boxes, S4_OP_RK4, mode), u[0].device)
+    _check(lib().s4_rk4(ctx.handle, arr, n, _ptrs(u), _ptrs(rho), None if c2 is None else _ptrs(c2),
+                        float(dt), int(nsteps), int(mode), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def s4_wave_adjoint_rhs(ctx, boxes, lu, lrho, c2, out_u, out_rho, stream=None):
+    arr, n = _boxes(boxes)
+    _check(lib().s4_wave_adjoint_rhs(ctx.handle, arr, n, _ptrs(lu), _ptrs(lrho),
+                                     None if c2 is None else _ptrs(c2), _ptrs(out_u), _ptrs(out_rho),
+                                     _stream(stream)))
+
+
+def s4_rk4_adjoint_step(ctx, box, u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, ws=None, stream=None):
+    arr, _ = _boxes(box)
+    if ws is None:
+        ws = workspace(s4_workspace_size(box, S4_OP_ADJOINT_STEP), u_n.device)
+    _check(lib().s4_rk4_adjoint_step(ctx.handle, arr, _ptr(u_n), _ptr(rho_n), _ptr(c2), float(dt), _ptr(lam_u),
+                                     _ptr(lam_rho), _ptr(c2_bar), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def s4_tune(ctx, op, boxes, flags=0, scratch=None, stream=None):
+    arr, n = _boxes(boxes)
+    if scratch is None:
+        scratch = workspace(s4_tune_scratch_size(boxes, op))
+    _check(lib().s4_tune(ctx.handle, op, arr, n, int(flags), _ptr(scratch), scratch.numel(), _stream(stream)))
+
+
+def s4_get_choice(ctx, op, boxes) -> dict:
+    arr, n = _boxes(boxes)
+    out = (ctypes.c_int * 8)()
+    _check(lib().s4_get_choice(ctx.handle, op, arr, n, out))
+    keys = ("kernel_op", "tile_x", "tile_y", "z_chunk", "threads", "tuned", "candidate", "ncandidates")
+    return dict(zip(keys, list(out)))
+
+
+def s4_set_choice(ctx, op, boxes, candidate):
+    arr, n = _boxes(boxes)
+    _check(lib().s4_set_choice(ctx.handle, op, arr, n, int(candidate)))
+
+
+def s4_copy(ctx, dst, src, nbytes=None, stream=None):
+    nb = dst.numel() * dst.element_size() if nbytes is None else int(nbytes)
+    _check(lib().s4_copy(ctx.handle, _ptr(dst), _ptr(src), nb, _stream(stream)))
+
+
+lib()  # fail at import when the HIP library is missing: there is no other implementation

@@ -1,0 +1,1096 @@
+// s4_api.cpp -- the C ABI of libsten4 (declared in include/sten4.h): argument
+// validation, workspace layout, tile choice and tuning, box tables for the
+// persistent batched launch, and the hipGraph cache of one RK4 step.
+//
+// Tile choice follows the paper's LoopControl (Sec. III-B): every "loop
+// setup" (operation, box sizes, ghost width, strides, device) gets initial
+// execution parameters from a heuristic fed by the device's properties, and
+// measured timings replace them with the fastest candidate.  Here the search
+// is an explicit sweep (s4_tune) rather than on-line hill climbing, and its
+// results persist in a JSON file (the paper's "save and restore execution
+// parameter settings", Sec. III-C).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "s4_internal.h"
+#include "s4_launch.h"
+#include "sten4.h"
+
+using namespace s4;
+
+// ---------------------------------------------------------------------------
+// errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char *where)
+{
+    return fail(S4_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define S4_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return hip_fail(e_, #call);                                                                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// tile candidates (the tuner's search space) and choices
+
+struct Cand {
+    int tx, nw, tz; // tile x extent, wavefronts per workgroup, z chunk (0 = whole box)
+};
+
+static const std::vector<Cand> &cands()
+{
+    static const std::vector<Cand> v = [] {
+        std::vector<Cand> c;
+        for (int tx : {64, 32, 16})
+            for (int nw : {8, 4})
+                for (int tz : {0, 64, 32, 16, 8})
+                    c.push_back({tx, nw, tz});
+        return c;
+    }();
+    return v;
+}
+
+static int cand_index(int tx, int nw, int tz)
+{
+    const auto &c = cands();
+    for (size_t i = 0; i < c.size(); ++i)
+        if (c[i].tx == tx && c[i].nw == nw && c[i].tz == tz)
+            return (int)i;
+    return 0;
+}
+
+static int kernel_op(int op)
+{
+    switch (op) {
+    case S4_OP_WAVE_RHS: return OP_RHS;
+    case S4_OP_RK4: return OP_STAGE;
+    case S4_OP_ADJOINT_RHS: return OP_ADJRHS;
+    case S4_OP_ADJOINT_STEP: return OP_ADJSTAGE;
+    default: return -1;
+    }
+}
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct s4_ctx {
+    int device = 0;
+    int ncu = 256;
+    int nxcd = 8;
+    std::string name;
+    std::string cache_path;
+    hipStream_t cap = nullptr; // private stream used only to capture graphs
+    std::map<std::string, int> tuned;
+    std::map<std::string, int> forced;
+    std::map<std::string, GraphEntry> graphs;
+    std::mutex mu;
+};
+
+static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbox)
+{
+    std::ostringstream o;
+    o << "op" << op << "|" << ctx->name << "|" << nbox;
+    for (int i = 0; i < nbox; ++i)
+        o << "|" << b[i].n[0] << "," << b[i].n[1] << "," << b[i].n[2] << ",g" << b[i].ghost << ",s"
+          << b[i].stride[1] << "," << b[i].stride[2];
+    return o.str();
+}
+
+static int tile_ty(const Cand &c)
+{
+    return c.nw * 64 / c.tx;
+}
+
+static int64_t items_of(const s4_box &b, const Cand &c)
+{
+    const int ty = tile_ty(c);
+    const int tz = c.tz > 0 ? std::min(c.tz, b.n[2]) : b.n[2];
+    return (int64_t)((b.n[0] + c.tx - 1) / c.tx) * ((b.n[1] + ty - 1) / ty) * ((b.n[2] + tz - 1) / tz);
+}
+
+// LoopControl-style initial parameters: the widest x tile the boxes fill,
+// 8 wavefronts, and the longest z chunk that still gives every CU about
+// four workgroups.
+static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
+{
+    int maxnx = 0;
+    for (int i = 0; i < nbox; ++i)
+        maxnx = std::max(maxnx, b[i].n[0]);
+    const int tx = maxnx >= 48 ? 64 : maxnx >= 24 ? 32 : 16;
+    const int nw = 8;
+    for (int tz : {0, 64, 32, 16}) {
+        int64_t items = 0;
+        for (int i = 0; i < nbox; ++i)
+            items += items_of(b[i], {tx, nw, tz});
+        if (items >= 4 * (int64_t)ctx->ncu)
+            return cand_index(tx, nw, tz);
+    }
+    return cand_index(tx, nw, 8);
+}
+
+struct Choice {
+    int cand;
+    int tuned;
+};
+
+static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox)
+{
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const std::string key = setup_key(ctx, op, b, nbox);
+    auto f = ctx->forced.find(key);
+    if (f != ctx->forced.end())
+        return {f->second, 0};
+    auto t = ctx->tuned.find(key);
+    if (t != ctx->tuned.end())
+        return {t->second, 1};
+    return {heuristic(ctx, b, nbox), 0};
+}
+
+// ---------------------------------------------------------------------------
+// validation (host only, before anything is launched)
+
+static int64_t box_elems(const s4_box &b)
+{
+    return b.stride[2] * ((int64_t)b.n[2] + 2 * b.ghost);
+}
+
+static size_t round256(size_t x)
+{
+    return (x + 255) & ~(size_t)255;
+}
+
+static size_t field_bytes(const s4_box &b)
+{
+    return round256((size_t)box_elems(b) * sizeof(double));
+}
+
+static int check_box(const s4_box &b, int i, int op)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (b.n[a] < 1)
+            return fail(S4_EINVAL, "box %d: n[%d] = %d < 1", i, a, b.n[a]);
+        if (b.n[a] > (1 << 24))
+            return fail(S4_EINVAL, "box %d: n[%d] = %d too large", i, a, b.n[a]);
+        if (!(std::isfinite(b.dx[a]) && b.dx[a] > 0.0))
+            return fail(S4_EINVAL, "box %d: dx[%d] must be finite and > 0", i, a);
+    }
+    if (b.ghost < 2)
+        return fail(S4_EGHOST, "box %d: ghost width %d < 2 (stencil radius)", i, b.ghost);
+    if (b.ghost > 64)
+        return fail(S4_EGHOST, "box %d: ghost width %d > 64", i, b.ghost);
+    if (b.stride[0] != 1)
+        return fail(S4_ELAYOUT, "box %d: stride[0] must be 1", i);
+    if (b.stride[1] < (int64_t)b.n[0] + 2 * b.ghost)
+        return fail(S4_ELAYOUT, "box %d: stride[1] %lld < n[0]+2g", i, (long long)b.stride[1]);
+    if (b.stride[2] / b.stride[1] < (int64_t)b.n[1] + 2 * b.ghost)
+        return fail(S4_ELAYOUT, "box %d: stride[2] %lld < stride[1]*(n[1]+2g)", i, (long long)b.stride[2]);
+    if (b.stride[2] > ((int64_t)1 << 40) || box_elems(b) > ((int64_t)1 << 42))
+        return fail(S4_ELAYOUT, "box %d: array too large", i);
+    if (op == S4_OP_FILL)
+        for (int a = 0; a < 3; ++a)
+            if (b.n[a] < b.ghost)
+                return fail(S4_EGHOST, "box %d: periodic fill needs n[%d] >= ghost", i, a);
+    for (const Cand &c : cands())
+        if (items_of(b, c) > 0x3fffffff)
+            return fail(S4_EINVAL, "box %d: too many tiles", i);
+    return S4_OK;
+}
+
+static int check_boxes(const s4_box *b, int nbox, int op)
+{
+    if (!b)
+        return fail(S4_EINVAL, "box array is NULL");
+    if (nbox <= 0)
+        return fail(S4_EINVAL, "nbox = %d <= 0", nbox);
+    if (nbox > (1 << 20))
+        return fail(S4_EINVAL, "nbox = %d too large", nbox);
+    for (int i = 0; i < nbox; ++i) {
+        int r = check_box(b[i], i, op);
+        if (r)
+            return r;
+    }
+    return S4_OK;
+}
+
+static int check_ptr(const void *p, const char *what, int i, bool may_be_null = false)
+{
+    if (!p)
+        return may_be_null ? S4_OK : fail(S4_EINVAL, "%s[%d] is NULL", what, i);
+    if ((uintptr_t)p & 7)
+        return fail(S4_ELAYOUT, "%s[%d] is not 8-byte aligned", what, i);
+    return S4_OK;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    if (!a || !b)
+        return false;
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+struct Range {
+    const void *p;
+    size_t n;
+    const char *what;
+    int box;
+};
+
+// every pair (written, other) must be disjoint
+static int check_disjoint(const std::vector<Range> &written, const std::vector<Range> &all)
+{
+    for (const Range &w : written)
+        for (const Range &o : all) {
+            if (&w == &o || (w.p == o.p && w.what == o.what && w.box == o.box))
+                continue;
+            if (overlap(w.p, w.n, o.p, o.n))
+                return fail(S4_EALIAS, "%s[%d] overlaps %s[%d]", w.what, w.box, o.what, o.box);
+        }
+    return S4_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device boxes
+
+static DevBox devbox(const s4_box &b, const Cand &c)
+{
+    DevBox D;
+    memset(&D, 0, sizeof D);
+    for (int a = 0; a < 3; ++a)
+        D.n[a] = b.n[a];
+    D.g = b.ghost;
+    D.sy = b.stride[1];
+    D.sz = b.stride[2];
+    D.cx = 1.0 / (12.0 * b.dx[0] * b.dx[0]);
+    D.cy = 1.0 / (12.0 * b.dx[1] * b.dx[1]);
+    D.cz = 1.0 / (12.0 * b.dx[2] * b.dx[2]);
+    D.c0 = -30.0 * (D.cx + D.cy + D.cz);
+    const int ty = tile_ty(c);
+    D.tz = c.tz > 0 ? std::min(c.tz, b.n[2]) : b.n[2];
+    D.tiles[0] = (b.n[0] + c.tx - 1) / c.tx;
+    D.tiles[1] = (b.n[1] + ty - 1) / ty;
+    D.tiles[2] = (b.n[2] + D.tz - 1) / D.tz;
+    return D;
+}
+
+static int64_t dev_items(const DevBox &D)
+{
+    return (int64_t)D.tiles[0] * D.tiles[1] * D.tiles[2];
+}
+
+static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const StageCoef &K, hipStream_t s)
+{
+    const int64_t items = dev_items(D);
+    hipError_t e = launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "stencil launch");
+    return S4_OK;
+}
+
+static int persistent_grid(s4_ctx *ctx, int op, const Cand &c, int64_t nitems)
+{
+    int per = max_blocks_per_cu(op, c.tx, c.nw);
+    if (per <= 0)
+        per = 2;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
+}
+
+// Copy a box table (and its zeroed item counters) into the caller's
+// workspace.  Done on every call that needs it: the workspace belongs to the
+// caller between calls, so nothing found there is trusted.  The stream is
+// synchronised so the host staging bytes may be released.
+static int upload_table(void *dst, const std::vector<char> &bytes, hipStream_t s)
+{
+    S4_HIP(hipMemcpyAsync(dst, bytes.data(), bytes.size(), hipMemcpyHostToDevice, s));
+    S4_HIP(hipStreamSynchronize(s));
+    return S4_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+
+static const int RK4_FIELDS = 6;   // Ua Ub Ra Rb AccU AccR
+static const int ADJ_FIELDS = 13;  // Ua Ub Ra Rb LU1..4 KBU KBa KBb AccU AccR
+static const int TUNE_FIELDS = 14; // enough distinct buffers for any op
+
+static size_t rk4_fields_bytes(const s4_box *b, int nbox)
+{
+    size_t t = 0;
+    for (int i = 0; i < nbox; ++i)
+        t += RK4_FIELDS * field_bytes(b[i]);
+    return t;
+}
+
+static size_t rk4_table_bytes(int nbox)
+{
+    return round256(4 * (size_t)nbox * sizeof(DevBox)) + 256; // 4 stage tables + item counters
+}
+
+// ---------------------------------------------------------------------------
+// API
+
+extern "C" {
+
+const char *s4_last_error(void)
+{
+    return g_err.c_str();
+}
+
+int s4_check_boxes(const s4_box *b, int nbox, int op)
+{
+    if (op < S4_OP_FILL || op > S4_OP_ADJOINT_STEP)
+        return fail(S4_EINVAL, "unknown op %d", op);
+    int r = check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    if (op == S4_OP_ADJOINT_STEP && nbox != 1)
+        return fail(S4_EINVAL, "the adjoint step takes one box");
+    return S4_OK;
+}
+
+int s4_workspace_size(const s4_box *b, int nbox, int op, int mode, size_t *bytes)
+{
+    if (!bytes)
+        return fail(S4_EINVAL, "bytes is NULL");
+    int r = s4_check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    if (op == S4_OP_RK4) {
+        if (mode < S4_PERBOX || mode > S4_GRAPH)
+            return fail(S4_EINVAL, "unknown mode %d", mode);
+        *bytes = rk4_fields_bytes(b, nbox) + rk4_table_bytes(nbox);
+    } else if (op == S4_OP_ADJOINT_STEP) {
+        *bytes = ADJ_FIELDS * field_bytes(b[0]);
+    } else {
+        *bytes = 0;
+    }
+    return S4_OK;
+}
+
+int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes)
+{
+    if (!bytes)
+        return fail(S4_EINVAL, "bytes is NULL");
+    int r = s4_check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    size_t t = 0;
+    for (int i = 0; i < nbox; ++i)
+        t += TUNE_FIELDS * field_bytes(b[i]);
+    *bytes = t + rk4_table_bytes(nbox);
+    return S4_OK;
+}
+
+static void load_cache(s4_ctx *ctx);
+
+int s4_create(int device, s4_ctx **out)
+{
+    if (!out)
+        return fail(S4_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    S4_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(S4_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    S4_HIP(hipSetDevice(device));
+    hipDeviceProp_t p;
+    S4_HIP(hipGetDeviceProperties(&p, device));
+    s4_ctx *c = new s4_ctx;
+    c->device = device;
+    c->ncu = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    c->name = p.gcnArchName;
+    {
+        size_t cut = c->name.find(':');
+        if (cut != std::string::npos)
+            c->name = c->name.substr(0, cut);
+    }
+    int nx = 0;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, device) == hipSuccess && nx > 0)
+        c->nxcd = nx;
+    else
+        c->nxcd = (c->name.rfind("gfx94", 0) == 0 || c->name.rfind("gfx95", 0) == 0) ? 8 : 1;
+    (void)hipGetLastError();
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(S4_EDEVICE, "cannot create the capture stream");
+    }
+    const char *cp = getenv("S4_TUNE_CACHE");
+    if (cp && *cp) {
+        c->cache_path = cp;
+        load_cache(c);
+    }
+    *out = c;
+    return S4_OK;
+}
+
+void s4_destroy(s4_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec)
+            (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph)
+            (void)hipGraphDestroy(kv.second.graph);
+    }
+    if (ctx->cap)
+        (void)hipStreamDestroy(ctx->cap);
+    delete ctx;
+}
+
+int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
+{
+    if (!ctx || !out)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = s4_check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    const Choice ch = choose(ctx, op, b, nbox);
+    const Cand &c = cands()[ch.cand];
+    out[0] = kernel_op(op);
+    out[1] = c.tx;
+    out[2] = tile_ty(c);
+    out[3] = c.tz;
+    out[4] = c.nw * 64;
+    out[5] = ch.tuned;
+    out[6] = ch.cand;
+    out[7] = (int)cands().size();
+    return S4_OK;
+}
+
+int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    int r = s4_check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    if (candidate >= (int)cands().size() || candidate < -1)
+        return fail(S4_EINVAL, "candidate %d out of range", candidate);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const std::string key = setup_key(ctx, op, b, nbox);
+    if (candidate < 0)
+        ctx->forced.erase(key);
+    else
+        ctx->forced[key] = candidate;
+    return S4_OK;
+}
+
+int s4_fill_ghosts_periodic(s4_ctx *ctx, const s4_box *b, int nbox, double *const *f, void *stream)
+{
+    if (!ctx || !f)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, nbox, S4_OP_FILL);
+    if (r)
+        return r;
+    for (int i = 0; i < nbox; ++i)
+        if ((r = check_ptr(f[i], "f", i)))
+            return r;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < nbox; ++i) {
+        DevBox D = devbox(b[i], cands()[0]);
+        D.q[0] = f[i];
+        hipError_t e = launch_fill(D, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "ghost fill launch");
+    }
+    return S4_OK;
+}
+
+int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u, const double *const *c2,
+                double *const *rho_t, void *stream)
+{
+    if (!ctx || !u || !rho_t)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, nbox, S4_OP_WAVE_RHS);
+    if (r)
+        return r;
+    std::vector<Range> wr, all;
+    for (int i = 0; i < nbox; ++i) {
+        if ((r = check_ptr(u[i], "u", i)) || (r = check_ptr(rho_t[i], "rho_t", i)) ||
+            (r = check_ptr(c2 ? c2[i] : nullptr, "c2", i, true)))
+            return r;
+        const size_t n = (size_t)box_elems(b[i]) * 8;
+        wr.push_back({rho_t[i], n, "rho_t", i});
+        all.push_back({u[i], n, "u", i});
+        if (c2 && c2[i])
+            all.push_back({c2[i], n, "c2", i});
+    }
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+    const Cand &c = cands()[choose(ctx, S4_OP_WAVE_RHS, b, nbox).cand];
+    StageCoef K{};
+    K.scale = 1.0;
+    for (int i = 0; i < nbox; ++i) {
+        DevBox D = devbox(b[i], c);
+        D.in = u[i];
+        D.p[0] = c2 ? c2[i] : nullptr;
+        D.q[0] = rho_t[i];
+        if ((r = launch_one(ctx, OP_RHS, c, D, K, (hipStream_t)stream)))
+            return r;
+    }
+    return S4_OK;
+}
+
+int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const *g, const double A[9],
+                   double *const *out, void *stream)
+{
+    (void)ctx;
+    (void)b;
+    (void)nfield;
+    (void)g;
+    (void)A;
+    (void)out;
+    (void)stream;
+    return fail(S4_ENOTSUP, "s4_deriv_mixed: not built yet");
+}
+
+// RK4 stage tables for all boxes: stage s reads u_s (stencil) and writes the
+// next stage input; the accumulators hold y_n + sum_{r<=s} b_r k_r.
+static void rk4_tables(const s4_box *b, int nbox, double *const *u, double *const *rho,
+                       const double *const *c2, char *ws, const Cand &c, std::vector<DevBox> &tab)
+{
+    tab.assign(4 * (size_t)nbox, DevBox{});
+    size_t off = 0;
+    int item0 = 0;
+    for (int i = 0; i < nbox; ++i) {
+        const size_t fb = field_bytes(b[i]);
+        double *F[RK4_FIELDS];
+        for (int k = 0; k < RK4_FIELDS; ++k)
+            F[k] = (double *)(ws + off + k * fb);
+        off += RK4_FIELDS * fb;
+        double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3], *AU = F[4], *AR = F[5];
+        const double *in_[4] = {u[i], Ua, Ub, Ua};
+        const double *rs_[4] = {rho[i], Ra, Rb, Ra};
+        double *uo_[4] = {Ua, Ub, Ua, u[i]};
+        double *ro_[4] = {Ra, Rb, Ra, rho[i]};
+        DevBox D = devbox(b[i], c);
+        D.item0 = item0;
+        item0 += (int)dev_items(D);
+        for (int s = 0; s < 4; ++s) {
+            DevBox E = D;
+            E.in = in_[s];
+            E.p[0] = rs_[s];
+            E.p[1] = u[i];
+            E.p[2] = rho[i];
+            E.p[3] = AU;
+            E.p[4] = AR;
+            E.p[5] = c2 ? c2[i] : nullptr;
+            E.q[0] = uo_[s];
+            E.q[1] = ro_[s];
+            E.q[2] = AU;
+            E.q[3] = AR;
+            tab[(size_t)s * nbox + i] = E;
+        }
+    }
+}
+
+static StageCoef rk4_coef(int s, double dt)
+{
+    static const double A[4] = {0.5, 0.5, 1.0, 0.0};
+    static const double B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    StageCoef K{};
+    K.stage = s + 1;
+    K.a = A[s] * dt;
+    K.b = B[s] * dt;
+    K.scale = 1.0;
+    return K;
+}
+
+// launch the four stages of one RK4 step (batched: nbox > 1 and table in ws)
+static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, int nbox, bool batched,
+                    DevBox *dtab, int *counters, int64_t nitems, double dt, hipStream_t s)
+{
+    for (int st = 0; st < 4; ++st) {
+        const StageCoef K = rk4_coef(st, dt);
+        if (batched) {
+            const int grid = persistent_grid(ctx, OP_STAGE, c, nitems);
+            hipError_t e = launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox,
+                                                (int)nitems, counters + 2 * st, grid, K, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "batched stage launch");
+        } else {
+            for (int i = 0; i < nbox; ++i) {
+                int r = launch_one(ctx, OP_STAGE, c, tab[(size_t)st * nbox + i], K, s);
+                if (r)
+                    return r;
+            }
+        }
+    }
+    return S4_OK;
+}
+
+static std::string graph_key(const s4_box *b, int nbox, double *const *u, double *const *rho,
+                             const double *const *c2, double dt, const void *ws, int cand, bool batched)
+{
+    std::ostringstream o;
+    o.precision(17);
+    o << "g" << nbox << "|" << dt << "|" << ws << "|" << cand << "|" << batched;
+    for (int i = 0; i < nbox; ++i) {
+        o << "|" << (const void *)u[i] << "," << (const void *)rho[i] << "," << (const void *)(c2 ? c2[i] : nullptr);
+        o << "," << b[i].n[0] << "," << b[i].n[1] << "," << b[i].n[2] << "," << b[i].ghost << "," << b[i].stride[1]
+          << "," << b[i].stride[2] << "," << b[i].dx[0] << "," << b[i].dx[1] << "," << b[i].dx[2];
+    }
+    return o.str();
+}
+
+int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho, const double *const *c2,
+           double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !u || !rho)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, nbox, S4_OP_RK4);
+    if (r)
+        return r;
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(S4_EINVAL, "dt must be finite and > 0");
+    if (nsteps < 0)
+        return fail(S4_EINVAL, "nsteps < 0");
+    if (mode < S4_PERBOX || mode > S4_GRAPH)
+        return fail(S4_EINVAL, "unknown mode %d", mode);
+    size_t need = rk4_fields_bytes(b, nbox) + rk4_table_bytes(nbox);
+    std::vector<Range> wr, all;
+    for (int i = 0; i < nbox; ++i) {
+        if ((r = check_ptr(u[i], "u", i)) || (r = check_ptr(rho[i], "rho", i)) ||
+            (r = check_ptr(c2 ? c2[i] : nullptr, "c2", i, true)))
+            return r;
+        const size_t n = (size_t)box_elems(b[i]) * 8;
+        wr.push_back({u[i], n, "u", i});
+        wr.push_back({rho[i], n, "rho", i});
+        if (c2 && c2[i])
+            all.push_back({c2[i], n, "c2", i});
+    }
+    if (nsteps == 0)
+        return S4_OK;
+    if (!workspace)
+        return fail(S4_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255)
+        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    wr.push_back({workspace, need, "workspace", 0});
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+
+    hipStream_t s = (hipStream_t)stream;
+    const Choice ch = choose(ctx, S4_OP_RK4, b, nbox);
+    const Cand &c = cands()[ch.cand];
+    char *ws = (char *)workspace;
+    std::vector<DevBox> tab;
+    rk4_tables(b, nbox, u, rho, c2, ws, c, tab);
+    int64_t nitems = 0;
+    for (int i = 0; i < nbox; ++i)
+        nitems += dev_items(tab[i]);
+    if (nitems > 0x3fffffff)
+        return fail(S4_EINVAL, "too many work items");
+    const bool batched = nbox > 1 && mode != S4_PERBOX;
+    DevBox *dtab = (DevBox *)(ws + rk4_fields_bytes(b, nbox));
+    int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
+    if (batched) {
+        // table bytes followed by zeroed item counters (8 ints)
+        std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
+        memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+        if ((r = upload_table(dtab, bytes, s)))
+            return r;
+    }
+    if (mode != S4_GRAPH) {
+        for (int step = 0; step < nsteps; ++step)
+            if ((r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s)))
+                return r;
+        return S4_OK;
+    }
+    const std::string key = graph_key(b, nbox, u, rho, c2, dt, workspace, ch.cand, batched);
+    GraphEntry ge;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->graphs.find(key);
+        if (it != ctx->graphs.end())
+            ge = it->second;
+    }
+    if (!ge.exec) {
+        S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, ctx->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+        if (r)
+            return r;
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ge.graph = g;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->graphs.size() >= 64) { // bounded cache: drop every captured step
+            for (auto &kv : ctx->graphs) {
+                (void)hipGraphExecDestroy(kv.second.exec);
+                (void)hipGraphDestroy(kv.second.graph);
+            }
+            ctx->graphs.clear();
+        }
+        ctx->graphs[key] = ge;
+    }
+    for (int step = 0; step < nsteps; ++step)
+        S4_HIP(hipGraphLaunch(ge.exec, s));
+    return S4_OK;
+}
+
+int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *lu,
+                        const double *const *lrho, const double *const *c2, double *const *out_u,
+                        double *const *out_rho, void *stream)
+{
+    if (!ctx || !lu || !lrho || !out_u || !out_rho)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, nbox, S4_OP_ADJOINT_RHS);
+    if (r)
+        return r;
+    std::vector<Range> wr, all;
+    for (int i = 0; i < nbox; ++i) {
+        if ((r = check_ptr(lu[i], "lu", i)) || (r = check_ptr(lrho[i], "lrho", i)) ||
+            (r = check_ptr(out_u[i], "out_u", i)) || (r = check_ptr(out_rho[i], "out_rho", i)) ||
+            (r = check_ptr(c2 ? c2[i] : nullptr, "c2", i, true)))
+            return r;
+        const size_t n = (size_t)box_elems(b[i]) * 8;
+        wr.push_back({out_u[i], n, "out_u", i});
+        wr.push_back({out_rho[i], n, "out_rho", i});
+        all.push_back({lu[i], n, "lu", i});
+        all.push_back({lrho[i], n, "lrho", i});
+        if (c2 && c2[i])
+            all.push_back({c2[i], n, "c2", i});
+    }
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_RHS, b, nbox).cand];
+    StageCoef K{};
+    K.scale = 1.0;
+    for (int i = 0; i < nbox; ++i) {
+        DevBox D = devbox(b[i], c);
+        D.in = lrho[i];
+        D.inmul = c2 ? c2[i] : nullptr;
+        D.p[0] = lu[i];
+        D.q[0] = out_u[i];
+        D.q[1] = out_rho[i];
+        if ((r = launch_one(ctx, OP_ADJRHS, c, D, K, (hipStream_t)stream)))
+            return r;
+    }
+    return S4_OK;
+}
+
+int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n, const double *c2,
+                        double dt, double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    int r = check_boxes(b, 1, S4_OP_ADJOINT_STEP);
+    if (r)
+        return r;
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(S4_EINVAL, "dt must be finite and > 0");
+    if ((r = check_ptr(u_n, "u_n", 0)) || (r = check_ptr(rho_n, "rho_n", 0)) ||
+        (r = check_ptr(lam_u, "lam_u", 0)) || (r = check_ptr(lam_rho, "lam_rho", 0)) ||
+        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(c2_bar, "c2_bar", 0, true)))
+        return r;
+    const size_t fb = field_bytes(b[0]);
+    const size_t need = ADJ_FIELDS * fb;
+    if (!workspace)
+        return fail(S4_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255)
+        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    const size_t n = (size_t)box_elems(b[0]) * 8;
+    std::vector<Range> wr = {{lam_u, n, "lam_u", 0}, {lam_rho, n, "lam_rho", 0}, {workspace, need, "workspace", 0}};
+    if (c2_bar)
+        wr.push_back({c2_bar, n, "c2_bar", 0});
+    std::vector<Range> all = {{u_n, n, "u_n", 0}, {rho_n, n, "rho_n", 0}};
+    if (c2)
+        all.push_back({c2, n, "c2", 0});
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+
+    hipStream_t s = (hipStream_t)stream;
+    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_STEP, b, 1).cand];
+    char *ws = (char *)workspace;
+    double *F[ADJ_FIELDS];
+    for (int k = 0; k < ADJ_FIELDS; ++k)
+        F[k] = (double *)(ws + k * fb);
+    double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3];
+    double *LU[4] = {F[4], F[5], F[6], F[7]};
+    double *KBU = F[8], *KBa = F[9], *KBb = F[10], *ACU = F[11], *ACR = F[12];
+    const DevBox D0 = devbox(b[0], c);
+
+    // forward recompute of the stage states, storing L u_s
+    static const double Afw[4] = {0.5, 0.5, 1.0, 0.0};
+    const double *in_[4] = {u_n, Ua, Ub, Ua};
+    const double *rs_[4] = {rho_n, Ra, Rb, Ra};
+    double *uo_[4] = {Ua, Ub, Ua, nullptr};
+    double *ro_[4] = {Ra, Rb, Ra, nullptr};
+    for (int st = 0; st < 4; ++st) {
+        DevBox E = D0;
+        E.in = in_[st];
+        E.p[0] = rs_[st];
+        E.p[1] = u_n;
+        E.p[2] = rho_n;
+        E.p[5] = c2;
+        E.q[0] = uo_[st];
+        E.q[1] = ro_[st];
+        E.q[2] = LU[st];
+        StageCoef K{};
+        K.stage = st + 1;
+        K.a = Afw[st] * dt;
+        K.scale = 1.0;
+        if ((r = launch_one(ctx, OP_FWDREC, c, E, K, s)))
+            return r;
+    }
+    // reverse sweep over the stages: 4, 3, 2, 1
+    static const double Cw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double *kin[4] = {KBa, KBb, KBa, lam_rho}; // stencil input of adjoint stage s (index s-1)
+    double *kout[4] = {lam_rho, KBa, KBb, KBa};      // kb_rho written by stage s
+    for (int st = 3; st >= 0; --st) {
+        DevBox E = D0;
+        E.in = kin[st];
+        E.inmul = c2;
+        E.p[0] = KBU;
+        E.p[1] = lam_u;
+        E.p[2] = lam_rho;
+        E.p[3] = ACU;
+        E.p[4] = ACR;
+        E.p[5] = LU[st];
+        E.p[6] = c2_bar;
+        E.q[0] = st == 0 ? lam_u : KBU;
+        E.q[1] = kout[st];
+        E.q[2] = ACU;
+        E.q[3] = ACR;
+        E.q[4] = c2_bar;
+        StageCoef K{};
+        K.stage = st + 1;
+        K.scale = st == 3 ? Cw[3] * dt : 1.0;
+        if (st > 0) {
+            K.b_next = Cw[st - 1] * dt;
+            K.a_next = Afw[st - 1] * dt;
+        }
+        if ((r = launch_one(ctx, OP_ADJSTAGE, c, E, K, s)))
+            return r;
+    }
+    return S4_OK;
+}
+
+int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!ctx || !dst || !src)
+        return fail(S4_EINVAL, "NULL argument");
+    if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+        return fail(S4_ELAYOUT, "copy needs 16-byte aligned pointers and size");
+    if (overlap(dst, bytes, src, bytes))
+        return fail(S4_EALIAS, "copy source and destination overlap");
+    if (bytes == 0)
+        return S4_OK;
+    const int grid = ctx->ncu * 8;
+    hipError_t e = launch_copy(dst, src, bytes, grid, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "copy launch");
+    return S4_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+
+static void save_cache(s4_ctx *ctx);
+
+int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scratch, size_t scratch_bytes,
+            void *stream)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    size_t need = 0;
+    int r = s4_tune_scratch_size(b, nbox, op, &need);
+    if (r)
+        return r;
+    const int kop = kernel_op(op);
+    if (kop < 0)
+        return fail(S4_EINVAL, "op %d has no tunable kernel", op);
+    if (!scratch || ((uintptr_t)scratch & 255))
+        return fail(S4_ELAYOUT, "scratch must be non-NULL and 256-byte aligned");
+    if (scratch_bytes < need)
+        return fail(S4_ENOMEM, "scratch %zu bytes < %zu needed", scratch_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    S4_HIP(hipMemsetAsync(scratch, 0, need, s));
+    // distinct buffers per box: in, inmul, p[0..6], q[0..4]
+    std::vector<std::vector<double *>> F(nbox);
+    size_t off = 0;
+    for (int i = 0; i < nbox; ++i) {
+        const size_t fb = field_bytes(b[i]);
+        for (int k = 0; k < TUNE_FIELDS; ++k)
+            F[i].push_back((double *)((char *)scratch + off + k * fb));
+        off += TUNE_FIELDS * fb;
+    }
+    DevBox *dtab = (DevBox *)((char *)scratch + off);
+    int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
+    const bool batched = nbox > 1;
+    StageCoef K{};
+    K.stage = 2;
+    K.a = K.b = K.b_next = K.a_next = 1e-3;
+    K.scale = 1.0;
+
+    std::vector<int> order;
+    for (int i = 0; i < (int)cands().size(); ++i)
+        order.push_back(i);
+    const int reps = flags ? 15 : 5;
+    hipEvent_t e0, e1;
+    S4_HIP(hipEventCreate(&e0));
+    S4_HIP(hipEventCreate(&e1));
+    int best = -1;
+    float best_t = 0;
+    for (int ci : order) {
+        const Cand &c = cands()[ci];
+        std::vector<DevBox> tab(nbox);
+        int64_t nitems = 0;
+        for (int i = 0; i < nbox; ++i) {
+            DevBox D = devbox(b[i], c);
+            D.item0 = (int)nitems;
+            nitems += dev_items(D);
+            D.in = F[i][0];
+            D.inmul = (kop == OP_ADJRHS || kop == OP_ADJSTAGE) ? F[i][1] : nullptr;
+            for (int k = 0; k < 7; ++k)
+                D.p[k] = F[i][2 + k];
+            for (int k = 0; k < 5; ++k)
+                D.q[k] = F[i][9 + k];
+            if (kop == OP_RHS || kop == OP_STAGE || kop == OP_FWDREC)
+                D.p[5] = nullptr; // c = 1 in the wave workloads
+            if (kop == OP_RHS)
+                D.p[0] = nullptr;
+            tab[i] = D;
+        }
+        if (batched) {
+            std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
+            memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+            if ((r = upload_table(dtab, bytes, s)))
+                break;
+        }
+        auto run = [&]() -> int {
+            if (batched) {
+                hipError_t e = launch_tiles_batched(kop, c.tx, c.nw, dtab, nbox, (int)nitems, counters,
+                                                    persistent_grid(ctx, kop, c, nitems), K, s);
+                return e == hipSuccess ? S4_OK : hip_fail(e, "tune launch");
+            }
+            return launch_one(ctx, kop, c, tab[0], K, s);
+        };
+        for (int w = 0; w < 2 && !r; ++w)
+            r = run();
+        std::vector<float> ts;
+        for (int k = 0; k < reps && !r; ++k) {
+            if (hipEventRecord(e0, s) != hipSuccess) {
+                r = fail(S4_EDEVICE, "event record");
+                break;
+            }
+            r = run();
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                r = r ? r : fail(S4_EDEVICE, "event sync");
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ts.push_back(ms);
+        }
+        if (r)
+            break;
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        if (best < 0 || med < best_t) {
+            best = ci;
+            best_t = med;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r)
+        return r;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[setup_key(ctx, op, b, nbox)] = best;
+    }
+    save_cache(ctx);
+    return S4_OK;
+}
+
+// JSON cache: {"<setup key>": candidate index, ...}; keys contain no quotes.
+static void load_cache(s4_ctx *ctx)
+{
+    std::ifstream f(ctx->cache_path);
+    if (!f)
+        return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while ((p = t.find('"', p)) != std::string::npos) {
+        size_t q = t.find('"', p + 1);
+        if (q == std::string::npos)
+            break;
+        std::string key = t.substr(p + 1, q - p - 1);
+        size_t colon = t.find(':', q);
+        if (colon == std::string::npos)
+            break;
+        int v = atoi(t.c_str() + colon + 1);
+        if (v >= 0 && v < (int)cands().size())
+            ctx->tuned[key] = v;
+        p = colon + 1;
+    }
+}
+
+static void save_cache(s4_ctx *ctx)
+{
+    if (ctx->cache_path.empty())
+        return;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::ofstream f(ctx->cache_path + ".tmp");
+    f << "{\n";
+    size_t k = 0;
+    for (auto &kv : ctx->tuned)
+        f << "  \"" << kv.first << "\": " << kv.second << (++k < ctx->tuned.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    std::rename((ctx->cache_path + ".tmp").c_str(), ctx->cache_path.c_str());
+}
+
+} // extern "C"

@@ -1,0 +1,248 @@
+// s4_internal.h -- types and tile geometry shared by the HIP kernels and the
+// host side of libsten4 (not installed; the public ABI is include/sten4.h).
+//
+// Traversal of one box (the GPU form of the paper's LoopControl split of a
+// loop's index space, Sec. III-A): the interior is cut into work items, each
+// an xy tile of TX x TY points and a chunk of TZ consecutive z planes.  A
+// workgroup owns one item at a time; its 64-wide wavefronts cover TX
+// consecutive x points (unit stride, so loads coalesce) and 64/TX rows; it
+// marches along z keeping the column's five stencil values (z-2..z+2) in
+// registers and stages the current plane, with a two-point halo in x and y,
+// in LDS.  Lanes outside the box do the loads (at readable addresses) but
+// store nothing: the edge mask of Sec. IV-C4.
+#pragma once
+
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#include <hip/hip_runtime.h>
+#define S4_HD __host__ __device__
+#else
+#define S4_HD
+#endif
+
+namespace s4 {
+
+// kinds of per-point work that ride on the tile traversal
+enum Op : int {
+    OP_RHS = 0,      // rho_t = c2 * L(u)                      (ghosts read)
+    OP_STAGE = 1,    // one fused RK4 stage                     (periodic addressing)
+    OP_ADJRHS = 2,   // (L(c2*lrho), lu)                        (periodic addressing)
+    OP_FWDREC = 3,   // forward stage recompute storing L(u_s)  (periodic addressing)
+    OP_ADJSTAGE = 4, // one fused adjoint RK4 stage             (periodic addressing)
+    OP_COUNT = 5
+};
+
+// One box as the kernels see it: geometry, stencil coefficients, the tile
+// decomposition and the op's field pointers.  All fields of a box share its
+// strides.  Passed by value to single-box kernels and stored as a device
+// table for the persistent batched kernels.
+struct DevBox {
+    int32_t n[3];
+    int32_t g;
+    int64_t sy, sz;        // element strides along y and z (x stride is 1)
+    double cx, cy, cz;     // 1 / (12 h_a^2)
+    double c0;             // -30 (cx + cy + cz)
+    int32_t tiles[3];      // tiles along x and y, z chunks
+    int32_t tz;            // z-chunk length
+    int32_t item0;         // index of this box's first work item in the launch
+    int32_t pad_;
+    const double *in;      // stencil input
+    const double *inmul;   // optional multiplier of the stencil input (c^2), pointwise
+    const double *p[7];    // op inputs (pointwise)
+    double *q[5];          // op outputs (pointwise)
+};
+
+// Scalars of one stage launch.
+struct StageCoef {
+    int stage;      // 1..4
+    double a;       // dt * (1/2, 1/2, 1, -)  weight of k_s in the next stage input
+    double b;       // dt * (1/6, 1/3, 1/3, 1/6)  weight of k_s in y_{n+1}
+    double scale;   // multiplier of the stencil input (adjoint stage 4: dt/6)
+    double b_next;  // adjoint: dt * c_{s-1}
+    double a_next;  // adjoint: dt * a_{s-1}
+};
+
+template <int TX, int NW>
+struct Tile {
+    static constexpr int NT = NW * 64;         // threads per workgroup
+    static constexpr int TY = NT / TX;         // rows per tile
+    static constexpr int LX = TX + 4;          // LDS plane row length (2-point halo each side)
+    static constexpr int LY = TY + 4;
+    static constexpr int NH = 4 * (TX + TY);   // halo points per plane
+    static constexpr int HS = (NH + NT - 1) / NT; // halo slots per thread
+    static_assert(TX == 16 || TX == 32 || TX == 64, "tile x extent");
+    static_assert(NT % TX == 0, "rows");
+};
+
+// Position p along an axis of n interior points mapped to an index that may
+// be read: periodic addressing wraps it into [0, n); ghost addressing keeps
+// it (callers never go below -2) but clamps points past n+1, which only
+// lanes outside the box touch, to the last ghost a radius-2 stencil reads.
+S4_HD inline int readable(int p, int n, bool wrap)
+{
+    if (wrap) {
+        int r = p % n;
+        return r < 0 ? r + n : r;
+    }
+    return p < n + 1 ? p : n + 1;
+}
+
+// element offset of point (i, j, k) from the box's ghost corner
+S4_HD inline int64_t elem(const DevBox &B, int i, int j, int k)
+{
+    return (int64_t)(i + B.g) + (int64_t)(j + B.g) * B.sy + (int64_t)(k + B.g) * B.sz;
+}
+
+// work item (local to its box) -> tile origin and z range
+struct ItemPos {
+    int x0, y0, z0, z1;
+};
+
+S4_HD inline ItemPos item_pos(const DevBox &B, int local, int tx_extent, int ty_extent)
+{
+    ItemPos P;
+    int tx = local % B.tiles[0];
+    int rest = local / B.tiles[0];
+    int ty = rest % B.tiles[1];
+    int tzi = rest / B.tiles[1];
+    P.x0 = tx * tx_extent;
+    P.y0 = ty * ty_extent;
+    P.z0 = tzi * B.tz;
+    P.z1 = P.z0 + B.tz < B.n[2] ? P.z0 + B.tz : B.n[2];
+    return P;
+}
+
+// halo slot h of a tile: LDS (row, col) and the tile-relative point (dx, dy)
+template <int TX, int NW>
+S4_HD inline void halo_slot(int h, int &lrow, int &lcol, int &dx, int &dy)
+{
+    using T = Tile<TX, NW>;
+    if (h < 2 * TX) { // two rows below the tile
+        dy = h / TX - 2;
+        dx = h % TX;
+    } else if (h < 4 * TX) { // two rows above
+        int e = h - 2 * TX;
+        dy = T::TY + e / TX;
+        dx = e % TX;
+    } else if (h < 4 * TX + 2 * T::TY) { // two columns left
+        int e = h - 4 * TX;
+        dy = e / 2;
+        dx = e % 2 - 2;
+    } else { // two columns right
+        int e = h - 4 * TX - 2 * T::TY;
+        dy = e / 2;
+        dx = TX + e % 2;
+    }
+    lrow = dy + 2;
+    lcol = dx + 2;
+}
+
+// Per-thread addressing of one work item, shared by the kernels and the
+// host-side geometry test: the thread's own column, its halo slots, the LDS
+// slots it writes, and the element offsets of plane k.
+template <int TX, int NW, bool WRAP>
+struct Walker {
+    using T = Tile<TX, NW>;
+    int i, j;          // interior point of this thread (may lie outside the box)
+    bool active;       // inside the box: computes and stores
+    int64_t col;       // x,y part of the element offset of the thread's column
+    int64_t hcol[T::HS];
+    int hl[T::HS];     // LDS index of each halo slot, -1 if unused
+    int lc;            // LDS index of the thread's own point
+    int nz, g;
+    int64_t sz;
+
+    S4_HD Walker(const DevBox &B, const ItemPos &P, int t)
+    {
+        const int lx = t % TX, ly = t / TX;
+        const int nx = B.n[0], ny = B.n[1];
+        nz = B.n[2];
+        g = B.g;
+        sz = B.sz;
+        i = P.x0 + lx;
+        j = P.y0 + ly;
+        active = i < nx && j < ny;
+        col = (int64_t)(readable(i, nx, WRAP) + g) + (int64_t)(readable(j, ny, WRAP) + g) * B.sy;
+        for (int s = 0; s < T::HS; ++s) {
+            const int h = t + s * T::NT;
+            int lrow = 0, lcol = 0, dx = 0, dy = 0;
+            if (h < T::NH)
+                halo_slot<TX, NW>(h, lrow, lcol, dx, dy);
+            hl[s] = h < T::NH ? lrow * T::LX + lcol : -1;
+            hcol[s] = (int64_t)(readable(P.x0 + dx, nx, WRAP) + g) +
+                      (int64_t)(readable(P.y0 + dy, ny, WRAP) + g) * B.sy;
+        }
+        lc = (ly + 2) * T::LX + (lx + 2);
+    }
+    // z part of the offset of plane k (k may be a stencil neighbour outside [0, nz))
+    S4_HD int64_t zoff(int k) const { return (int64_t)(readable(k, nz, WRAP) + g) * sz; }
+    // element offset of the thread's interior point in plane k (active threads only)
+    S4_HD int64_t point(const DevBox &B, int k) const
+    {
+        return (int64_t)(i + g) + (int64_t)(j + g) * B.sy + (int64_t)(k + g) * sz;
+    }
+};
+
+// Ghost shell of a box, enumerated for a one-thread-per-point fill: two z
+// slabs over the full x, y extent, two y slabs over the full x extent and
+// interior z, two x slabs over interior y, z.  Returns false for t past the
+// last ghost point.
+S4_HD inline int64_t ghost_count(const DevBox &B)
+{
+    const int64_t g = B.g, X = B.n[0] + 2 * g, Y = B.n[1] + 2 * g;
+    return 2 * g * X * Y + (int64_t)B.n[2] * 2 * g * X + (int64_t)B.n[2] * B.n[1] * 2 * g;
+}
+
+S4_HD inline bool ghost_point(const DevBox &B, int64_t t, int &i, int &j, int &k)
+{
+    const int g = B.g, nx = B.n[0], ny = B.n[1], nz = B.n[2];
+    const int64_t X = nx + 2 * g, Y = ny + 2 * g;
+    const int64_t nA = 2 * g * X * Y, nB = (int64_t)nz * 2 * g * X, nC = (int64_t)nz * ny * 2 * g;
+    if (t < 0)
+        return false;
+    if (t < nA) {
+        const int64_t pz = t / (X * Y), rem = t % (X * Y);
+        k = pz < g ? (int)pz - g : nz + (int)pz - g;
+        j = (int)(rem / X) - g;
+        i = (int)(rem % X) - g;
+        return true;
+    }
+    if ((t -= nA) < nB) {
+        k = (int)(t / (2 * g * X));
+        const int64_t rem = t % (2 * g * X);
+        const int r = (int)(rem / X);
+        j = r < g ? r - g : ny + r - g;
+        i = (int)(rem % X) - g;
+        return true;
+    }
+    if ((t -= nB) < nC) {
+        k = (int)(t / ((int64_t)ny * 2 * g));
+        const int64_t rem = t % ((int64_t)ny * 2 * g);
+        j = (int)(rem / (2 * g));
+        const int cc = (int)(rem % (2 * g));
+        i = cc < g ? cc - g : nx + cc - g;
+        return true;
+    }
+    return false;
+}
+
+S4_HD inline int wrap_index(int p, int n)
+{
+    int r = p % n;
+    return r < 0 ? r + n : r;
+}
+
+// split a launch of `nblocks` workgroups so that the hardware's round-robin
+// placement (block b runs on XCD b % nxcd) gives each XCD a contiguous range
+// of logical items: neighbouring tiles then share that XCD's L2.
+S4_HD inline int xcd_remap(int b, int nblocks, int nxcd)
+{
+    if (nxcd <= 1 || nblocks < nxcd)
+        return b;
+    int q = nblocks / nxcd, r = nblocks % nxcd;
+    int x = b % nxcd, l = b / nxcd;
+    return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+} // namespace s4

@@ -1,0 +1,363 @@
+// s4_kernels.hip -- FP64 4th-order stencil kernels for gfx950.
+//
+// All stencil work rides on one traversal (see s4_internal.h): a workgroup
+// takes an xy tile and a z chunk of a box, keeps each column's five
+// z-values in registers, stages the current plane with its 2-point halo in
+// LDS (double buffered, one barrier per plane) and hands the Laplacian at
+// each interior point to a pointwise epilogue (the "op").  The path is bound
+// by HBM bandwidth, not arithmetic, so there is no MFMA: the design goal is
+// one HBM read of every input point and one write of every output point.
+//
+// Arithmetic: FP64 throughout, written with explicit fma() and compiled
+// without automatic contraction, so every tile shape and launch mode
+// produces bit-identical results.
+
+#include "s4_internal.h"
+#include "s4_launch.h"
+
+namespace s4 {
+
+// L f at a point from its 13 taps (4th-order centred five-point formula per
+// axis): sum_a (16 (f_{-1} + f_{+1}) - (f_{-2} + f_{+2}) - 30 f_0) / (12 h_a^2)
+__device__ __forceinline__ double lap4(const DevBox &B, double c, double xm2, double xm1,
+                                       double xp1, double xp2, double ym2, double ym1,
+                                       double yp1, double yp2, double zm2, double zm1,
+                                       double zp1, double zp2)
+{
+    double sx = fma(16.0, xm1 + xp1, -(xm2 + xp2));
+    double sy = fma(16.0, ym1 + yp1, -(ym2 + yp2));
+    double sz = fma(16.0, zm1 + zp1, -(zm2 + zp2));
+    double r = B.c0 * c;
+    r = fma(B.cx, sx, r);
+    r = fma(B.cy, sy, r);
+    r = fma(B.cz, sz, r);
+    return r;
+}
+
+__device__ __forceinline__ void st(double *p, double v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// ---------------------------------------------------------------------------
+// pointwise epilogues.  c: element offset of the interior point; center: the
+// stencil input there (after the input transform); raw: scale * in[c];
+// lap: L of the transformed input.
+
+template <int OPK>
+__device__ __forceinline__ void epilogue(const DevBox &B, const StageCoef &K, int64_t c,
+                                         double center, double raw, double lap)
+{
+    if constexpr (OPK == OP_RHS) {
+        // rho_t = c^2 L u   (c2 optional)
+        const double *c2 = B.p[0];
+        st(B.q[0] + c, c2 ? c2[c] * lap : lap);
+    } else if constexpr (OPK == OP_STAGE) {
+        // k_s = (rho_s, c^2 L u_s); next stage input and the running sum
+        const double *c2 = B.p[5];
+        const double kr = c2 ? c2[c] * lap : lap;
+        const double ku = B.p[0][c];
+        if (K.stage == 1) { // y_s = y_n: u_n is the centre value
+            st(B.q[0] + c, fma(K.a, ku, center));
+            st(B.q[1] + c, fma(K.a, kr, ku));
+            st(B.q[2] + c, fma(K.b, ku, center));
+            st(B.q[3] + c, fma(K.b, kr, ku));
+        } else if (K.stage < 4) {
+            const double un = B.p[1][c], rn = B.p[2][c];
+            const double au = B.p[3][c], ar = B.p[4][c];
+            st(B.q[0] + c, fma(K.a, ku, un));
+            st(B.q[1] + c, fma(K.a, kr, rn));
+            st(B.q[2] + c, fma(K.b, ku, au));
+            st(B.q[3] + c, fma(K.b, kr, ar));
+        } else { // y_{n+1} = acc + dt/6 k4
+            const double au = B.p[3][c], ar = B.p[4][c];
+            st(B.q[0] + c, fma(K.b, ku, au));
+            st(B.q[1] + c, fma(K.b, kr, ar));
+        }
+    } else if constexpr (OPK == OP_ADJRHS) {
+        // F^T(lu, lrho) = (L(c^2 lrho), lu)
+        st(B.q[0] + c, lap);
+        st(B.q[1] + c, B.p[0][c]);
+    } else if constexpr (OPK == OP_FWDREC) {
+        // forward stage recompute: store L u_s; next stage input (u, rho)
+        const double *c2 = B.p[5];
+        st(B.q[2] + c, lap);
+        if (K.stage < 4) {
+            const double kr = c2 ? c2[c] * lap : lap;
+            const double ku = B.p[0][c];
+            const double un = K.stage == 1 ? center : B.p[1][c];
+            const double rn = K.stage == 1 ? ku : B.p[2][c];
+            st(B.q[0] + c, fma(K.a, ku, un));
+            st(B.q[1] + c, fma(K.a, kr, rn));
+        }
+    } else if constexpr (OPK == OP_ADJSTAGE) {
+        // adjoint stage s: yb_s = F^T(kb_s) = (L(c^2 kb_rho), kb_u);
+        // c2bar += kb_rho * L u_s; acc += yb_s;
+        // kb_{s-1} = dt c_{s-1} ybar + dt a_{s-1} yb_s   (s > 1)
+        // ybar_n = ybar + acc                              (s == 1)
+        const double lu = B.p[1][c], lr = B.p[2][c];
+        const double kbu = K.stage == 4 ? K.scale * lu : B.p[0][c];
+        const double ybu = lap, ybr = kbu;
+        if (B.q[4]) {
+            const double cb = B.p[6][c];
+            B.q[4][c] = fma(raw, B.p[5][c], cb);
+        }
+        double accu = ybu, accr = ybr;
+        if (K.stage < 4) {
+            accu = B.p[3][c] + ybu;
+            accr = B.p[4][c] + ybr;
+        }
+        if (K.stage > 1) {
+            st(B.q[0] + c, fma(K.a_next, ybu, K.b_next * lu));
+            st(B.q[1] + c, fma(K.a_next, ybr, K.b_next * lr));
+            st(B.q[2] + c, accu);
+            st(B.q[3] + c, accr);
+        } else {
+            B.q[0][c] = lu + accu;
+            B.q[1][c] = lr + accr;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one work item: an xy tile marched over its z chunk
+
+template <int TX, int NW, bool WRAP, int OPK>
+__device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, const StageCoef &K,
+                                         double *lds)
+{
+    using T = Tile<TX, NW>;
+    constexpr int PLANE = T::LY * T::LX;
+    const Walker<TX, NW, WRAP> w(B, P, threadIdx.x);
+    const int lc = w.lc;
+    const double *in = B.in;
+    const double *mul = B.inmul;
+    const double scale = K.scale;
+
+    // input transform: w = mul * (scale * in); raw = scale * in
+    auto ldw = [&](int64_t e, double &raw) -> double {
+        double v = in[e];
+        if (OPK == OP_ADJSTAGE)
+            v = scale * v;
+        raw = v;
+        if (mul)
+            v = mul[e] * v;
+        return v;
+    };
+
+    double r2, r3, r4, rd;
+    double q0 = ldw(w.col + w.zoff(P.z0 - 2), rd);
+    double q1 = ldw(w.col + w.zoff(P.z0 - 1), rd);
+    double q2 = ldw(w.col + w.zoff(P.z0), r2);
+    double q3 = ldw(w.col + w.zoff(P.z0 + 1), r3);
+    int buf = 0;
+    for (int k = P.z0; k < P.z1; ++k) {
+        const double q4 = ldw(w.col + w.zoff(k + 2), r4);
+        const int64_t zo = w.zoff(k);
+        double hvv[T::HS];
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0)
+                hvv[s] = ldw(w.hcol[s] + zo, rd);
+        double *L = lds + buf * PLANE;
+        L[lc] = q2;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0)
+                L[w.hl[s]] = hvv[s];
+        __syncthreads();
+        if (w.active) {
+            const double lap = lap4(B, q2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2],
+                                    L[lc - 2 * T::LX], L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX],
+                                    q0, q1, q3, q4);
+            epilogue<OPK>(B, K, w.point(B, k), q2, r2, lap);
+        }
+        q0 = q1;
+        q1 = q2;
+        q2 = q3;
+        q3 = q4;
+        r2 = r3;
+        r3 = r4;
+        buf ^= 1;
+    }
+}
+
+template <int TX, int NW, bool WRAP, int OPK>
+__global__ __launch_bounds__(NW * 64) void k_tiles_single(DevBox B, StageCoef K, int nxcd)
+{
+    using T = Tile<TX, NW>;
+    __shared__ double lds[2 * T::LY * T::LX];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, TX, T::TY);
+    run_item<TX, NW, WRAP, OPK>(B, P, K, lds);
+}
+
+// Persistent form: a fixed grid pulls items of all boxes from one counter.
+// counter[0] hands out items, counter[1] counts workgroups that ran out of
+// work; the last one resets both, so every launch starts from zero without
+// a memset.
+template <int TX, int NW, bool WRAP, int OPK>
+__global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restrict__ tab, int nbox,
+                                                          int nitems, int *counter, StageCoef K)
+{
+    using T = Tile<TX, NW>;
+    __shared__ double lds[2 * T::LY * T::LX];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(&counter[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= nitems)
+            break;
+        // box of this item: last box with item0 <= item
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevBox B = tab[lo];
+        const ItemPos P = item_pos(B, item - B.item0, TX, T::TY);
+        run_item<TX, NW, WRAP, OPK>(B, P, K, lds);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counter[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&counter[0], 0);
+            atomicExch(&counter[1], 0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// periodic ghost fill: every ghost point copies the interior point at its
+// wrapped coordinates.  One thread per ghost point; the ghost shell of a box
+// is enumerated as two z slabs (full x, y extent), two y slabs (full x
+// extent, interior z) and two x slabs (interior y, z).
+
+__global__ __launch_bounds__(256) void k_fill_periodic(DevBox B)
+{
+    int i, j, k;
+    if (!ghost_point(B, (int64_t)blockIdx.x * 256 + threadIdx.x, i, j, k))
+        return;
+    double *f = B.q[0];
+    f[elem(B, i, j, k)] = f[elem(B, wrap_index(i, B.n[0]), wrap_index(j, B.n[1]), wrap_index(k, B.n[2]))];
+}
+
+// ---------------------------------------------------------------------------
+// streaming copy probe (16-byte vectors, grid stride)
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void k_copy(dvec2 *__restrict__ dst, const dvec2 *__restrict__ src,
+                                             int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (; i < n; i += stride) {
+        dvec2 v = __builtin_nontemporal_load(src + i);
+        __builtin_nontemporal_store(v, dst + i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+template <int TX, int NW, bool WRAP, int OPK>
+static hipError_t launch_single_t(const DevBox &B, const StageCoef &K, int nitems, int nxcd, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tiles_single<TX, NW, WRAP, OPK>), dim3(nitems), dim3(NW * 64), 0, s, B, K, nxcd);
+    return hipGetLastError();
+}
+
+template <int TX, int NW, bool WRAP, int OPK>
+static hipError_t launch_batched_t(const DevBox *tab, int nbox, int nitems, int *counter, int grid,
+                                   const StageCoef &K, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tiles_batched<TX, NW, WRAP, OPK>), dim3(grid), dim3(NW * 64), 0, s, tab, nbox,
+                       nitems, counter, K);
+    return hipGetLastError();
+}
+
+#define S4_FOR_OPS(X, TX, NW)                                                                          \
+    X(TX, NW, false, OP_RHS)                                                                           \
+    X(TX, NW, true, OP_STAGE)                                                                          \
+    X(TX, NW, true, OP_ADJRHS)                                                                         \
+    X(TX, NW, true, OP_FWDREC)                                                                         \
+    X(TX, NW, true, OP_ADJSTAGE)
+
+#define S4_FOR_SHAPES(X)                                                                               \
+    S4_FOR_OPS(X, 64, 4)                                                                               \
+    S4_FOR_OPS(X, 64, 8)                                                                               \
+    S4_FOR_OPS(X, 32, 4)                                                                               \
+    S4_FOR_OPS(X, 32, 8)                                                                               \
+    S4_FOR_OPS(X, 16, 4)                                                                               \
+    S4_FOR_OPS(X, 16, 8)
+
+static bool wrap_of(int op)
+{
+    return op != OP_RHS;
+}
+
+hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const StageCoef &K, int nitems,
+                               int nxcd, hipStream_t s)
+{
+    const bool wrap = wrap_of(op);
+#define X(TX_, NW_, W_, O_)                                                                            \
+    if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
+        return launch_single_t<TX_, NW_, W_, O_>(B, K, nitems, nxcd, s);
+    S4_FOR_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
+                                int *counter, int grid, const StageCoef &K, hipStream_t s)
+{
+    const bool wrap = wrap_of(op);
+#define X(TX_, NW_, W_, O_)                                                                            \
+    if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
+        return launch_batched_t<TX_, NW_, W_, O_>(tab, nbox, nitems, counter, grid, K, s);
+    S4_FOR_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int max_blocks_per_cu(int op, int tx, int nw)
+{
+    const bool wrap = wrap_of(op);
+    int nb = 0;
+#define X(TX_, NW_, W_, O_)                                                                            \
+    if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_) {                                            \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tiles_batched<TX_, NW_, W_, O_>,        \
+                                                         NW_ * 64, 0) != hipSuccess)                   \
+            return 0;                                                                                  \
+        return nb;                                                                                     \
+    }
+    S4_FOR_SHAPES(X)
+#undef X
+    return 0;
+}
+
+hipError_t launch_fill(const DevBox &B, hipStream_t s)
+{
+    const int64_t nblk = (ghost_count(B) + 255) / 256;
+    if (nblk > 0x7fffffff)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_periodic, dim3((unsigned)nblk), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (dvec2 *)dst, (const dvec2 *)src,
+                       (int64_t)(bytes / 16));
+    return hipGetLastError();
+}
+
+} // namespace s4

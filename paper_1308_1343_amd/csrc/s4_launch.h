@@ -1,0 +1,29 @@
+// s4_launch.h -- launchers exported by s4_kernels.hip to the host side.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "s4_internal.h"
+
+namespace s4 {
+
+// One box, one workgroup per work item (grid = nitems); nxcd > 1 spreads
+// contiguous item ranges over the XCDs.
+hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const StageCoef &K, int nitems,
+                               int nxcd, hipStream_t s);
+
+// All boxes of a device table in one persistent launch of `grid` workgroups
+// over a shared item counter (counter[0..1] must be zero before the first
+// launch; each launch leaves them zero).
+hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
+                                int *counter, int grid, const StageCoef &K, hipStream_t s);
+
+// Resident workgroups per CU of the batched kernel for this shape (0 if unknown).
+int max_blocks_per_cu(int op, int tx, int nw);
+
+// Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
+hipError_t launch_fill(const DevBox &B, hipStream_t s);
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s);
+
+} // namespace s4

@@ -1,0 +1,221 @@
+// Host-side check of the stencil traversal's addressing (s4_internal.h), run
+// by tests/test_geometry.py.  For every work item, thread and plane of a
+// box it replays the loads, LDS writes and stores the kernels issue -- with
+// the same Walker, item_pos and halo_slot code -- tagging each value with the
+// element it came from, and checks that
+//   * every global read lies inside the box's array (and, with periodic
+//     addressing, inside the interior; with ghost addressing, inside the
+//     radius-2 shell),
+//   * no two threads write different points into one LDS slot of a plane,
+//   * each of the 13 stencil taps an active lane uses holds the right point,
+//   * every interior point is stored exactly once and nothing else is.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "s4_internal.h"
+
+using namespace s4;
+
+static int fails = 0;
+#define CHECK(cond, ...)                                                                               \
+    do {                                                                                               \
+        if (!(cond)) {                                                                                 \
+            if (fails < 20) {                                                                          \
+                fprintf(stderr, "FAIL %s:%d: ", __FILE__, __LINE__);                                  \
+                fprintf(stderr, __VA_ARGS__);                                                          \
+                fprintf(stderr, "\n");                                                                 \
+            }                                                                                          \
+            ++fails;                                                                                   \
+        }                                                                                              \
+    } while (0)
+
+static int wrapi(int p, int n)
+{
+    int r = p % n;
+    return r < 0 ? r + n : r;
+}
+
+template <int TX, int NW, bool WRAP>
+static void run(int nx, int ny, int nz, int g, int padx, int pady, int tz_req)
+{
+    using T = Tile<TX, NW>;
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.g = g;
+    B.sy = nx + 2 * g + padx;
+    B.sz = B.sy * (ny + 2 * g + pady);
+    B.tz = tz_req > 0 && tz_req < nz ? tz_req : nz;
+    B.tiles[0] = (nx + TX - 1) / TX;
+    B.tiles[1] = (ny + T::TY - 1) / T::TY;
+    B.tiles[2] = (nz + B.tz - 1) / B.tz;
+    const int64_t total = B.sz * (nz + 2 * g);
+    std::vector<int> written(total, 0);
+    const int nitems = B.tiles[0] * B.tiles[1] * B.tiles[2];
+    auto expect = [&](int i, int j, int k) -> int64_t {
+        if (WRAP)
+            return elem(B, wrapi(i, nx), wrapi(j, ny), wrapi(k, nz));
+        return elem(B, i, j, k);
+    };
+    auto check_read = [&](int64_t e, const char *what) {
+        CHECK(e >= 0 && e < total, "%s read %lld outside [0,%lld)", what, (long long)e, (long long)total);
+        if (e < 0 || e >= total)
+            return;
+        const int k = (int)(e / B.sz) - g, j = (int)(e % B.sz / B.sy) - g, i = (int)(e % B.sy) - g;
+        if (WRAP)
+            CHECK(i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz, "%s read a ghost (%d,%d,%d)", what, i, j, k);
+        else
+            CHECK(i >= -2 && i < nx + 2 && j >= -2 && j < ny + 2 && k >= -2 && k < nz + 2,
+                  "%s read beyond the radius-2 shell (%d,%d,%d)", what, i, j, k);
+    };
+    // also exercise the XCD remap: logical item of every hardware block
+    std::vector<int> seen(nitems, 0);
+    for (int b = 0; b < nitems; ++b) {
+        const int it = xcd_remap(b, nitems, 8);
+        CHECK(it >= 0 && it < nitems, "remap out of range");
+        if (it >= 0 && it < nitems)
+            seen[it]++;
+    }
+    for (int it = 0; it < nitems; ++it)
+        CHECK(seen[it] == 1, "remap not a bijection at %d", it);
+
+    std::vector<Walker<TX, NW, WRAP>> W;
+    std::vector<int64_t> lds(2 * T::LY * T::LX);
+    for (int item = 0; item < nitems; ++item) {
+        const ItemPos P = item_pos(B, item, TX, T::TY);
+        CHECK(P.z0 < P.z1 && P.z1 <= nz, "empty or overlong z range");
+        W.clear();
+        for (int t = 0; t < T::NT; ++t)
+            W.emplace_back(B, P, t);
+        std::vector<int64_t> q(T::NT * 5);
+        for (int t = 0; t < T::NT; ++t)
+            for (int d = 0; d < 4; ++d) {
+                const int64_t e = W[t].col + W[t].zoff(P.z0 - 2 + d);
+                check_read(e, "queue warm-up");
+                q[t * 5 + d] = e;
+            }
+        for (int k = P.z0; k < P.z1; ++k) {
+            std::fill(lds.begin(), lds.end(), -1);
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                const int64_t e4 = w.col + w.zoff(k + 2);
+                check_read(e4, "queue");
+                q[t * 5 + 4] = e4;
+                CHECK(w.lc >= 0 && w.lc < T::LY * T::LX, "LDS slot out of range");
+                const int64_t own = q[t * 5 + 2];
+                CHECK(lds[w.lc] == -1 || lds[w.lc] == own, "LDS own-slot conflict");
+                lds[w.lc] = own;
+                for (int s = 0; s < T::HS; ++s) {
+                    if (w.hl[s] < 0)
+                        continue;
+                    const int64_t e = w.hcol[s] + w.zoff(k);
+                    check_read(e, "halo");
+                    CHECK(w.hl[s] >= 0 && w.hl[s] < T::LY * T::LX, "halo LDS slot out of range");
+                    CHECK(lds[w.hl[s]] == -1 || lds[w.hl[s]] == e, "halo LDS conflict");
+                    lds[w.hl[s]] = e;
+                }
+            }
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                if (!w.active)
+                    continue;
+                const int i = w.i, j = w.j;
+                CHECK(q[t * 5 + 2] == expect(i, j, k), "centre tag");
+                for (int d = -2; d <= 2; ++d) {
+                    if (d == 0)
+                        continue;
+                    CHECK(lds[w.lc + d] == expect(i + d, j, k), "x tap %d at (%d,%d,%d)", d, i, j, k);
+                    CHECK(lds[w.lc + d * T::LX] == expect(i, j + d, k), "y tap %d at (%d,%d,%d)", d, i, j, k);
+                    CHECK(q[t * 5 + 2 + d] == expect(i, j, k + d), "z tap %d at (%d,%d,%d)", d, i, j, k);
+                }
+                const int64_t c = w.point(B, k);
+                CHECK(c == elem(B, i, j, k), "store offset");
+                if (c >= 0 && c < total)
+                    written[c]++;
+            }
+            for (int t = 0; t < T::NT; ++t)
+                for (int d = 0; d < 4; ++d)
+                    q[t * 5 + d] = q[t * 5 + d + 1];
+        }
+    }
+    for (int k = -g; k < nz + g; ++k)
+        for (int j = -g; j < ny + g; ++j)
+            for (int i = -g; i < nx + g; ++i) {
+                const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+                const int c = written[elem(B, i, j, k)];
+                CHECK(c == (in ? 1 : 0), "point (%d,%d,%d) stored %d times", i, j, k, c);
+            }
+}
+
+// the ghost-fill enumeration: every ghost point of the shell exactly once,
+// never an interior point, and every source an interior point
+static void ghost_shell(int nx, int ny, int nz, int g)
+{
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.g = g;
+    B.sy = nx + 2 * g;
+    B.sz = B.sy * (ny + 2 * g);
+    const int64_t total = B.sz * (nz + 2 * g);
+    std::vector<int> hit(total, 0);
+    const int64_t cnt = ghost_count(B);
+    for (int64_t t = -1; t < cnt + 300; ++t) {
+        int i = 0, j = 0, k = 0;
+        const bool ok = ghost_point(B, t, i, j, k);
+        CHECK(ok == (t >= 0 && t < cnt), "ghost_point validity at %lld", (long long)t);
+        if (!ok)
+            continue;
+        CHECK(i >= -g && i < nx + g && j >= -g && j < ny + g && k >= -g && k < nz + g, "ghost out of the array");
+        const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+        CHECK(!in, "interior point (%d,%d,%d) enumerated as ghost", i, j, k);
+        hit[elem(B, i, j, k)]++;
+        const int si = wrap_index(i, nx), sj = wrap_index(j, ny), sk = wrap_index(k, nz);
+        CHECK(si >= 0 && si < nx && sj >= 0 && sj < ny && sk >= 0 && sk < nz, "source not interior");
+    }
+    for (int k = -g; k < nz + g; ++k)
+        for (int j = -g; j < ny + g; ++j)
+            for (int i = -g; i < nx + g; ++i) {
+                const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+                CHECK(hit[elem(B, i, j, k)] == (in ? 0 : 1), "ghost (%d,%d,%d) hit %d times", i, j, k,
+                      hit[elem(B, i, j, k)]);
+            }
+}
+
+template <int TX, int NW>
+static void shapes()
+{
+    const int S[][7] = {
+        // nx ny nz g padx pady tz
+        {32, 32, 32, 2, 0, 0, 0},   {32, 32, 32, 2, 12, 0, 8},  {37, 19, 23, 2, 3, 1, 16},
+        {5, 7, 3, 2, 0, 0, 2},      {1, 1, 1, 2, 0, 0, 0},      {2, 3, 2, 3, 1, 0, 1},
+        {70, 9, 5, 3, 6, 2, 4},     {16, 48, 11, 2, 0, 0, 64},  {64, 8, 9, 4, 0, 0, 3},
+        {129, 17, 6, 2, 15, 0, 32},
+    };
+    for (auto &s : S) {
+        run<TX, NW, false>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
+        run<TX, NW, true>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
+    }
+}
+
+int main()
+{
+    const int G[][4] = {{32, 32, 32, 2}, {5, 7, 6, 3}, {70, 9, 5, 3}, {2, 2, 2, 2}, {3, 17, 4, 3}, {1, 1, 1, 2}};
+    for (auto &s : G)
+        ghost_shell(s[0], s[1], s[2], s[3]);
+    shapes<64, 4>();
+    shapes<64, 8>();
+    shapes<32, 4>();
+    shapes<32, 8>();
+    shapes<16, 4>();
+    shapes<16, 8>();
+    if (fails) {
+        fprintf(stderr, "%d failures\n", fails);
+        return 1;
+    }
+    printf("tile walk OK\n");
+    return 0;
+}

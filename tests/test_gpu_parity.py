@@ -1,0 +1,262 @@
+"""HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance: max-norm relative error over interior points <= 1e-12 (the kernels
+fuse multiply-adds and scale by precomputed 1/(12 h^2), the oracle divides
+and does not fuse, so results agree to rounding, not bit for bit).  Integer
+and copy work (ghost fill) is compared bit for bit; tile shapes and launch
+modes of the HIP path are compared with each other bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1308_1343_amd as S
+import workload as W
+from _gpu import NAN, dev, dev_full, ghosts_untouched, host, inner, rel
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return S.Context(0)
+
+
+def rand_box(n, g, seed, stream):
+    nx, ny, nz = n
+    return O.embed(W.uniform_pm1(seed, stream, (nz, ny, nx)), g)
+
+
+SHAPES = [((32, 32, 32), 2), ((37, 19, 23), 2), ((5, 7, 6), 3), ((70, 9, 5), 3), ((1, 3, 2), 2), ((64, 64, 16), 2)]
+
+
+@pytest.mark.parametrize("n,g", SHAPES)
+@pytest.mark.parametrize("pad", [True, False])
+def test_fill_bitexact(ctx, n, g, pad):
+    if min(n) < g:
+        pytest.skip("periodic fill needs n >= g")
+    a = rand_box(n, g, 1, 1)
+    t = dev(a, g, pad)
+    S.s4_fill_ghosts_periodic(ctx, S.box_of(t, g, 0.1), [t])
+    want = O.fill_ghosts_periodic(a.copy(), g)
+    np.testing.assert_array_equal(host(t), want)
+
+
+@pytest.mark.parametrize("n,g", SHAPES)
+@pytest.mark.parametrize("with_c2", [False, True])
+def test_wave_rhs_parity(ctx, n, g, with_c2):
+    dx = (1.0 / 32, 1.0 / 24, 1.0 / 40)
+    a = O.fill_ghosts_periodic(rand_box(n, g, 2, 1), g)
+    c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(2, 2, n[::-1]), g) if with_c2 else None
+    u = dev_full(a, g)
+    c2d = dev(c2, g) if with_c2 else None
+    out = S.alloc_field(n, g, fill=NAN)
+    b = S.box_of(u, g, dx)
+    S.s4_wave_rhs(ctx, b, [u], None if c2d is None else [c2d], [out])
+    got = host(out)
+    want = O.wave_rhs(a, g, dx, c2)
+    assert rel(got, want, g) <= TOL
+    assert np.all(np.isfinite(inner(got, g))) and ghosts_untouched(got, g)
+
+
+def test_wave32_rhs_and_candidates_bitwise(ctx):
+    d = W.wave32()
+    g = d["ghost"]
+    a = O.fill_ghosts_periodic(O.embed(d["u"], g), g)
+    u = dev_full(a, g)
+    b = S.box_of(u, g, d["dx"])
+    want = O.wave_rhs(a, g, d["dx"])
+    ref = None
+    nc = S.s4_get_choice(ctx, S.S4_OP_WAVE_RHS, b)["ncandidates"]
+    for cand in range(nc):
+        S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, cand)
+        out = S.alloc_field(d["n"], g, fill=NAN)
+        S.s4_wave_rhs(ctx, b, [u], None, [out])
+        got = host(out)
+        if ref is None:
+            ref = got
+            assert rel(got, want, g) <= TOL
+        np.testing.assert_array_equal(got, ref, err_msg=f"candidate {cand}")
+    S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, -1)
+
+
+@pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
+def test_wave32_rk4_parity(ctx, mode):
+    d = W.wave32()
+    g = d["ghost"]
+    u0, r0 = O.embed(d["u"], g), O.embed(d["rho"], g)
+    wu, wr = O.rk4(u0, r0, g, d["dx"], d["dt"], d["nsteps"])
+    u, r = dev(u0, g), dev(r0, g)
+    b = S.box_of(u, g, d["dx"])
+    S.s4_rk4(ctx, b, [u], [r], None, d["dt"], d["nsteps"], mode)
+    gu, gr = host(u), host(r)
+    assert rel(gu, wu, g) <= TOL and rel(gr, wr, g) <= TOL
+    assert ghosts_untouched(gu, g) and ghosts_untouched(gr, g)
+
+
+def test_rk4_modes_and_candidates_bitwise(ctx):
+    n, g = (37, 19, 23), 2
+    dx = (1 / 37, 1 / 19, 1 / 23)
+    dt = 0.2 / 37
+    u0, r0 = rand_box(n, g, 3, 1), rand_box(n, g, 3, 2)
+    c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(3, 3, n[::-1]), g)
+    wu, wr = O.rk4(u0, r0, g, dx, dt, 3, c2)
+    c2d = dev(c2, g)
+    ref = None
+    b = None
+    for cand in [None, 0, 7, 13, 21, 29]:
+        for mode in ["perbox", "graph"]:
+            u, r = dev(u0, g), dev(r0, g)
+            b = S.box_of(u, g, dx)
+            if cand is not None:
+                S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
+            S.s4_rk4(ctx, b, [u], [r], [c2d], dt, 3, mode)
+            got = (host(u), host(r))
+            if ref is None:
+                ref = got
+                assert rel(got[0], wu, g) <= TOL and rel(got[1], wr, g) <= TOL
+            np.testing.assert_array_equal(got[0], ref[0])
+            np.testing.assert_array_equal(got[1], ref[1])
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+
+
+def small_bboxset(seed=7, nbox=9):
+    seq = W.Sequence(seed, 1)
+    boxes = []
+    for i in range(nbox):
+        n = tuple(seq.integer(5, 40) for _ in range(3))
+        lev = i % 3
+        h = (1.0 / 32) / 2 ** lev
+        boxes.append(dict(n=n, level=lev, dx=(h, h, h)))
+    return boxes
+
+
+def run_bboxset(ctx, boxes, g, dt, nsteps, mode, seed=8, ws=None):
+    us, rs, bs = [], [], []
+    for i, bx in enumerate(boxes):
+        u0, r0 = rand_box(bx["n"], g, seed, 2 * i), rand_box(bx["n"], g, seed, 2 * i + 1)
+        u, r = dev(u0, g), dev(r0, g)
+        us.append(u)
+        rs.append(r)
+        bs.append(S.box_of(u, g, bx["dx"], bx["level"]))
+    S.s4_rk4(ctx, bs, us, rs, None, dt, nsteps, mode, ws=ws)
+    return [host(u) for u in us], [host(r) for r in rs]
+
+
+def test_bboxset_modes_match_oracle(ctx):
+    boxes = small_bboxset()
+    g, dt = 3, 0.25 / 128
+    res = {m: run_bboxset(ctx, boxes, g, dt, 2, m) for m in ["perbox", "batched", "graph"]}
+    for m in ["batched", "graph"]:
+        for a, b in zip(res[m][0] + res[m][1], res["perbox"][0] + res["perbox"][1]):
+            np.testing.assert_array_equal(a, b)
+    for i, bx in enumerate(boxes):
+        u0, r0 = rand_box(bx["n"], g, 8, 2 * i), rand_box(bx["n"], g, 8, 2 * i + 1)
+        wu, wr = O.rk4(u0, r0, g, bx["dx"], dt, 2)
+        assert rel(res["graph"][0][i], wu, g) <= TOL and rel(res["graph"][1][i], wr, g) <= TOL
+
+
+def test_graph_replays_match_eager(ctx):
+    """One captured step replayed several times, with eager work in between."""
+    boxes = small_bboxset(11, 5)
+    g, dt = 3, 0.25 / 128
+    us, rs, bs = [], [], []
+    for i, bx in enumerate(boxes):
+        u, r = dev(rand_box(bx["n"], g, 12, 2 * i), g), dev(rand_box(bx["n"], g, 12, 2 * i + 1), g)
+        us.append(u); rs.append(r); bs.append(S.box_of(u, g, bx["dx"]))
+    ue = [dev(host(u), g) for u in us]
+    re_ = [dev(host(r), g) for r in rs]
+    ws = S.workspace(S.s4_workspace_size(bs, S.S4_OP_RK4, S.S4_GRAPH))
+    wse = S.workspace(S.s4_workspace_size(bs, S.S4_OP_RK4, S.S4_BATCHED))
+    for rep in range(4):
+        S.s4_rk4(ctx, bs, us, rs, None, dt, 1, "graph", ws=ws)
+        S.s4_rk4(ctx, [S.box_of(u, g, bx["dx"]) for u, bx in zip(ue, boxes)], ue, re_, None, dt, 1, "batched", ws=wse)
+        torch.cuda.synchronize()
+        for a, b in zip(us + rs, ue + re_):
+            np.testing.assert_array_equal(host(a), host(b), err_msg=f"replay {rep}")
+
+
+@pytest.mark.parametrize("with_c2", [False, True])
+def test_adjoint_rhs_parity_and_identity(ctx, with_c2):
+    n, g = (12, 10, 14), 2
+    dx = (0.1, 0.12, 0.08)
+    c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(4, 1, n[::-1]), g) if with_c2 else None
+    lu, lr = rand_box(n, g, 4, 2), rand_box(n, g, 4, 3)
+    wu, wr = O.wave_adjoint_rhs(lu, lr, g, dx, c2)
+    ou, orr = S.alloc_field(n, g, fill=NAN), S.alloc_field(n, g, fill=NAN)
+    lud, lrd = dev(lu, g), dev(lr, g)
+    c2d = [dev(c2, g)] if with_c2 else None
+    b = S.box_of(lud, g, dx)
+    S.s4_wave_adjoint_rhs(ctx, b, [lud], [lrd], c2d, [ou], [orr])
+    gu, gr = host(ou), host(orr)
+    assert rel(gu, wu, g) <= TOL
+    np.testing.assert_array_equal(inner(gr, g), inner(wr, g))
+    # <A v, w> = <v, A^T w> with A v = (rho, c^2 L_p u) from the forward kernels
+    v_u = O.fill_ghosts_periodic(rand_box(n, g, 4, 5), g)
+    v_r = rand_box(n, g, 4, 6)
+    rt = S.alloc_field(n, g, fill=NAN)
+    S.s4_wave_rhs(ctx, b, [dev_full(v_u, g)], c2d, [rt])
+    Av_r = host(rt)
+    lhs = np.sum(inner(v_r, g) * inner(lu, g)) + np.sum(inner(Av_r, g) * inner(lr, g))
+    rhs = np.sum(inner(v_u, g) * inner(gu, g)) + np.sum(inner(v_r, g) * inner(gr, g))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.sum(np.abs(inner(Av_r, g) * inner(lr, g))))
+
+
+@pytest.mark.parametrize("with_c2", [False, True])
+def test_adjoint_step_parity(ctx, with_c2):
+    n, g = (10, 12, 9), 2
+    dx = (1 / 10, 1 / 12, 1 / 9)
+    dt = 0.02
+    c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(5, 1, n[::-1]), g) if with_c2 else None
+    un, rn = rand_box(n, g, 5, 2), rand_box(n, g, 5, 3)
+    lu, lr = rand_box(n, g, 5, 4), rand_box(n, g, 5, 5)
+    cb0 = rand_box(n, g, 5, 6) if with_c2 else None
+    wu, wr, wc = O.rk4_adjoint_step(un, rn, lu, lr, g, dx, dt, c2, cb0)
+    und, rnd = dev(un, g), dev(rn, g)
+    lud, lrd = dev(lu, g), dev(lr, g)
+    c2d = dev(c2, g) if with_c2 else None
+    cbd = dev(cb0, g) if with_c2 else None
+    b = S.box_of(und, g, dx)
+    S.s4_rk4_adjoint_step(ctx, b, und, rnd, c2d, dt, lud, lrd, cbd)
+    assert rel(host(lud), wu, g) <= TOL
+    assert rel(host(lrd), wr, g) <= TOL
+    if with_c2:
+        assert rel(host(cbd), wc, g) <= TOL
+    # inputs untouched
+    np.testing.assert_array_equal(inner(host(und), g), inner(un, g))
+
+
+def test_tune_records_choice(ctx):
+    n, g = (40, 24, 20), 2
+    u = S.alloc_field(n, g, fill=0.0)
+    b = S.box_of(u, g, 0.05)
+    assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["tuned"] == 0
+    S.s4_tune(ctx, S.S4_OP_RK4, b, flags=0)
+    ch = S.s4_get_choice(ctx, S.S4_OP_RK4, b)
+    assert ch["tuned"] == 1 and 0 <= ch["candidate"] < ch["ncandidates"]
+
+
+def test_copy_probe(ctx):
+    src = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    S.s4_copy(ctx, dst, src)
+    assert torch.equal(dst, src)
+
+
+def test_errors_on_device_calls(ctx):
+    n, g = (8, 8, 8), 2
+    u = S.alloc_field(n, g, fill=0.0)
+    b = S.box_of(u, g, 0.1)
+    with pytest.raises(S.Sten4Error) as e:
+        S.s4_wave_rhs(ctx, b, [u], None, [u])  # output aliases the stencil input
+    assert e.value.code == S.S4_EALIAS
+    r = S.alloc_field(n, g, fill=0.0)
+    small = S.workspace(1024)
+    with pytest.raises(S.Sten4Error) as e:
+        S.s4_rk4(ctx, b, [u], [r], None, 0.01, 1, "perbox", ws=small)
+    assert e.value.code == S.S4_ENOMEM
+    with pytest.raises(S.Sten4Error) as e:
+        S.s4_rk4(ctx, b, [u], [r], None, -0.01, 1, "perbox")
+    assert e.value.code == S.S4_EINVAL
