@@ -184,6 +184,99 @@ struct Walker {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Mixed-derivative traversal.  The LDS plane holds the plane being loaded
+// with a full 5x5 neighbourhood (corners included, which the xy cross
+// derivative reads); a second LDS plane holds D1_x of that plane on the
+// tile's rows and its two rows above and below.
+
+template <int TX, int NW>
+struct MixTile {
+    using T = Tile<TX, NW>;
+    static constexpr int LX = TX + 4, LY = T::TY + 4;
+    static constexpr int PF = LX * LY;          // f plane
+    static constexpr int PD = TX * LY;          // D1_x plane
+    static constexpr int NHC = T::NH + 16;      // halo incl. 16 corner points
+    static constexpr int HS = (NHC + T::NT - 1) / T::NT;
+    static constexpr int ND = 4 * TX;           // D1_x points on the halo rows
+    static constexpr int DS = (ND + T::NT - 1) / T::NT;
+};
+
+// halo slot h of the mixed tile: edges as halo_slot, then the 16 corners
+template <int TX, int NW>
+S4_HD inline void halo_slot_c(int h, int &dx, int &dy)
+{
+    using T = Tile<TX, NW>;
+    if (h < T::NH) {
+        int lrow, lcol;
+        halo_slot<TX, NW>(h, lrow, lcol, dx, dy);
+        return;
+    }
+    const int e = h - T::NH;
+    const int ox = e % 4, oy = e / 4;
+    dx = ox < 2 ? ox - 2 : TX + ox - 2;
+    dy = oy < 2 ? oy - 2 : T::TY + oy - 2;
+}
+
+template <int TX, int NW>
+struct MixWalker {
+    using T = Tile<TX, NW>;
+    using M = MixTile<TX, NW>;
+    int i, j;
+    bool active;
+    int64_t col;
+    int64_t hcol[M::HS];
+    int hl[M::HS];   // f-plane LDS index of each halo slot, -1 if unused
+    int lf;          // f-plane LDS index of the own point
+    int ld;          // D1_x-plane LDS index of the own point
+    int dlf[M::DS];  // f-plane LDS index of each halo-row D1_x point, -1 if unused
+    int dld[M::DS];  // D1_x-plane LDS index of it
+    int nz, g;
+    int64_t sz;
+
+    S4_HD MixWalker(const DevBox &B, const ItemPos &P, int t)
+    {
+        const int lx = t % TX, ly = t / TX;
+        const int nx = B.n[0], ny = B.n[1];
+        nz = B.n[2];
+        g = B.g;
+        sz = B.sz;
+        i = P.x0 + lx;
+        j = P.y0 + ly;
+        active = i < nx && j < ny;
+        col = (int64_t)(readable(i, nx, false) + g) + (int64_t)(readable(j, ny, false) + g) * B.sy;
+        for (int s = 0; s < M::HS; ++s) {
+            const int h = t + s * T::NT;
+            int dx = 0, dy = 0;
+            if (h < M::NHC)
+                halo_slot_c<TX, NW>(h, dx, dy);
+            hl[s] = h < M::NHC ? (dy + 2) * M::LX + dx + 2 : -1;
+            // rows and columns left of the box start at -2 >= -g; right and
+            // above are clamped like the own point
+            hcol[s] = (int64_t)(readable(P.x0 + dx, nx, false) + g) +
+                      (int64_t)(readable(P.y0 + dy, ny, false) + g) * B.sy;
+        }
+        lf = (ly + 2) * M::LX + lx + 2;
+        ld = (ly + 2) * TX + lx;
+        for (int s = 0; s < M::DS; ++s) {
+            const int h = t + s * T::NT;
+            if (h < M::ND) {
+                const int r = h / TX, dx = h % TX;
+                const int dy = r < 2 ? r - 2 : T::TY + r - 2;
+                dlf[s] = (dy + 2) * M::LX + dx + 2;
+                dld[s] = (dy + 2) * TX + dx;
+            } else {
+                dlf[s] = dld[s] = -1;
+            }
+        }
+    }
+    S4_HD int64_t zoff(int k) const { return (int64_t)(readable(k, nz, false) + g) * sz; }
+    S4_HD int64_t point(const DevBox &B, int k) const
+    {
+        return (int64_t)(i + g) + (int64_t)(j + g) * B.sy + (int64_t)(k + g) * sz;
+    }
+};
+
 // Ghost shell of a box, enumerated for a one-thread-per-point fill: two z
 // slabs over the full x, y extent, two y slabs over the full x extent and
 // interior z, two x slabs over interior y, z.  Returns false for t past the
