@@ -36,6 +36,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpoint-updates/s + % HBM peak, 4th-order 3D stencil RHS; batched & adjoint"
 HBM_PEAK_GBS = 8000.0
+# FP64 operations per field point issued by the mixed kernel (fma counted as 2):
+# D1_x, D1_y, D1_z 5 each; D2 in x, y, z 5 each; D1_x on halo rows 5 * 4/TY
+# (~2.5 at TY = 8); D_xy, D_xz, D_yz 5 each; quadratic form 12; sums 3
+MIXED_FLOPS_PER_FIELD_POINT = 63
 
 
 def log(*a):
@@ -68,7 +72,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="rk4,rhs,copy,batched,adjoint,cpu")
+    ap.add_argument("--sections", default="rk4,rhs,copy,mixed,batched,adjoint,cpu")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -178,6 +182,43 @@ def main():
         out["copy"] = {"bytes": 2 * nb, "us": round(ms * 1e3, 1), "GBs": round(2 * nb / (ms / 1e3) / 1e9, 1)}
         log(f"[bench] copy: {out['copy']}")
         del a, b
+
+    # ------------------------------------------------------------------ multi-field mixed derivatives
+    if "mixed" in sections:
+        md = W.mixed_fields()
+        gm = md["ghost"]
+        nm = md["n"]
+        mpts = nm[0] * nm[1] * nm[2]
+        gfs = []
+        for f in md["fields"]:
+            t = S.alloc_field(nm, gm, fill=0.0)
+            S.interior(t, gm).copy_(torch.from_numpy(f))
+            gfs.append(t)
+        mbox = S.box_of(gfs[0], gm, md["dx"])
+        S.s4_fill_ghosts_periodic(ctx, [mbox] * len(gfs), gfs)
+        mouts = [S.alloc_field(nm, gm, fill=0.0) for _ in gfs]
+        for _ in range(3):
+            S.s4_deriv_mixed(ctx, mbox, gfs, md["A"], mouts)
+        reps = 10
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            S.s4_deriv_mixed(ctx, mbox, gfs, md["A"], mouts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nf = len(gfs)
+        gbs = mpts * nf * 16 / (ms / 1e3) / 1e9
+        ch = S.s4_get_choice(ctx, S.S4_OP_DERIV_MIXED, mbox)
+        out["mixed"] = {"workload": "mixed192: 6 fields, 192^3 + 2 ghosts, sine-mode fields, symmetric A",
+                        "us_per_call": round(ms * 1e3, 1), "gpoint_per_s": round(mpts / (ms / 1e3) / 1e9, 2),
+                        "field_gpoint_per_s": round(mpts * nf / (ms / 1e3) / 1e9, 1),
+                        "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                        "bytes_per_point": 16 * nf,
+                        "fp64_tflops_est": round(mpts * nf * MIXED_FLOPS_PER_FIELD_POINT / (ms / 1e3) / 1e12, 2),
+                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]]}
+        log(f"[bench] mixed: {out['mixed']}")
+        del gfs, mouts
 
     # ------------------------------------------------------------------ batched bboxset
     if "batched" in sections:

@@ -42,7 +42,10 @@ class WaveRK4(torch.autograd.Function):
             if t.shape != u0.shape or t.stride() != u0.stride():
                 raise ValueError("u0, rho0 and c2 must share one layout")
         ws = workspace(s4_workspace_size(box, S4_OP_RK4, S4_GRAPH), u0.device)
-        u, rho = _copy_field(u0.detach()), _copy_field(rho0.detach())
+        # outputs carry interior values only; their ghosts are zero constants
+        u, rho = _like(u0, ghost), _like(rho0, ghost)
+        interior(u, ghost).copy_(interior(u0.detach(), ghost))
+        interior(rho, ghost).copy_(interior(rho0.detach(), ghost))
         c2d = None if c2 is None else [c2.detach()]
         ckpts = []
         step = 0

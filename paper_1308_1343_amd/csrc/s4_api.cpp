@@ -95,6 +95,7 @@ static int kernel_op(int op)
     case S4_OP_RK4: return OP_STAGE;
     case S4_OP_ADJOINT_RHS: return OP_ADJRHS;
     case S4_OP_ADJOINT_STEP: return OP_ADJSTAGE;
+    case S4_OP_DERIV_MIXED: return OP_COUNT; // its own kernel, k_mixed
     default: return -1;
     }
 }
@@ -374,8 +375,8 @@ int s4_check_boxes(const s4_box *b, int nbox, int op)
     int r = check_boxes(b, nbox, op);
     if (r)
         return r;
-    if (op == S4_OP_ADJOINT_STEP && nbox != 1)
-        return fail(S4_EINVAL, "the adjoint step takes one box");
+    if ((op == S4_OP_ADJOINT_STEP || op == S4_OP_DERIV_MIXED) && nbox != 1)
+        return fail(S4_EINVAL, "op %d takes one box", op);
     return S4_OK;
 }
 
@@ -565,17 +566,71 @@ int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u, 
     return S4_OK;
 }
 
+static MixArgs mix_args(const s4_box &b, const Cand &c, const double A[9])
+{
+    MixArgs M;
+    memset(&M, 0, sizeof M);
+    M.B = devbox(b, c);
+    M.items = (int)dev_items(M.B);
+    M.a[0] = A[0];
+    M.a[1] = A[4];
+    M.a[2] = A[8];
+    M.a[3] = A[1] + A[3];
+    M.a[4] = A[2] + A[6];
+    M.a[5] = A[5] + A[7];
+    for (int a = 0; a < 3; ++a) {
+        M.d1[a] = 1.0 / (12.0 * b.dx[a]);
+        M.d2[a] = 1.0 / (12.0 * b.dx[a] * b.dx[a]);
+    }
+    return M;
+}
+
+static int launch_mixed_fields(s4_ctx *ctx, const Cand &c, MixArgs M, int nfield, const double *const *g,
+                               double *const *out, hipStream_t s)
+{
+    for (int f0 = 0; f0 < nfield; f0 += 8) {
+        const int nf = std::min(8, nfield - f0);
+        for (int k = 0; k < 8; ++k) {
+            M.f[k] = k < nf ? g[f0 + k] : nullptr;
+            M.out[k] = k < nf ? out[f0 + k] : nullptr;
+        }
+        hipError_t e = launch_mixed(c.tx, c.nw, M, nf, ctx->nxcd, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "mixed-derivative launch");
+    }
+    return S4_OK;
+}
+
 int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const *g, const double A[9],
                    double *const *out, void *stream)
 {
-    (void)ctx;
-    (void)b;
-    (void)nfield;
-    (void)g;
-    (void)A;
-    (void)out;
-    (void)stream;
-    return fail(S4_ENOTSUP, "s4_deriv_mixed: not built yet");
+    if (!ctx || !g || !out || !A)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, 1, S4_OP_DERIV_MIXED);
+    if (r)
+        return r;
+    if (nfield < 1 || nfield > (1 << 16))
+        return fail(S4_EINVAL, "nfield = %d out of range", nfield);
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(A[k]))
+            return fail(S4_EINVAL, "A[%d] is not finite", k);
+    std::vector<Range> wr, all;
+    const size_t n = (size_t)box_elems(b[0]) * 8;
+    for (int k = 0; k < nfield; ++k) {
+        if ((r = check_ptr(g[k], "g", k)) || (r = check_ptr(out[k], "out", k)))
+            return r;
+        wr.push_back({out[k], n, "out", k});
+        all.push_back({g[k], n, "g", k});
+    }
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+    const Cand &c = cands()[choose(ctx, S4_OP_DERIV_MIXED, b, 1).cand];
+    const MixArgs M = mix_args(b[0], c, A);
+    if ((int64_t)M.items * 8 > 0x7fffffff)
+        return fail(S4_EINVAL, "too many work items");
+    return launch_mixed_fields(ctx, c, M, nfield, g, out, (hipStream_t)stream);
 }
 
 // RK4 stage tables for all boxes: stage s reads u_s (stencil) and writes the
@@ -968,7 +1023,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     }
     DevBox *dtab = (DevBox *)((char *)scratch + off);
     int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
-    const bool batched = nbox > 1;
+    const bool batched = nbox > 1 && kop != OP_COUNT;
     StageCoef K{};
     K.stage = 2;
     K.a = K.b = K.b_next = K.a_next = 1e-3;
@@ -1010,6 +1065,13 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
                 break;
         }
         auto run = [&]() -> int {
+            if (kop == OP_COUNT) {
+                const double A[9] = {1, 0.5, 0.25, 0.5, 1, 0.5, 0.25, 0.5, 1};
+                MixArgs M = mix_args(b[0], c, A);
+                const double *gin[1] = {F[0][0]};
+                double *gout[1] = {F[0][9]};
+                return launch_mixed_fields(ctx, c, M, 1, gin, gout, s);
+            }
             if (batched) {
                 hipError_t e = launch_tiles_batched(kop, c.tx, c.nw, dtab, nbox, (int)nitems, counters,
                                                     persistent_grid(ctx, kop, c, nitems), K, s);

@@ -53,6 +53,19 @@ struct DevBox {
     double *q[5];          // op outputs (pointwise)
 };
 
+// Arguments of one multi-field mixed-derivative launch (fields share B's
+// layout; work item lin covers field lin / items, tile lin % items).
+struct MixArgs {
+    DevBox B;
+    const double *f[8];
+    double *out[8];
+    double a[6];  // A_xx, A_yy, A_zz, A_xy + A_yx, A_xz + A_zx, A_yz + A_zy
+    double d1[3]; // 1 / (12 h_a)
+    double d2[3]; // 1 / (12 h_a^2)
+    int32_t nfield;
+    int32_t items;
+};
+
 // Scalars of one stage launch.
 struct StageCoef {
     int stage;      // 1..4

@@ -235,6 +235,97 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restr
 }
 
 // ---------------------------------------------------------------------------
+// multi-field mixed-derivative kernel:
+//   out = sum_a D2_a f + sum_{a<b} D_ab f + sum_{a,b} A_ab (D1_a f)(D1_b f)
+// D_ab is the tensor product of two D1 stencils, evaluated factored: D_xy as
+// D1_y of the D1_x plane (second LDS plane), D_xz and D_yz as D1_z of the
+// register queues of D1_x f and D1_y f.  The LDS plane is the one being
+// loaded (the leading plane k+2); its in-plane terms are computed on arrival
+// and queued until plane k is complete.  Ghost zones (edges included) are
+// read.
+
+template <int TX, int NW>
+__global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
+{
+    using T = Tile<TX, NW>;
+    using MT = MixTile<TX, NW>;
+    constexpr int LX = MT::LX;
+    __shared__ double sf[2 * MT::PF];
+    __shared__ double sd[2 * MT::PD];
+    const int lin = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const int field = lin / M.items;
+    const int item = lin - field * M.items;
+    const DevBox &B = M.B;
+    const ItemPos P = item_pos(B, item, TX, T::TY);
+    const MixWalker<TX, NW> w(B, P, threadIdx.x);
+    const double *__restrict__ f = M.f[field];
+    double *__restrict__ out = M.out[field];
+    const double d1x = M.d1[0], d1y = M.d1[1], d1z = M.d1[2];
+    const double d2x = M.d2[0], d2y = M.d2[1], d2z = M.d2[2];
+
+    double fq0 = 0, fq1 = 0, fq2 = 0, fq3 = 0, fq4 = 0; // f at planes kk-4 .. kk
+    double xq0 = 0, xq1 = 0, xq2 = 0, xq3 = 0, xq4 = 0; // D1_x f
+    double yq0 = 0, yq1 = 0, yq2 = 0, yq3 = 0, yq4 = 0; // D1_y f
+    double pq0 = 0, pq1 = 0, pq2 = 0;                   // D2_x + D2_y + D_xy at kk-2 .. kk
+    int buf = 0;
+    for (int kk = P.z0 - 2; kk <= P.z1 + 1; ++kk) {
+        const int64_t zo = w.zoff(kk);
+        const double fv = f[w.col + zo];
+        double hv[MT::HS];
+#pragma unroll
+        for (int s = 0; s < MT::HS; ++s)
+            if (w.hl[s] >= 0)
+                hv[s] = f[w.hcol[s] + zo];
+        double *F = sf + buf * MT::PF;
+        double *D = sd + buf * MT::PD;
+        F[w.lf] = fv;
+#pragma unroll
+        for (int s = 0; s < MT::HS; ++s)
+            if (w.hl[s] >= 0)
+                F[w.hl[s]] = hv[s];
+        __syncthreads();
+        const int c = w.lf;
+        const double xm2 = F[c - 2], xm1 = F[c - 1], xp1 = F[c + 1], xp2 = F[c + 2];
+        const double ym2 = F[c - 2 * LX], ym1 = F[c - LX], yp1 = F[c + LX], yp2 = F[c + 2 * LX];
+        const double gx = d1x * fma(8.0, xp1 - xm1, -(xp2 - xm2));
+        const double gy = d1y * fma(8.0, yp1 - ym1, -(yp2 - ym2));
+        const double sx = fma(16.0, xm1 + xp1, -(xm2 + xp2));
+        const double sy = fma(16.0, ym1 + yp1, -(ym2 + yp2));
+        D[w.ld] = gx;
+#pragma unroll
+        for (int s = 0; s < MT::DS; ++s)
+            if (w.dlf[s] >= 0) {
+                const int e = w.dlf[s];
+                D[w.dld[s]] = d1x * fma(8.0, F[e + 1] - F[e - 1], -(F[e + 2] - F[e - 2]));
+            }
+        __syncthreads();
+        const int dd = w.ld;
+        const double gxy = d1y * fma(8.0, D[dd + TX] - D[dd - TX], -(D[dd + 2 * TX] - D[dd - 2 * TX]));
+        const double pin = fma(d2x, fma(-30.0, fv, sx), fma(d2y, fma(-30.0, fv, sy), gxy));
+        fq0 = fq1; fq1 = fq2; fq2 = fq3; fq3 = fq4; fq4 = fv;
+        xq0 = xq1; xq1 = xq2; xq2 = xq3; xq3 = xq4; xq4 = gx;
+        yq0 = yq1; yq1 = yq2; yq2 = yq3; yq3 = yq4; yq4 = gy;
+        pq0 = pq1; pq1 = pq2; pq2 = pin;
+        if (kk >= P.z0 + 2 && w.active) {
+            const double gz = d1z * fma(8.0, fq3 - fq1, -(fq4 - fq0));
+            const double d2zv = d2z * fma(-30.0, fq2, fma(16.0, fq1 + fq3, -(fq0 + fq4)));
+            const double gxz = d1z * fma(8.0, xq3 - xq1, -(xq4 - xq0));
+            const double gyz = d1z * fma(8.0, yq3 - yq1, -(yq4 - yq0));
+            const double ex = xq2, ey = yq2;
+            double q = M.a[0] * ex * ex;
+            q = fma(M.a[1] * ey, ey, q);
+            q = fma(M.a[2] * gz, gz, q);
+            q = fma(M.a[3] * ex, ey, q);
+            q = fma(M.a[4] * ex, gz, q);
+            q = fma(M.a[5] * ey, gz, q);
+            const double lin2 = pq0 + d2zv + gxz + gyz;
+            st(out + w.point(B, kk - 2), lin2 + q);
+        }
+        buf ^= 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // periodic ghost fill: every ghost point copies the interior point at its
 // wrapped coordinates.  One thread per ghost point; the ghost shell of a box
 // is enumerated as two z slabs (full x, y extent), two y slabs (full x
@@ -342,6 +433,21 @@ int max_blocks_per_cu(int op, int tx, int nw)
     S4_FOR_SHAPES(X)
 #undef X
     return 0;
+}
+
+hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, hipStream_t s)
+{
+    const int64_t grid = (int64_t)M.items * nfield;
+    if (grid <= 0 || grid > 0x7fffffff)
+        return hipErrorInvalidValue;
+#define X(TX_, NW_)                                                                                    \
+    if (tx == TX_ && nw == NW_) {                                                                      \
+        hipLaunchKernelGGL((k_mixed<TX_, NW_>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, M, nxcd);  \
+        return hipGetLastError();                                                                      \
+    }
+    X(64, 4) X(64, 8) X(32, 4) X(32, 8) X(16, 4) X(16, 8)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fill(const DevBox &B, hipStream_t s)

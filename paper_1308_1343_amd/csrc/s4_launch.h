@@ -21,6 +21,10 @@ hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int n
 // Resident workgroups per CU of the batched kernel for this shape (0 if unknown).
 int max_blocks_per_cu(int op, int tx, int nw);
 
+// Multi-field mixed-derivative kernel over fields [0, nfield) of M (nfield <= 8);
+// one workgroup per (field, tile) item.
+hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, hipStream_t s);
+
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 

@@ -149,6 +149,100 @@ static void run(int nx, int ny, int nz, int g, int padx, int pady, int tz_req)
             }
 }
 
+// the mixed-derivative traversal (ghost addressing, leading-plane LDS with
+// corners, second LDS plane of D1_x on the tile rows and the halo rows)
+template <int TX, int NW>
+static void run_mixed(int nx, int ny, int nz, int g, int padx, int tz_req)
+{
+    using T = Tile<TX, NW>;
+    using M = MixTile<TX, NW>;
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.g = g;
+    B.sy = nx + 2 * g + padx;
+    B.sz = B.sy * (ny + 2 * g);
+    B.tz = tz_req > 0 && tz_req < nz ? tz_req : nz;
+    B.tiles[0] = (nx + TX - 1) / TX;
+    B.tiles[1] = (ny + T::TY - 1) / T::TY;
+    B.tiles[2] = (nz + B.tz - 1) / B.tz;
+    const int64_t total = B.sz * (nz + 2 * g);
+    std::vector<int> written(total, 0);
+    const int nitems = B.tiles[0] * B.tiles[1] * B.tiles[2];
+    std::vector<int64_t> F(M::PF), D(M::PD);
+    for (int item = 0; item < nitems; ++item) {
+        const ItemPos P = item_pos(B, item, TX, T::TY);
+        std::vector<MixWalker<TX, NW>> W;
+        for (int t = 0; t < T::NT; ++t)
+            W.emplace_back(B, P, t);
+        for (int kk = P.z0 - 2; kk <= P.z1 + 1; ++kk) {
+            std::fill(F.begin(), F.end(), -1);
+            std::fill(D.begin(), D.end(), -1);
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                const int64_t e = w.col + w.zoff(kk);
+                CHECK(e >= 0 && e < total, "mixed own read out of range");
+                CHECK(F[w.lf] == -1 || F[w.lf] == e, "mixed own LDS conflict");
+                F[w.lf] = e;
+                for (int s = 0; s < M::HS; ++s) {
+                    if (w.hl[s] < 0)
+                        continue;
+                    const int64_t h = w.hcol[s] + w.zoff(kk);
+                    CHECK(h >= 0 && h < total, "mixed halo read out of range");
+                    CHECK(w.hl[s] >= 0 && w.hl[s] < M::PF, "mixed halo slot out of range");
+                    CHECK(F[w.hl[s]] == -1 || F[w.hl[s]] == h, "mixed halo LDS conflict");
+                    F[w.hl[s]] = h;
+                }
+            }
+            // D1_x points: valid when all four x taps hold the x neighbours of the centre
+            auto d1x_tag = [&](int e) -> int64_t {
+                for (int d = -2; d <= 2; ++d)
+                    if (e + d < 0 || e + d >= M::PF || F[e + d] < 0)
+                        return -2;
+                for (int d = -2; d <= 2; ++d)
+                    if (d != 0 && F[e + d] != F[e] + d)
+                        return -2;
+                return F[e];
+            };
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                CHECK(w.ld >= 0 && w.ld < M::PD, "D slot out of range");
+                D[w.ld] = d1x_tag(w.lf);
+                for (int s = 0; s < M::DS; ++s)
+                    if (w.dlf[s] >= 0) {
+                        CHECK(w.dld[s] >= 0 && w.dld[s] < M::PD, "D halo slot out of range");
+                        CHECK(D[w.dld[s]] == -1, "D halo slot written twice");
+                        D[w.dld[s]] = d1x_tag(w.dlf[s]);
+                    }
+            }
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                if (!w.active)
+                    continue;
+                const int i = w.i, j = w.j;
+                for (int d = -2; d <= 2; ++d) {
+                    CHECK(F[w.lf + d] == elem(B, i + d, j, kk), "mixed x tap");
+                    CHECK(F[w.lf + d * M::LX] == elem(B, i, j + d, kk), "mixed y tap");
+                    CHECK(D[w.ld + d * TX] == elem(B, i, j + d, kk), "D1_x at row %d of (%d,%d,%d)", d, i, j, kk);
+                }
+                if (kk >= P.z0 + 2) {
+                    const int64_t c = w.point(B, kk - 2);
+                    CHECK(c == elem(B, i, j, kk - 2), "mixed store offset");
+                    written[c]++;
+                }
+            }
+        }
+    }
+    for (int k = -g; k < nz + g; ++k)
+        for (int j = -g; j < ny + g; ++j)
+            for (int i = -g; i < nx + g; ++i) {
+                const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+                CHECK(written[elem(B, i, j, k)] == (in ? 1 : 0), "mixed point (%d,%d,%d) stored %d times", i, j, k,
+                      written[elem(B, i, j, k)]);
+            }
+}
+
 // the ghost-fill enumeration: every ghost point of the shell exactly once,
 // never an interior point, and every source an interior point
 static void ghost_shell(int nx, int ny, int nz, int g)
@@ -198,6 +292,7 @@ static void shapes()
     for (auto &s : S) {
         run<TX, NW, false>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
         run<TX, NW, true>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
+        run_mixed<TX, NW>(s[0], s[1], s[2], s[3], s[4], s[6]);
     }
 }
 

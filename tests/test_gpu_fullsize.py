@@ -1,0 +1,88 @@
+"""Full-size workloads, in the launch configuration the benchmark times:
+256^3 wave RK4 for all 100 steps against the oracle, the pure-mode closed
+form at 256^3, and the 60-box bboxset step in all three launch modes."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1308_1343_amd as S
+import workload as W
+from _gpu import host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return S.Context(0)
+
+
+def to_dev(a, n, g, fill=0.0):
+    t = S.alloc_field(n, g, fill=fill)
+    S.interior(t, g).copy_(torch.from_numpy(a))
+    return t
+
+
+def test_wave256_rk4_100_steps_vs_oracle(ctx):
+    d = W.wave256()
+    g, n = d["ghost"], d["n"]
+    u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
+    b = S.box_of(u, g, d["dx"])
+    S.s4_rk4(ctx, b, [u], [r], None, d["dt"], d["nsteps"], "graph")
+    wu, wr = O.rk4(O.embed(d["u"], g), O.embed(d["rho"], g), g, d["dx"], d["dt"], d["nsteps"])
+    assert rel(host(u), wu, g) <= 1e-12
+    assert rel(host(r), wr, g) <= 1e-12
+
+
+def test_wave256_pure_mode_closed_form(ctx):
+    """u0 = sin(2 pi x) sin(2 pi y) sin(2 pi z), rho0 = 0: after N steps
+    (u, rho) = P^N (1, 0) S with P the RK4 polynomial of dt [[0, 1], [lam, 0]]
+    and lam the discrete symbol of the 4th-order Laplacian."""
+    n, g, N = 256, 2, 100
+    h = 1.0 / n
+    dt = 0.25 * h
+    th = 2 * math.pi * h
+    lam = 3 * (-2 * math.cos(2 * th) + 32 * math.cos(th) - 30) / (12 * h * h)
+    Z = dt * np.array([[0.0, 1.0], [lam, 0.0]])
+    P = np.eye(2)
+    T = np.eye(2)
+    for k in range(1, 5):
+        T = T @ Z / k
+        P = P + T
+    PN = np.linalg.matrix_power(P, N)
+    Smode = W.sine_mode_111(n)
+    u = to_dev(Smode, (n, n, n), g)
+    r = to_dev(np.zeros_like(Smode), (n, n, n), g)
+    b = S.box_of(u, g, h)
+    S.s4_rk4(ctx, b, [u], [r], None, dt, N, "graph")
+    su = S.interior(u, g).cpu().numpy()
+    sr = S.interior(r, g).cpu().numpy()
+    assert np.max(np.abs(su - PN[0, 0] * Smode)) <= 1e-12
+    assert np.max(np.abs(sr - PN[1, 0] * Smode)) <= 1e-12 * math.sqrt(-lam)
+
+
+def test_bboxset60_step_all_modes_vs_oracle(ctx):
+    d = W.bboxset()
+    g = d["ghost"]
+    res = {}
+    for mode in ("perbox", "batched", "graph"):
+        us, rs, bs = [], [], []
+        for i, bx in enumerate(d["boxes"]):
+            u, r = to_dev(d["u"][i], bx["n"], g), to_dev(d["rho"][i], bx["n"], g)
+            us.append(u)
+            rs.append(r)
+            bs.append(S.box_of(u, g, bx["dx"], bx["level"]))
+        S.s4_rk4(ctx, bs, us, rs, None, d["dt"], 1, mode)
+        res[mode] = ([S.interior(u, g).cpu().numpy() for u in us], [S.interior(r, g).cpu().numpy() for r in rs])
+    for mode in ("batched", "graph"):
+        for a, b in zip(res[mode][0] + res[mode][1], res["perbox"][0] + res["perbox"][1]):
+            np.testing.assert_array_equal(a, b)
+    for i, bx in enumerate(d["boxes"]):
+        wu, wr = O.rk4(O.embed(d["u"][i], g), O.embed(d["rho"][i], g), g, bx["dx"], d["dt"], 1)
+        wi = wu[g:-g, g:-g, g:-g]
+        ri = wr[g:-g, g:-g, g:-g]
+        assert np.max(np.abs(res["graph"][0][i] - wi)) <= 1e-12 * np.max(np.abs(wi))
+        assert np.max(np.abs(res["graph"][1][i] - ri)) <= 1e-12 * np.max(np.abs(ri))

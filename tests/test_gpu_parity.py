@@ -260,3 +260,63 @@ def test_errors_on_device_calls(ctx):
     with pytest.raises(S.Sten4Error) as e:
         S.s4_rk4(ctx, b, [u], [r], None, -0.01, 1, "perbox")
     assert e.value.code == S.S4_EINVAL
+
+
+# --------------------------------------------------------------------------- multi-field kernel
+
+@pytest.mark.parametrize("n,g", [((20, 17, 13), 2), ((33, 9, 12), 3), ((8, 40, 6), 2), ((70, 5, 4), 2)])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_mixed_parity(ctx, n, g, symmetric):
+    dx = (1.0 / n[0], 1.3 / n[1], 0.9 / n[2])
+    fs = [O.fill_ghosts_periodic(rand_box(n, g, 6, k), g) for k in range(3)]
+    A = W.random_symmetric3(6, 9)
+    if not symmetric:
+        A[0, 1] += 0.3
+        A[2, 0] -= 0.2
+    gd = [dev_full(f, g) for f in fs]
+    outs = [S.alloc_field(n, g, fill=NAN) for _ in fs]
+    b = S.box_of(gd[0], g, dx)
+    S.s4_deriv_mixed(ctx, b, gd, A, outs)
+    for k, f in enumerate(fs):
+        got = host(outs[k])
+        want = O.deriv_mixed(f, g, dx, A)
+        assert rel(got, want, g) <= TOL, k
+        assert ghosts_untouched(got, g)
+
+
+def test_mixed_candidates_bitwise_and_many_fields(ctx):
+    n, g = (40, 24, 20), 2
+    dx = (0.025, 0.04, 0.05)
+    fs = [O.fill_ghosts_periodic(rand_box(n, g, 7, k), g) for k in range(10)]  # > 8: two launches
+    A = W.random_symmetric3(7, 99)
+    gd = [dev_full(f, g) for f in fs]
+    b = S.box_of(gd[0], g, dx)
+    ref = None
+    nc = S.s4_get_choice(ctx, S.S4_OP_DERIV_MIXED, b)["ncandidates"]
+    for cand in list(range(0, nc, 3)) + [nc - 1]:
+        S.s4_set_choice(ctx, S.S4_OP_DERIV_MIXED, b, cand)
+        outs = [S.alloc_field(n, g, fill=NAN) for _ in fs]
+        S.s4_deriv_mixed(ctx, b, gd, A, outs)
+        got = [host(o) for o in outs]
+        if ref is None:
+            ref = got
+            for k, f in enumerate(fs):
+                assert rel(got[k], O.deriv_mixed(f, g, dx, A), g) <= TOL
+        for a, r in zip(got, ref):
+            np.testing.assert_array_equal(a, r, err_msg=f"candidate {cand}")
+    S.s4_set_choice(ctx, S.S4_OP_DERIV_MIXED, b, -1)
+
+
+def test_mixed192_full_size(ctx):
+    """The 6-field workload at its full size (192^3 + 2 ghosts, sine-mode fields)."""
+    d = W.mixed_fields()
+    g = d["ghost"]
+    fs = [O.fill_ghosts_periodic(O.embed(f, g), g) for f in d["fields"]]
+    gd = [dev_full(f, g) for f in fs]
+    outs = [S.alloc_field(d["n"], g, fill=NAN) for _ in fs]
+    b = S.box_of(gd[0], g, d["dx"])
+    S.s4_deriv_mixed(ctx, b, gd, d["A"], outs)
+    for k, f in enumerate(fs):
+        got = host(outs[k])
+        assert rel(got, O.deriv_mixed(f, g, d["dx"], d["A"]), g) <= TOL, k
+        assert ghosts_untouched(got, g)
