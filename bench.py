@@ -125,7 +125,7 @@ def main():
     log(f"[bench] rk4 256^3: {K} steps in {wall * 1e3:.2f} ms wall, {ev_ms:.2f} ms events, finite={finite}")
     value = npts * K / wall / 1e9
     # dominant kernel: the fused stage kernel, 4 launches per step, nothing else in the timed region
-    stage_bytes = [6, 10, 10, 6]  # 8-byte accesses per point: reads + writes of stages 1..4
+    stage_bytes = [4, 8, 10, 6]  # 8-byte accesses per point: reads + writes of stages 1..4
     bytes_per_launch = npts * 8 * sum(stage_bytes) / 4
     launch_s = ev_ms / 1e3 / (4 * K)
     achieved = bytes_per_launch / launch_s / 1e9

@@ -191,9 +191,22 @@ static size_t round256(size_t x)
     return (x + 255) & ~(size_t)255;
 }
 
+// Workspace fields copy the box's strides.  Each starts `field_shift` bytes
+// past a 256-byte boundary so that its interior rows start on 128-byte lines
+// whenever the strides are multiples of 16 elements (the padded layout).
+static size_t field_shift(const s4_box &b)
+{
+    return (size_t)((16 - b.ghost % 16) % 16) * sizeof(double);
+}
+
 static size_t field_bytes(const s4_box &b)
 {
-    return round256((size_t)box_elems(b) * sizeof(double));
+    return round256((size_t)box_elems(b) * sizeof(double) + field_shift(b));
+}
+
+static double *ws_field(char *base, const s4_box &b)
+{
+    return (double *)(base + field_shift(b));
 }
 
 static int check_box(const s4_box &b, int i, int op)
@@ -645,7 +658,7 @@ static void rk4_tables(const s4_box *b, int nbox, double *const *u, double *cons
         const size_t fb = field_bytes(b[i]);
         double *F[RK4_FIELDS];
         for (int k = 0; k < RK4_FIELDS; ++k)
-            F[k] = (double *)(ws + off + k * fb);
+            F[k] = ws_field(ws + off + k * fb, b[i]);
         off += RK4_FIELDS * fb;
         double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3], *AU = F[4], *AR = F[5];
         const double *in_[4] = {u[i], Ua, Ub, Ua};
@@ -910,7 +923,7 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
     char *ws = (char *)workspace;
     double *F[ADJ_FIELDS];
     for (int k = 0; k < ADJ_FIELDS; ++k)
-        F[k] = (double *)(ws + k * fb);
+        F[k] = ws_field(ws + k * fb, b[0]);
     double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3];
     double *LU[4] = {F[4], F[5], F[6], F[7]};
     double *KBU = F[8], *KBa = F[9], *KBb = F[10], *ACU = F[11], *ACR = F[12];
@@ -1018,14 +1031,14 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     for (int i = 0; i < nbox; ++i) {
         const size_t fb = field_bytes(b[i]);
         for (int k = 0; k < TUNE_FIELDS; ++k)
-            F[i].push_back((double *)((char *)scratch + off + k * fb));
+            F[i].push_back(ws_field((char *)scratch + off + k * fb, b[i]));
         off += TUNE_FIELDS * fb;
     }
     DevBox *dtab = (DevBox *)((char *)scratch + off);
     int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
     const bool batched = nbox > 1 && kop != OP_COUNT;
     StageCoef K{};
-    K.stage = 2;
+    K.stage = 3; // the stage that moves the most bytes
     K.a = K.b = K.b_next = K.a_next = 1e-3;
     K.scale = 1.0;
 

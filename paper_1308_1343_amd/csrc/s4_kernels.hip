@@ -39,54 +39,107 @@ __device__ __forceinline__ void st(double *p, double v)
     __builtin_nontemporal_store(v, p);
 }
 
+// load of a stream read only at the point itself: non-temporal, so it does
+// not evict the stencil input's planes that neighbouring tiles still read
+__device__ __forceinline__ double ldp(const double *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 // ---------------------------------------------------------------------------
-// pointwise epilogues.  c: element offset of the interior point; center: the
-// stencil input there (after the input transform); raw: scale * in[c];
-// lap: L of the transformed input.
+// pointwise epilogues, split in two so the loads of plane k+1 can be issued
+// before plane k is computed.  pw_load reads the streams an op needs at the
+// point c; pw_apply combines them with the stencil result and stores.
+// center: the stencil input at the point (after the input transform);
+// raw: scale * in[c]; lap: L of the transformed input.
+
+struct PW {
+    double v[6];
+};
 
 template <int OPK>
-__device__ __forceinline__ void epilogue(const DevBox &B, const StageCoef &K, int64_t c,
-                                         double center, double raw, double lap)
+__device__ __forceinline__ void pw_load(const DevBox &B, const StageCoef &K, int64_t c, PW &w)
+{
+    if constexpr (OPK == OP_RHS) {
+        w.v[0] = B.p[0] ? ldp(B.p[0] + c) : 1.0; // c^2
+    } else if constexpr (OPK == OP_STAGE) {
+        w.v[0] = B.p[5] ? ldp(B.p[5] + c) : 1.0; // c^2
+        w.v[1] = ldp(B.p[0] + c);                // rho_s
+        if (K.stage == 2 || K.stage == 3) {
+            w.v[2] = ldp(B.p[1] + c); // u_n
+            w.v[3] = ldp(B.p[2] + c); // rho_n
+        }
+        if (K.stage >= 3) {
+            w.v[4] = ldp(B.p[3] + c); // acc_u
+            w.v[5] = ldp(B.p[4] + c); // acc_rho
+        }
+    } else if constexpr (OPK == OP_ADJRHS) {
+        w.v[0] = ldp(B.p[0] + c); // lu
+    } else if constexpr (OPK == OP_FWDREC) {
+        if (K.stage < 4) {
+            w.v[0] = B.p[5] ? ldp(B.p[5] + c) : 1.0; // c^2
+            w.v[1] = ldp(B.p[0] + c);                // rho_s
+            if (K.stage > 1) {
+                w.v[2] = ldp(B.p[1] + c); // u_n
+                w.v[3] = ldp(B.p[2] + c); // rho_n
+            }
+        }
+    } else if constexpr (OPK == OP_ADJSTAGE) {
+        w.v[0] = ldp(B.p[1] + c); // lam_u (ybar)
+        w.v[1] = ldp(B.p[2] + c); // lam_rho
+        if (K.stage < 4) {
+            w.v[2] = ldp(B.p[0] + c); // kb_u
+            w.v[3] = ldp(B.p[3] + c); // acc_u
+            w.v[4] = ldp(B.p[4] + c); // acc_rho
+        }
+        w.v[5] = B.q[4] ? ldp(B.p[5] + c) : 0.0; // L u_s
+    }
+}
+
+template <int OPK>
+__device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, int64_t c, double center,
+                                         double raw, double lap, const PW &w)
 {
     if constexpr (OPK == OP_RHS) {
         // rho_t = c^2 L u   (c2 optional)
-        const double *c2 = B.p[0];
-        st(B.q[0] + c, c2 ? c2[c] * lap : lap);
+        st(B.q[0] + c, B.p[0] ? w.v[0] * lap : lap);
     } else if constexpr (OPK == OP_STAGE) {
-        // k_s = (rho_s, c^2 L u_s); next stage input and the running sum
-        const double *c2 = B.p[5];
-        const double kr = c2 ? c2[c] * lap : lap;
-        const double ku = B.p[0][c];
-        if (K.stage == 1) { // y_s = y_n: u_n is the centre value
+        // k_s = (rho_s, c^2 L u_s).  Stage s writes the next stage input
+        // y_n + a_s dt k_s; the running sum acc = y_n + dt sum_r b_r k_r is
+        // first formed in stage 2 from y_2 = y_n + dt/2 k1 (so dt/6 k1 is
+        // (y_2 - y_n)/3), which saves stage 1 writing it and stage 2 reading it.
+        const double kr = B.p[5] ? w.v[0] * lap : lap;
+        const double ku = w.v[1];
+        if (K.stage == 1) { // y_s = y_n: u_n is the centre value, rho_n = rho_s
             st(B.q[0] + c, fma(K.a, ku, center));
             st(B.q[1] + c, fma(K.a, kr, ku));
-            st(B.q[2] + c, fma(K.b, ku, center));
-            st(B.q[3] + c, fma(K.b, kr, ku));
-        } else if (K.stage < 4) {
-            const double un = B.p[1][c], rn = B.p[2][c];
-            const double au = B.p[3][c], ar = B.p[4][c];
+        } else if (K.stage == 2) { // centre = u_2, ku = rho_2
+            const double un = w.v[2], rn = w.v[3];
             st(B.q[0] + c, fma(K.a, ku, un));
             st(B.q[1] + c, fma(K.a, kr, rn));
-            st(B.q[2] + c, fma(K.b, ku, au));
-            st(B.q[3] + c, fma(K.b, kr, ar));
+            st(B.q[2] + c, fma(K.b, ku, fma(1.0 / 3.0, center - un, un)));
+            st(B.q[3] + c, fma(K.b, kr, fma(1.0 / 3.0, ku - rn, rn)));
+        } else if (K.stage == 3) {
+            st(B.q[0] + c, fma(K.a, ku, w.v[2]));
+            st(B.q[1] + c, fma(K.a, kr, w.v[3]));
+            st(B.q[2] + c, fma(K.b, ku, w.v[4]));
+            st(B.q[3] + c, fma(K.b, kr, w.v[5]));
         } else { // y_{n+1} = acc + dt/6 k4
-            const double au = B.p[3][c], ar = B.p[4][c];
-            st(B.q[0] + c, fma(K.b, ku, au));
-            st(B.q[1] + c, fma(K.b, kr, ar));
+            st(B.q[0] + c, fma(K.b, ku, w.v[4]));
+            st(B.q[1] + c, fma(K.b, kr, w.v[5]));
         }
     } else if constexpr (OPK == OP_ADJRHS) {
         // F^T(lu, lrho) = (L(c^2 lrho), lu)
         st(B.q[0] + c, lap);
-        st(B.q[1] + c, B.p[0][c]);
+        st(B.q[1] + c, w.v[0]);
     } else if constexpr (OPK == OP_FWDREC) {
         // forward stage recompute: store L u_s; next stage input (u, rho)
-        const double *c2 = B.p[5];
         st(B.q[2] + c, lap);
         if (K.stage < 4) {
-            const double kr = c2 ? c2[c] * lap : lap;
-            const double ku = B.p[0][c];
-            const double un = K.stage == 1 ? center : B.p[1][c];
-            const double rn = K.stage == 1 ? ku : B.p[2][c];
+            const double kr = B.p[5] ? w.v[0] * lap : lap;
+            const double ku = w.v[1];
+            const double un = K.stage == 1 ? center : w.v[2];
+            const double rn = K.stage == 1 ? ku : w.v[3];
             st(B.q[0] + c, fma(K.a, ku, un));
             st(B.q[1] + c, fma(K.a, kr, rn));
         }
@@ -95,17 +148,15 @@ __device__ __forceinline__ void epilogue(const DevBox &B, const StageCoef &K, in
         // c2bar += kb_rho * L u_s; acc += yb_s;
         // kb_{s-1} = dt c_{s-1} ybar + dt a_{s-1} yb_s   (s > 1)
         // ybar_n = ybar + acc                              (s == 1)
-        const double lu = B.p[1][c], lr = B.p[2][c];
-        const double kbu = K.stage == 4 ? K.scale * lu : B.p[0][c];
+        const double lu = w.v[0], lr = w.v[1];
+        const double kbu = K.stage == 4 ? K.scale * lu : w.v[2];
         const double ybu = lap, ybr = kbu;
-        if (B.q[4]) {
-            const double cb = B.p[6][c];
-            B.q[4][c] = fma(raw, B.p[5][c], cb);
-        }
+        if (B.q[4])
+            st(B.q[4] + c, fma(raw, w.v[5], ldp(B.p[6] + c)));
         double accu = ybu, accr = ybr;
         if (K.stage < 4) {
-            accu = B.p[3][c] + ybu;
-            accr = B.p[4][c] + ybr;
+            accu = w.v[3] + ybu;
+            accr = w.v[4] + ybr;
         }
         if (K.stage > 1) {
             st(B.q[0] + c, fma(K.a_next, ybu, K.b_next * lu));
@@ -113,14 +164,17 @@ __device__ __forceinline__ void epilogue(const DevBox &B, const StageCoef &K, in
             st(B.q[2] + c, accu);
             st(B.q[3] + c, accr);
         } else {
-            B.q[0][c] = lu + accu;
-            B.q[1][c] = lr + accr;
+            st(B.q[0] + c, lu + accu);
+            st(B.q[1] + c, lr + accr);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// one work item: an xy tile marched over its z chunk
+// one work item: an xy tile marched over its z chunk.  Software pipelined:
+// right after the barrier of plane k the loads of plane k+1 (the column's
+// next z value, the halo, the pointwise streams) are issued, so they are in
+// flight while plane k is computed and stored.
 
 template <int TX, int NW, bool WRAP, int OPK>
 __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, const StageCoef &K,
@@ -150,34 +204,57 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
     double q1 = ldw(w.col + w.zoff(P.z0 - 1), rd);
     double q2 = ldw(w.col + w.zoff(P.z0), r2);
     double q3 = ldw(w.col + w.zoff(P.z0 + 1), r3);
-    int buf = 0;
-    for (int k = P.z0; k < P.z1; ++k) {
-        const double q4 = ldw(w.col + w.zoff(k + 2), r4);
-        const int64_t zo = w.zoff(k);
-        double hvv[T::HS];
+    double q4 = ldw(w.col + w.zoff(P.z0 + 2), r4);
+    double hv[T::HS];
+    {
+        const int64_t zo = w.zoff(P.z0);
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
-                hvv[s] = ldw(w.hcol[s] + zo, rd);
+                hv[s] = ldw(w.hcol[s] + zo, rd);
+    }
+    PW pw;
+    if (w.active)
+        pw_load<OPK>(B, K, w.point(B, P.z0), pw);
+    int buf = 0;
+    for (int k = P.z0; k < P.z1; ++k) {
         double *L = lds + buf * PLANE;
         L[lc] = q2;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
-                L[w.hl[s]] = hvv[s];
+                L[w.hl[s]] = hv[s];
         __syncthreads();
+        double q4n = 0.0, r4n = 0.0, hvn[T::HS];
+        PW pwn;
+        if (k + 1 < P.z1) {
+            q4n = ldw(w.col + w.zoff(k + 3), r4n);
+            const int64_t zo = w.zoff(k + 1);
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    hvn[s] = ldw(w.hcol[s] + zo, rd);
+            if (w.active)
+                pw_load<OPK>(B, K, w.point(B, k + 1), pwn);
+        }
         if (w.active) {
             const double lap = lap4(B, q2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2],
                                     L[lc - 2 * T::LX], L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX],
                                     q0, q1, q3, q4);
-            epilogue<OPK>(B, K, w.point(B, k), q2, r2, lap);
+            pw_apply<OPK>(B, K, w.point(B, k), q2, r2, lap, pw);
         }
         q0 = q1;
         q1 = q2;
         q2 = q3;
         q3 = q4;
+        q4 = q4n;
         r2 = r3;
         r3 = r4;
+        r4 = r4n;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            hv[s] = hvn[s];
+        pw = pwn;
         buf ^= 1;
     }
 }
