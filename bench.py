@@ -53,16 +53,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_key, launches_bytes):
+def traffic_from_profile(kernel_key, tile):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source with the same tile choice; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
         return None
     e = t.get(kernel_key)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash() or list(e.get("tile", [])) != list(tile):
         return None
     return e.get("bytes_per_launch")
 
@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sections", default="rk4,rhs,copy,mixed,batched,adjoint,cpu")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
+    ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -89,6 +91,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.tune_cache:
+        os.environ["S4_TUNE_CACHE"] = args.tune_cache
     ctx = S.Context(0)
     K, WU = args.steps, args.warmup
     out = {}
@@ -106,6 +110,14 @@ def main():
 
     u, rho = to_dev(d["u"]), to_dev(d["rho"])
     box = S.box_of(u, g, d["dx"])
+    tuned = {}
+    if not args.no_tune:
+        # the library's tile sweep for each loop setup timed below (run before any timing)
+        t0 = time.perf_counter()
+        for op in (S.S4_OP_RK4, S.S4_OP_WAVE_RHS):
+            S.s4_tune(ctx, op, box, flags=1)
+        tuned["wave256_s"] = round(time.perf_counter() - t0, 3)
+        torch.cuda.empty_cache()
     ws = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
     choice = S.s4_get_choice(ctx, S.S4_OP_RK4, box)
     stream = torch.cuda.current_stream()
@@ -130,7 +142,8 @@ def main():
     launch_s = ev_ms / 1e3 / (4 * K)
     achieved = bytes_per_launch / launch_s / 1e9
     kname = f"k_tiles_single<{choice['tile_x']},{choice['threads'] // 64},periodic,stage>"
-    traffic = traffic_from_profile("stage_wave256", bytes_per_launch)
+    tile_rk4 = [choice["tile_x"], choice["tile_y"], choice["z_chunk"], choice["threads"]]
+    traffic = traffic_from_profile("stage_wave256", tile_rk4)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "avg_launch_us": round(launch_s * 1e6, 2),
@@ -161,7 +174,8 @@ def main():
                       "gpoint_per_s": round(npts / (ms / 1e3) / 1e9, 1), "achieved_GBs": round(gbs, 1),
                       "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": 16,
                       "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
-                      "traffic": traffic_from_profile("rhs_wave256", npts * 16)}
+                      "traffic": traffic_from_profile("rhs_wave256", [ch["tile_x"], ch["tile_y"], ch["z_chunk"],
+                                                                      ch["threads"]])}
         log(f"[bench] rhs: {out['rhs']}")
         del us, outs
 
@@ -195,6 +209,9 @@ def main():
             S.interior(t, gm).copy_(torch.from_numpy(f))
             gfs.append(t)
         mbox = S.box_of(gfs[0], gm, md["dx"])
+        if not args.no_tune:
+            S.s4_tune(ctx, S.S4_OP_DERIV_MIXED, mbox, flags=1)
+            torch.cuda.empty_cache()
         S.s4_fill_ghosts_periodic(ctx, [mbox] * len(gfs), gfs)
         mouts = [S.alloc_field(nm, gm, fill=0.0) for _ in gfs]
         for _ in range(3):
@@ -233,6 +250,9 @@ def main():
             fields.append((fu, fr))
             boxes.append(S.box_of(fu, gb, bx["dx"], bx["level"]))
         bpts = sum(int(np.prod(bx["n"])) for bx in bd["boxes"])
+        if not args.no_tune:
+            S.s4_tune(ctx, S.S4_OP_RK4, boxes, flags=1)
+            torch.cuda.empty_cache()
         wsb = S.workspace(S.s4_workspace_size(boxes, S.S4_OP_RK4, S.S4_GRAPH))
         us_ = [f[0] for f in fields]
         rs_ = [f[1] for f in fields]
@@ -273,6 +293,11 @@ def main():
             return t
 
         u0, r0, c2, ut = compact(ad["u0"]), compact(ad["rho0"]), compact(ad["c2"], 1.0), compact(ad["u_target"])
+        if not args.no_tune:
+            abox = S.box_of(u0, ga, ad["dx"])
+            for op in (S.S4_OP_RK4, S.S4_OP_ADJOINT_STEP):
+                S.s4_tune(ctx, op, abox, flags=1)
+            torch.cuda.empty_cache()
         times = []
         for rep in range(2):
             u0.requires_grad_(True)
@@ -327,7 +352,8 @@ def main():
            "config": {"workload": "wave256_rk4: 256^3 interior + 2 ghosts, periodic, FP64, h=1/256, dt=h/4, "
                                   "u=U+Gaussian(0.1), rho=U, RK4 steps (hipGraph of 4 fused stage kernels)",
                       "points": npts, "seed": d["seed"], "tile": [choice["tile_x"], choice["tile_y"],
-                                                                   choice["z_chunk"], choice["threads"]]},
+                                                                   choice["z_chunk"], choice["threads"]],
+                      "tile_from_tuner": bool(choice["tuned"])},
            "roofline": roof, "cpu_baseline": cpu}
     rec.update(out)
     print(json.dumps(rec), flush=True)

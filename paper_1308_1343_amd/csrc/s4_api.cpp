@@ -356,7 +356,7 @@ static int upload_table(void *dst, const std::vector<char> &bytes, hipStream_t s
 
 static const int RK4_FIELDS = 6;   // Ua Ub Ra Rb AccU AccR
 static const int ADJ_FIELDS = 13;  // Ua Ub Ra Rb LU1..4 KBU KBa KBb AccU AccR
-static const int TUNE_FIELDS = 14; // enough distinct buffers for any op
+static const int TUNE_SETS = 7;    // independent buffer sets the tuner rotates through
 
 static size_t rk4_fields_bytes(const s4_box *b, int nbox)
 {
@@ -412,6 +412,20 @@ int s4_workspace_size(const s4_box *b, int nbox, int op, int mode, size_t *bytes
     return S4_OK;
 }
 
+// fields of tuning scratch per box: the buffers one timed call of the op
+// touches, in as many independent sets as the tuner rotates through
+static int tune_fields(int op)
+{
+    switch (op) {
+    case S4_OP_RK4: return 2 + RK4_FIELDS;               // u, rho + the RK4 workspace
+    case S4_OP_WAVE_RHS: return 2 * TUNE_SETS;           // (u, rho_t) per set
+    case S4_OP_ADJOINT_RHS: return 5 * 2;                // (lu, lrho, c2, out_u, out_rho) x 2 sets
+    case S4_OP_ADJOINT_STEP: return 6 + ADJ_FIELDS;      // u_n rho_n c2 lam_u lam_rho c2_bar + workspace
+    case S4_OP_DERIV_MIXED: return 2 * TUNE_SETS;        // TUNE_SETS fields in, as many out
+    default: return 0;
+    }
+}
+
 int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes)
 {
     if (!bytes)
@@ -421,7 +435,7 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes)
         return r;
     size_t t = 0;
     for (int i = 0; i < nbox; ++i)
-        t += TUNE_FIELDS * field_bytes(b[i]);
+        t += (size_t)tune_fields(op) * field_bytes(b[i]);
     *bytes = t + rk4_table_bytes(nbox);
     return S4_OK;
 }
@@ -883,51 +897,21 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
     return S4_OK;
 }
 
-int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n, const double *c2,
-                        double dt, double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
-                        size_t ws_bytes, void *stream)
+// The eight launches of one backward RK4 step: forward recompute of the
+// stage states storing L u_s, then the adjoint stages 4, 3, 2, 1.
+static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *u_n, const double *rho_n,
+                               const double *c2, double dt, double *lam_u, double *lam_rho, double *c2_bar,
+                               char *ws, hipStream_t s)
 {
-    if (!ctx)
-        return fail(S4_EINVAL, "ctx is NULL");
-    int r = check_boxes(b, 1, S4_OP_ADJOINT_STEP);
-    if (r)
-        return r;
-    if (!(std::isfinite(dt) && dt > 0.0))
-        return fail(S4_EINVAL, "dt must be finite and > 0");
-    if ((r = check_ptr(u_n, "u_n", 0)) || (r = check_ptr(rho_n, "rho_n", 0)) ||
-        (r = check_ptr(lam_u, "lam_u", 0)) || (r = check_ptr(lam_rho, "lam_rho", 0)) ||
-        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(c2_bar, "c2_bar", 0, true)))
-        return r;
-    const size_t fb = field_bytes(b[0]);
-    const size_t need = ADJ_FIELDS * fb;
-    if (!workspace)
-        return fail(S4_EINVAL, "workspace is NULL");
-    if ((uintptr_t)workspace & 255)
-        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
-    if (ws_bytes < need)
-        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
-    const size_t n = (size_t)box_elems(b[0]) * 8;
-    std::vector<Range> wr = {{lam_u, n, "lam_u", 0}, {lam_rho, n, "lam_rho", 0}, {workspace, need, "workspace", 0}};
-    if (c2_bar)
-        wr.push_back({c2_bar, n, "c2_bar", 0});
-    std::vector<Range> all = {{u_n, n, "u_n", 0}, {rho_n, n, "rho_n", 0}};
-    if (c2)
-        all.push_back({c2, n, "c2", 0});
-    for (auto &w : wr)
-        all.push_back(w);
-    if ((r = check_disjoint(wr, all)))
-        return r;
-
-    hipStream_t s = (hipStream_t)stream;
-    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_STEP, b, 1).cand];
-    char *ws = (char *)workspace;
+    int r;
+    const size_t fb = field_bytes(b);
     double *F[ADJ_FIELDS];
     for (int k = 0; k < ADJ_FIELDS; ++k)
-        F[k] = ws_field(ws + k * fb, b[0]);
+        F[k] = ws_field(ws + k * fb, b);
     double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3];
     double *LU[4] = {F[4], F[5], F[6], F[7]};
     double *KBU = F[8], *KBa = F[9], *KBb = F[10], *ACU = F[11], *ACR = F[12];
-    const DevBox D0 = devbox(b[0], c);
+    const DevBox D0 = devbox(b, c);
 
     // forward recompute of the stage states, storing L u_s
     static const double Afw[4] = {0.5, 0.5, 1.0, 0.0};
@@ -985,6 +969,46 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
     return S4_OK;
 }
 
+int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n, const double *c2,
+                        double dt, double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    int r = check_boxes(b, 1, S4_OP_ADJOINT_STEP);
+    if (r)
+        return r;
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(S4_EINVAL, "dt must be finite and > 0");
+    if ((r = check_ptr(u_n, "u_n", 0)) || (r = check_ptr(rho_n, "rho_n", 0)) ||
+        (r = check_ptr(lam_u, "lam_u", 0)) || (r = check_ptr(lam_rho, "lam_rho", 0)) ||
+        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(c2_bar, "c2_bar", 0, true)))
+        return r;
+    const size_t fb = field_bytes(b[0]);
+    const size_t need = ADJ_FIELDS * fb;
+    if (!workspace)
+        return fail(S4_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255)
+        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    const size_t n = (size_t)box_elems(b[0]) * 8;
+    std::vector<Range> wr = {{lam_u, n, "lam_u", 0}, {lam_rho, n, "lam_rho", 0}, {workspace, need, "workspace", 0}};
+    if (c2_bar)
+        wr.push_back({c2_bar, n, "c2_bar", 0});
+    std::vector<Range> all = {{u_n, n, "u_n", 0}, {rho_n, n, "rho_n", 0}};
+    if (c2)
+        all.push_back({c2, n, "c2", 0});
+    for (auto &w : wr)
+        all.push_back(w);
+    if ((r = check_disjoint(wr, all)))
+        return r;
+
+    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_STEP, b, 1).cand];
+    return adjoint_step_launch(ctx, c, b[0], u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, (char *)workspace,
+                               (hipStream_t)stream);
+}
+
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)
 {
     if (!ctx || !dst || !src)
@@ -1025,72 +1049,114 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         return fail(S4_ENOMEM, "scratch %zu bytes < %zu needed", scratch_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     S4_HIP(hipMemsetAsync(scratch, 0, need, s));
-    // distinct buffers per box: in, inmul, p[0..6], q[0..4]
+    const int nf = tune_fields(op);
     std::vector<std::vector<double *>> F(nbox);
     size_t off = 0;
     for (int i = 0; i < nbox; ++i) {
         const size_t fb = field_bytes(b[i]);
-        for (int k = 0; k < TUNE_FIELDS; ++k)
+        for (int k = 0; k < nf; ++k)
             F[i].push_back(ws_field((char *)scratch + off + k * fb, b[i]));
-        off += TUNE_FIELDS * fb;
+        off += (size_t)nf * fb;
     }
-    DevBox *dtab = (DevBox *)((char *)scratch + off);
-    int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
-    const bool batched = nbox > 1 && kop != OP_COUNT;
-    StageCoef K{};
-    K.stage = 3; // the stage that moves the most bytes
-    K.a = K.b = K.b_next = K.a_next = 1e-3;
-    K.scale = 1.0;
-
-    std::vector<int> order;
-    for (int i = 0; i < (int)cands().size(); ++i)
-        order.push_back(i);
+    char *tail = (char *)scratch + off; // box tables and counters (batched RK4)
+    const double dt = 1e-9 * std::min({b[0].dx[0], b[0].dx[1], b[0].dx[2]});
     const int reps = flags ? 15 : 5;
     hipEvent_t e0, e1;
     S4_HIP(hipEventCreate(&e0));
     S4_HIP(hipEventCreate(&e1));
     int best = -1;
     float best_t = 0;
-    for (int ci : order) {
+    for (int ci = 0; ci < (int)cands().size() && !r; ++ci) {
         const Cand &c = cands()[ci];
-        std::vector<DevBox> tab(nbox);
+        // per candidate: what one call of the op launches, on scratch buffers
+        std::vector<DevBox> tab;
         int64_t nitems = 0;
-        for (int i = 0; i < nbox; ++i) {
-            DevBox D = devbox(b[i], c);
-            D.item0 = (int)nitems;
-            nitems += dev_items(D);
-            D.in = F[i][0];
-            D.inmul = (kop == OP_ADJRHS || kop == OP_ADJSTAGE) ? F[i][1] : nullptr;
-            for (int k = 0; k < 7; ++k)
-                D.p[k] = F[i][2 + k];
-            for (int k = 0; k < 5; ++k)
-                D.q[k] = F[i][9 + k];
-            if (kop == OP_RHS || kop == OP_STAGE || kop == OP_FWDREC)
-                D.p[5] = nullptr; // c = 1 in the wave workloads
-            if (kop == OP_RHS)
-                D.p[0] = nullptr;
-            tab[i] = D;
-        }
-        if (batched) {
-            std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
-            memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
-            if ((r = upload_table(dtab, bytes, s)))
-                break;
-        }
-        auto run = [&]() -> int {
-            if (kop == OP_COUNT) {
-                const double A[9] = {1, 0.5, 0.25, 0.5, 1, 0.5, 0.25, 0.5, 1};
-                MixArgs M = mix_args(b[0], c, A);
-                const double *gin[1] = {F[0][0]};
-                double *gout[1] = {F[0][9]};
-                return launch_mixed_fields(ctx, c, M, 1, gin, gout, s);
+        DevBox *dtab = (DevBox *)tail;
+        int *counters = (int *)(tail + round256(4 * (size_t)nbox * sizeof(DevBox)));
+        const bool batched = op == S4_OP_RK4 && nbox > 1;
+        if (op == S4_OP_RK4) {
+            std::vector<double *> us(nbox), rs(nbox);
+            for (int i = 0; i < nbox; ++i) {
+                us[i] = F[i][0];
+                rs[i] = F[i][1];
+            }
+            // the RK4 workspace of box i is its fields 2..7, contiguous per box
+            std::vector<char *> wsb(nbox);
+            for (int i = 0; i < nbox; ++i)
+                wsb[i] = (char *)F[i][2] - field_shift(b[i]);
+            tab.assign(4 * (size_t)nbox, DevBox{});
+            for (int i = 0; i < nbox; ++i) {
+                std::vector<DevBox> one;
+                double *ui[1] = {us[i]}, *ri[1] = {rs[i]};
+                rk4_tables(&b[i], 1, ui, ri, nullptr, wsb[i], c, one);
+                for (int st = 0; st < 4; ++st) {
+                    one[st].item0 = (int)nitems;
+                    tab[(size_t)st * nbox + i] = one[st];
+                }
+                nitems += dev_items(one[0]);
             }
             if (batched) {
-                hipError_t e = launch_tiles_batched(kop, c.tx, c.nw, dtab, nbox, (int)nitems, counters,
-                                                    persistent_grid(ctx, kop, c, nitems), K, s);
-                return e == hipSuccess ? S4_OK : hip_fail(e, "tune launch");
+                std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
+                memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+                if ((r = upload_table(dtab, bytes, s)))
+                    break;
             }
-            return launch_one(ctx, kop, c, tab[0], K, s);
+        }
+        int rot = 0;
+        auto run = [&]() -> int {
+            const int set = rot++ % TUNE_SETS;
+            switch (op) {
+            case S4_OP_RK4:
+                return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s);
+            case S4_OP_WAVE_RHS: {
+                StageCoef K{};
+                K.scale = 1.0;
+                for (int i = 0; i < nbox; ++i) {
+                    DevBox D = devbox(b[i], c);
+                    D.in = F[i][2 * set];
+                    D.q[0] = F[i][2 * set + 1];
+                    int rr = launch_one(ctx, OP_RHS, c, D, K, s);
+                    if (rr)
+                        return rr;
+                }
+                return S4_OK;
+            }
+            case S4_OP_ADJOINT_RHS: {
+                StageCoef K{};
+                K.scale = 1.0;
+                const int o = 5 * (set % 2);
+                for (int i = 0; i < nbox; ++i) {
+                    DevBox D = devbox(b[i], c);
+                    D.in = F[i][o + 1];
+                    D.inmul = F[i][o + 2];
+                    D.p[0] = F[i][o];
+                    D.q[0] = F[i][o + 3];
+                    D.q[1] = F[i][o + 4];
+                    int rr = launch_one(ctx, OP_ADJRHS, c, D, K, s);
+                    if (rr)
+                        return rr;
+                }
+                return S4_OK;
+            }
+            case S4_OP_ADJOINT_STEP: {
+                const std::vector<double *> &G = F[0];
+                return adjoint_step_launch(ctx, c, b[0], G[0], G[1], G[2], 1.0, G[3], G[4], G[5],
+                                           (char *)G[6] - field_shift(b[0]), s);
+            }
+            case S4_OP_DERIV_MIXED: {
+                const double A[9] = {1, 0.5, 0.25, 0.5, 1, 0.5, 0.25, 0.5, 1};
+                MixArgs M = mix_args(b[0], c, A);
+                const double *gin[TUNE_SETS];
+                double *gout[TUNE_SETS];
+                for (int k = 0; k < TUNE_SETS; ++k) {
+                    gin[k] = F[0][k];
+                    gout[k] = F[0][TUNE_SETS + k];
+                }
+                return launch_mixed_fields(ctx, c, M, TUNE_SETS, gin, gout, s);
+            }
+            default:
+                return fail(S4_EINVAL, "op %d has no tunable kernel", op);
+            }
         };
         for (int w = 0; w < 2 && !r; ++w)
             r = run();
