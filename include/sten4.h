@@ -209,7 +209,9 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
 /* The tile choice the library would use for `op` on box b (or on the set):
  * out[0] variant id, out[1] tile x, out[2] tile y, out[3] z chunk,
  * out[4] threads per workgroup, out[5] 1 if it came from tuning,
- * out[6] candidate index, out[7] number of candidates. */
+ * out[6] candidate index, out[7] number of candidates this op may use on
+ * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 when the choice is
+ * the fused stage-pair kernel set of RK4. */
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
 
 /* Force a candidate (index into the op's candidate list) for this loop

@@ -62,8 +62,15 @@ static int hip_fail(hipError_t e, const char *where)
 // ---------------------------------------------------------------------------
 // tile candidates (the tuner's search space) and choices
 
+// A candidate is a kernel set and its tile (the paper's "execution
+// parameters" plus its future-work choice between sets of loop kernels,
+// Sec. III-C).  variant 0: one kernel per operation or RK4 stage, tile
+// tx x (nw*64/tx); variant 1 (RK4 on one box only): two fused stage-pair
+// kernels per step, workgroup tx x (nw*64/tx) lanes, output tile
+// (tx-4) x (nw*64/tx - 4).  tz is the z chunk (0 = whole box).
 struct Cand {
-    int tx, nw, tz; // tile x extent, wavefronts per workgroup, z chunk (0 = whole box)
+    int tx, nw, tz;
+    int variant;
 };
 
 static const std::vector<Cand> &cands()
@@ -73,19 +80,28 @@ static const std::vector<Cand> &cands()
         for (int tx : {64, 32, 16})
             for (int nw : {8, 4})
                 for (int tz : {0, 64, 32, 16, 8})
-                    c.push_back({tx, nw, tz});
+                    c.push_back({tx, nw, tz, 0});
+        for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
+            for (int tz : {64, 32, 16})
+                c.push_back({tn.first, tn.second, tz, 1});
         return c;
     }();
     return v;
 }
 
-static int cand_index(int tx, int nw, int tz)
+static int cand_index(int tx, int nw, int tz, int variant = 0)
 {
     const auto &c = cands();
     for (size_t i = 0; i < c.size(); ++i)
-        if (c[i].tx == tx && c[i].nw == nw && c[i].tz == tz)
+        if (c[i].tx == tx && c[i].nw == nw && c[i].tz == tz && c[i].variant == variant)
             return (int)i;
     return 0;
+}
+
+// whether candidate c may run op on nbox boxes
+static bool cand_allowed(const Cand &c, int op, int nbox)
+{
+    return c.variant == 0 || (op == S4_OP_RK4 && nbox == 1);
 }
 
 static int kernel_op(int op)
@@ -133,11 +149,22 @@ static int tile_ty(const Cand &c)
     return c.nw * 64 / c.tx;
 }
 
+// output tile extents in x and y
+static int out_tx(const Cand &c)
+{
+    return c.variant == 1 ? c.tx - 4 : c.tx;
+}
+
+static int out_ty(const Cand &c)
+{
+    return c.variant == 1 ? tile_ty(c) - 4 : tile_ty(c);
+}
+
 static int64_t items_of(const s4_box &b, const Cand &c)
 {
-    const int ty = tile_ty(c);
+    const int tx = out_tx(c), ty = out_ty(c);
     const int tz = c.tz > 0 ? std::min(c.tz, b.n[2]) : b.n[2];
-    return (int64_t)((b.n[0] + c.tx - 1) / c.tx) * ((b.n[1] + ty - 1) / ty) * ((b.n[2] + tz - 1) / tz);
+    return (int64_t)((b.n[0] + tx - 1) / tx) * ((b.n[1] + ty - 1) / ty) * ((b.n[2] + tz - 1) / tz);
 }
 
 // LoopControl-style initial parameters: the widest x tile the boxes fill,
@@ -310,9 +337,9 @@ static DevBox devbox(const s4_box &b, const Cand &c)
     D.cy = 1.0 / (12.0 * b.dx[1] * b.dx[1]);
     D.cz = 1.0 / (12.0 * b.dx[2] * b.dx[2]);
     D.c0 = -30.0 * (D.cx + D.cy + D.cz);
-    const int ty = tile_ty(c);
+    const int tx = out_tx(c), ty = out_ty(c);
     D.tz = c.tz > 0 ? std::min(c.tz, b.n[2]) : b.n[2];
-    D.tiles[0] = (b.n[0] + c.tx - 1) / c.tx;
+    D.tiles[0] = (b.n[0] + tx - 1) / tx;
     D.tiles[1] = (b.n[1] + ty - 1) / ty;
     D.tiles[2] = (b.n[2] + D.tz - 1) / D.tz;
     return D;
@@ -506,14 +533,17 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
         return r;
     const Choice ch = choose(ctx, op, b, nbox);
     const Cand &c = cands()[ch.cand];
-    out[0] = kernel_op(op);
+    out[0] = c.variant == 1 ? 100 : kernel_op(op); // 100: fused RK4 stage pairs
     out[1] = c.tx;
     out[2] = tile_ty(c);
     out[3] = c.tz;
     out[4] = c.nw * 64;
     out[5] = ch.tuned;
     out[6] = ch.cand;
-    out[7] = (int)cands().size();
+    int allowed = 0; // the candidates this op may use form a prefix of the list
+    while (allowed < (int)cands().size() && cand_allowed(cands()[allowed], op, nbox))
+        ++allowed;
+    out[7] = allowed;
     return S4_OK;
 }
 
@@ -526,6 +556,8 @@ int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
         return r;
     if (candidate >= (int)cands().size() || candidate < -1)
         return fail(S4_EINVAL, "candidate %d out of range", candidate);
+    if (candidate >= 0 && !cand_allowed(cands()[candidate], op, nbox))
+        return fail(S4_ENOTSUP, "candidate %d (fused RK4 stage pairs) applies to S4_OP_RK4 on one box only", candidate);
     std::lock_guard<std::mutex> lk(ctx->mu);
     const std::string key = setup_key(ctx, op, b, nbox);
     if (candidate < 0)
@@ -735,6 +767,64 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
     return S4_OK;
 }
 
+// Fused stage-pair RK4 on one box.  One step is two launches: pair 0 reads
+// y_n = (ui, ri) and writes y_3 (U3, R3) and the running sum (AU, AR); pair 1
+// reads them and writes y_{n+1} to (uo, ro).  Steps alternate between the
+// caller's state and a ping-pong copy in the workspace, so an even number
+// of steps ends in the caller's buffers.
+struct PairFields {
+    double *U3, *R3, *Up, *Rp, *AU, *AR;
+};
+
+static PairFields pair_fields(const s4_box &b, char *ws)
+{
+    const size_t fb = field_bytes(b);
+    auto F = [&](int k) { return ws_field(ws + k * fb, b); };
+    return {F(0), F(2), F(1), F(3), F(4), F(5)};
+}
+
+static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *ui, const double *ri,
+                         double *uo, double *ro, const double *c2, const PairFields &W, double dt, hipStream_t s)
+{
+    DevBox D = devbox(b, c);
+    const int items = (int)dev_items(D);
+    DevBox A = D;
+    A.in = ui;
+    A.p[0] = ri;
+    A.p[5] = c2;
+    A.q[0] = W.U3;
+    A.q[1] = W.R3;
+    A.q[2] = W.AU;
+    A.q[3] = W.AR;
+    hipError_t e = launch_rk4_pair(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "stage-pair launch");
+    DevBox Bx = D;
+    Bx.in = W.U3;
+    Bx.p[0] = W.R3;
+    Bx.p[1] = ui;
+    Bx.p[2] = ri;
+    Bx.p[3] = W.AU;
+    Bx.p[4] = W.AR;
+    Bx.p[5] = c2;
+    Bx.q[0] = uo;
+    Bx.q[1] = ro;
+    e = launch_rk4_pair(1, c.tx, c.nw, Bx, rk4_coef(2, dt), rk4_coef(3, dt), items, ctx->nxcd, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "stage-pair launch");
+    return S4_OK;
+}
+
+// two fused steps: (u, rho) -> ping-pong copy -> (u, rho)
+static int rk4_pair_double_step(s4_ctx *ctx, const Cand &c, const s4_box &b, double *u, double *rho,
+                                const double *c2, const PairFields &W, double dt, hipStream_t s)
+{
+    int r = rk4_pair_step(ctx, c, b, u, rho, W.Up, W.Rp, c2, W, dt, s);
+    if (r)
+        return r;
+    return rk4_pair_step(ctx, c, b, W.Up, W.Rp, u, rho, c2, W, dt, s);
+}
+
 static std::string graph_key(const s4_box *b, int nbox, double *const *u, double *const *rho,
                              const double *const *c2, double dt, const void *ws, int cand, bool batched)
 {
@@ -791,8 +881,65 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
 
     hipStream_t s = (hipStream_t)stream;
     const Choice ch = choose(ctx, S4_OP_RK4, b, nbox);
-    const Cand &c = cands()[ch.cand];
     char *ws = (char *)workspace;
+    if (cands()[ch.cand].variant == 1 && nbox == 1) {
+        // fused stage pairs: pairs of steps, an odd last step with the stage kernels
+        const Cand &cp = cands()[ch.cand];
+        const PairFields W = pair_fields(b[0], ws);
+        const double *c2b = c2 ? c2[0] : nullptr;
+        const int pairs = nsteps / 2;
+        if (pairs > 0) {
+            if (mode != S4_GRAPH) {
+                for (int k = 0; k < pairs; ++k)
+                    if ((r = rk4_pair_double_step(ctx, cp, b[0], u[0], rho[0], c2b, W, dt, s)))
+                        return r;
+            } else {
+                const std::string key = "pair|" + graph_key(b, nbox, u, rho, c2, dt, workspace, ch.cand, false);
+                GraphEntry ge;
+                {
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    auto it = ctx->graphs.find(key);
+                    if (it != ctx->graphs.end())
+                        ge = it->second;
+                }
+                if (!ge.exec) {
+                    S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+                    r = rk4_pair_double_step(ctx, cp, b[0], u[0], rho[0], c2b, W, dt, ctx->cap);
+                    hipGraph_t g = nullptr;
+                    hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+                    if (r)
+                        return r;
+                    if (e != hipSuccess)
+                        return hip_fail(e, "hipStreamEndCapture");
+                    e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+                    if (e != hipSuccess) {
+                        (void)hipGraphDestroy(g);
+                        return hip_fail(e, "hipGraphInstantiate");
+                    }
+                    ge.graph = g;
+                    std::lock_guard<std::mutex> lk(ctx->mu);
+                    if (ctx->graphs.size() >= 64) {
+                        for (auto &kv : ctx->graphs) {
+                            (void)hipGraphExecDestroy(kv.second.exec);
+                            (void)hipGraphDestroy(kv.second.graph);
+                        }
+                        ctx->graphs.clear();
+                    }
+                    ctx->graphs[key] = ge;
+                }
+                for (int k = 0; k < pairs; ++k)
+                    S4_HIP(hipGraphLaunch(ge.exec, s));
+            }
+        }
+        if (nsteps % 2 == 0)
+            return S4_OK;
+        // odd remainder: one step with the per-stage kernels (same arithmetic)
+        const Cand &c0 = cands()[heuristic(ctx, b, nbox)];
+        std::vector<DevBox> tab0;
+        rk4_tables(b, nbox, u, rho, c2, ws, c0, tab0);
+        return rk4_step(ctx, c0, tab0, nbox, false, nullptr, nullptr, dev_items(tab0[0]), dt, s);
+    }
+    const Cand &c = cands()[ch.cand];
     std::vector<DevBox> tab;
     rk4_tables(b, nbox, u, rho, c2, ws, c, tab);
     int64_t nitems = 0;
@@ -1068,6 +1215,8 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     float best_t = 0;
     for (int ci = 0; ci < (int)cands().size() && !r; ++ci) {
         const Cand &c = cands()[ci];
+        if (!cand_allowed(c, op, nbox))
+            continue;
         // per candidate: what one call of the op launches, on scratch buffers
         std::vector<DevBox> tab;
         int64_t nitems = 0;
@@ -1103,10 +1252,15 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             }
         }
         int rot = 0;
+        const PairFields pf = op == S4_OP_RK4 ? pair_fields(b[0], (char *)F[0][2] - field_shift(b[0])) : PairFields{};
         auto run = [&]() -> int {
             const int set = rot++ % TUNE_SETS;
             switch (op) {
             case S4_OP_RK4:
+                if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
+                    return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
+                                         set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
+                                         s);
                 return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s);
             case S4_OP_WAVE_RHS: {
                 StageCoef K{};

@@ -312,6 +312,179 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restr
 }
 
 // ---------------------------------------------------------------------------
+// Two RK4 stages fused in one pass (temporal blocking by a stage pair).
+//
+// Pair 0 runs stages 1 and 2: reads y_n, writes y_3 = y_n + dt/2 k2 and the
+// running sum y_n + dt/6 k1 + dt/3 k2.  Pair 1 runs stages 3 and 4: reads
+// y_3, y_n and the running sum, writes y_{n+1} (to another buffer: its
+// first stage reads y_n around the tile, which neighbouring tiles would
+// otherwise overwrite).  A workgroup of TXE x TYE lanes computes the first
+// stage of the pair on its whole region and the second stage on the inner
+// (TXE-4) x (TYE-4) output tile; the second stage trails the first by two z
+// planes.  The first stage's input plane (with a 2-point halo) lives in a
+// 4-plane LDS ring, its output in a 3-plane ring, and each lane keeps the
+// z-queues of both stage inputs and short delay lines of its pointwise
+// values in registers.  One barrier per plane; the next plane's loads are
+// issued right after it.  The per-point formulas are the stage kernel's, so
+// the two paths give bit-identical results.
+
+__device__ __forceinline__ int mod3(int p)
+{
+    const int r = p % 3;
+    return r < 0 ? r + 3 : r;
+}
+
+template <int TXE, int NW, int PAIR, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
+{
+    using T = Tile<TXE, NW>;
+    constexpr int TYE = T::TY;
+    constexpr int TXO = TXE - 4, TYO = TYE - 4;
+    constexpr int P1 = T::LY * T::LX; // ring-1 plane: first-stage input with halo
+    constexpr int P2 = TXE * TYE;     // ring-2 plane: first-stage output
+    __shared__ double ring1[4 * P1];
+    __shared__ double ring2[3 * P2];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, TXO, TYO);
+    ItemPos Pe = P;
+    Pe.x0 -= 2;
+    Pe.y0 -= 2;
+    const Walker<TXE, NW, true> w(B, Pe, threadIdx.x);
+    const int lx = threadIdx.x % TXE, ly = threadIdx.x / TXE;
+    const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < B.n[0] && w.j < B.n[1];
+    const int l2 = ly * TXE + lx;
+    const double *__restrict__ in = B.in;
+    const double *c2 = HASC2 ? B.p[5] : nullptr;
+
+    double qa0 = 0, qa1 = 0, qa2 = 0, qa3 = 0, qa4 = 0; // first-stage input, planes f-4 .. f
+    double qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, qb4 = 0; // first-stage output u, planes f-6 .. f-2
+    double da0 = 0, da1 = 0, da2 = 0;                   // pair 0: rho_n   pair 1: rho_4
+    double db0 = 0, db1 = 0, db2 = 0;                   // pair 0: rho_2   pair 1: acc_u after stage 3
+    double dd0 = 0, dd1 = 0, dd2 = 0;                   //                 pair 1: acc_rho after stage 3
+    double dc0 = 1, dc1 = 1, dc2 = 1;                   // c^2
+    // loads one plane ahead: the input column and halo of plane f, and the
+    // first stage's pointwise streams at plane f - 2
+    const bool acc_lane = PAIR == 1 && out;
+    auto load_pw = [&](int p, double *v) {
+        const int64_t e = w.col + w.zoff(p);
+        if (HASC2)
+            v[0] = ldp(c2 + e);
+        v[1] = ldp(B.p[0] + e); // pair 0: rho_n   pair 1: rho_3
+        if (PAIR == 1) {
+            v[2] = ldp(B.p[1] + e); // u_n
+            v[3] = ldp(B.p[2] + e); // rho_n
+            if (acc_lane && p >= P.z0 && p < P.z1) {
+                v[4] = ldp(B.p[3] + e); // acc_u
+                v[5] = ldp(B.p[4] + e); // acc_rho
+            }
+        }
+    };
+    double nown, nhv[T::HS], npw[6] = {1, 0, 0, 0, 0, 0}, pw[6] = {1, 0, 0, 0, 0, 0};
+    {
+        const int f = P.z0 - 4;
+        const int64_t zo = w.zoff(f);
+        nown = in[w.col + zo];
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0)
+                nhv[s] = in[w.hcol[s] + zo];
+    }
+    for (int f = P.z0 - 4; f <= P.z1 + 3; ++f) {
+        qa0 = qa1;
+        qa1 = qa2;
+        qa2 = qa3;
+        qa3 = qa4;
+        qa4 = nown;
+        double *R1 = ring1 + (f & 3) * P1;
+        R1[w.lc] = qa4;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0)
+                R1[w.hl[s]] = nhv[s];
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+            pw[v] = npw[v];
+        __syncthreads();
+        const int p1 = f - 2;
+        if (f + 1 <= P.z1 + 3) {
+            const int64_t zo = w.zoff(f + 1);
+            nown = in[w.col + zo];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    nhv[s] = in[w.hcol[s] + zo];
+            if (p1 + 1 >= P.z0 - 2)
+                load_pw(p1 + 1, npw);
+        }
+        if (p1 >= P.z0 - 2) {
+            // first stage of the pair at plane p1, on the whole region
+            const double *L = ring1 + (p1 & 3) * P1;
+            const int lc = w.lc;
+            const double lap = lap4(B, qa2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
+                                    L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa0, qa1, qa3, qa4);
+            const double cc = pw[0];
+            const double kr = HASC2 ? cc * lap : lap;
+            double next_u, next_r;
+            if (PAIR == 0) { // stage 1: y_2 = y_n + dt/2 k1
+                const double un = qa2, rn = pw[1];
+                next_u = fma(K1.a, rn, un);
+                next_r = fma(K1.a, kr, rn);
+                db0 = next_r;
+                da0 = rn;
+            } else { // stage 3: y_4 = y_n + dt k3; acc += dt/3 k3
+                const double ku = pw[1], un = pw[2], rn = pw[3];
+                next_u = fma(K1.a, ku, un);
+                next_r = fma(K1.a, kr, rn);
+                da0 = next_r;
+                if (acc_lane && p1 >= P.z0 && p1 < P.z1) {
+                    db0 = fma(K1.b, ku, pw[4]);
+                    dd0 = fma(K1.b, kr, pw[5]);
+                }
+            }
+            if (HASC2)
+                dc0 = cc;
+            ring2[mod3(p1) * P2 + l2] = next_u;
+            qb0 = qb1;
+            qb1 = qb2;
+            qb2 = qb3;
+            qb3 = qb4;
+            qb4 = next_u;
+        }
+        const int p2 = f - 4;
+        if (out && p2 >= P.z0 && p2 < P.z1) {
+            // second stage of the pair at plane p2 = p1 - 2, on the output tile
+            const double *L = ring2 + mod3(p2) * P2;
+            const double lap = lap4(B, qb2, L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
+                                    L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb0, qb1, qb3, qb4);
+            const double kr = HASC2 ? dc2 * lap : lap;
+            const int64_t c = w.point(B, p2);
+            if (PAIR == 0) { // stage 2: y_3 = y_n + dt/2 k2; acc = y_n + (y_2 - y_n)/3 + dt/3 k2
+                const double un = qa0, rn = da2, u2 = qb2, r2 = db2;
+                st(B.q[0] + c, fma(K2.a, r2, un));
+                st(B.q[1] + c, fma(K2.a, kr, rn));
+                st(B.q[2] + c, fma(K2.b, r2, fma(1.0 / 3.0, u2 - un, un)));
+                st(B.q[3] + c, fma(K2.b, kr, fma(1.0 / 3.0, r2 - rn, rn)));
+            } else { // stage 4: y_{n+1} = acc + dt/6 k4
+                st(B.q[0] + c, fma(K2.b, da2, db2));
+                st(B.q[1] + c, fma(K2.b, kr, dd2));
+            }
+        }
+        if (p1 >= P.z0 - 2) {
+            da2 = da1;
+            da1 = da0;
+            db2 = db1;
+            db1 = db0;
+            dd2 = dd1;
+            dd1 = dd0;
+            if (HASC2) {
+                dc2 = dc1;
+                dc1 = dc0;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // multi-field mixed-derivative kernel:
 //   out = sum_a D2_a f + sum_{a<b} D_ab f + sum_{a,b} A_ab (D1_a f)(D1_b f)
 // D_ab is the tensor product of two D1 stencils, evaluated factored: D_xy as
@@ -524,6 +697,30 @@ hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, 
     }
     X(64, 4) X(64, 8) X(32, 4) X(32, 8) X(16, 4) X(16, 8)
 #undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
+                           int nitems, int nxcd, hipStream_t s)
+{
+#define Y(TXE_, NW_, P_, C_)                                                                           \
+    hipLaunchKernelGGL((k_rk4_pair<TXE_, NW_, P_, C_>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd)
+#define X(TXE_, NW_)                                                                                   \
+    if (txe == TXE_ && nw == NW_) {                                                                    \
+        const bool c2 = B.p[5] != nullptr;                                                             \
+        if (pair == 0 && c2)                                                                           \
+            Y(TXE_, NW_, 0, true);                                                                     \
+        else if (pair == 0)                                                                            \
+            Y(TXE_, NW_, 0, false);                                                                    \
+        else if (c2)                                                                                   \
+            Y(TXE_, NW_, 1, true);                                                                     \
+        else                                                                                           \
+            Y(TXE_, NW_, 1, false);                                                                    \
+        return hipGetLastError();                                                                      \
+    }
+    X(32, 8) X(64, 8) X(64, 16) X(32, 16)
+#undef X
+#undef Y
     return hipErrorInvalidValue;
 }
 

@@ -25,6 +25,11 @@ int max_blocks_per_cu(int op, int tx, int nw);
 // one workgroup per (field, tile) item.
 hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, hipStream_t s);
 
+// One fused pair of RK4 stages (pair 0: stages 1-2, pair 1: stages 3-4) on box
+// B: workgroups of txe x (nw*64/txe) lanes, output tiles of (txe-4) x (tye-4).
+hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
+                           int nitems, int nxcd, hipStream_t s);
+
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 

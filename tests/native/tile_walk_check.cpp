@@ -243,6 +243,121 @@ static void run_mixed(int nx, int ny, int nz, int g, int padx, int tz_req)
             }
 }
 
+// the fused stage-pair traversal (k_rk4_pair): first stage on the whole
+// TXE x TYE region from a 4-plane ring, second stage two planes behind on
+// the inner tile from a 3-plane ring, periodic addressing.  Tags encode a
+// point (wrapped into the box) and the stage that produced it.
+static int mod3h(int p)
+{
+    const int r = p % 3;
+    return r < 0 ? r + 3 : r;
+}
+
+template <int TXE, int NW>
+static void run_pair(int nx, int ny, int nz, int g, int padx, int tz_req)
+{
+    using T = Tile<TXE, NW>;
+    constexpr int TYE = T::TY;
+    constexpr int TXO = TXE - 4, TYO = TYE - 4;
+    constexpr int P1 = T::LY * T::LX, P2 = TXE * TYE;
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.g = g;
+    B.sy = nx + 2 * g + padx;
+    B.sz = B.sy * (ny + 2 * g);
+    B.tz = tz_req > 0 && tz_req < nz ? tz_req : nz;
+    B.tiles[0] = (nx + TXO - 1) / TXO;
+    B.tiles[1] = (ny + TYO - 1) / TYO;
+    B.tiles[2] = (nz + B.tz - 1) / B.tz;
+    const int64_t total = B.sz * (nz + 2 * g);
+    std::vector<int> written(total, 0);
+    const int nitems = B.tiles[0] * B.tiles[1] * B.tiles[2];
+    auto tag = [&](int i, int j, int k, int stage) -> int64_t {
+        return elem(B, wrap_index(i, nx), wrap_index(j, ny), wrap_index(k, nz)) * 4 + stage;
+    };
+    std::vector<int64_t> ring1(4 * P1), ring2(3 * P2);
+    for (int item = 0; item < nitems; ++item) {
+        const ItemPos P = item_pos(B, item, TXO, TYO);
+        ItemPos Pe = P;
+        Pe.x0 -= 2;
+        Pe.y0 -= 2;
+        std::vector<Walker<TXE, NW, true>> W;
+        for (int t = 0; t < T::NT; ++t)
+            W.emplace_back(B, Pe, t);
+        std::vector<int64_t> qa(T::NT * 5, -1), qb(T::NT * 5, -1);
+        std::fill(ring1.begin(), ring1.end(), -1);
+        std::fill(ring2.begin(), ring2.end(), -1);
+        for (int f = P.z0 - 4; f <= P.z1 + 3; ++f) {
+            // loads and ring-1 writes (before the barrier)
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                const int64_t e = w.col + w.zoff(f);
+                CHECK(e >= 0 && e < total, "pair load out of range");
+                for (int d = 0; d < 4; ++d)
+                    qa[t * 5 + d] = qa[t * 5 + d + 1];
+                qa[t * 5 + 4] = tag(w.i, w.j, f, 0);
+                CHECK(e * 4 == tag(w.i, w.j, f, 0), "pair own column address");
+                int64_t *R1 = &ring1[(f & 3) * P1];
+                R1[w.lc] = qa[t * 5 + 4];
+                for (int s = 0; s < T::HS; ++s) {
+                    if (w.hl[s] < 0)
+                        continue;
+                    const int64_t h = w.hcol[s] + w.zoff(f);
+                    CHECK(h >= 0 && h < total, "pair halo out of range");
+                    R1[w.hl[s]] = h * 4;
+                }
+            }
+            const int p1 = f - 2, p2 = f - 4;
+            // first stage at p1, every lane
+            if (p1 >= P.z0 - 2) {
+                for (int t = 0; t < T::NT; ++t) {
+                    const auto &w = W[t];
+                    const int64_t *L = &ring1[(p1 & 3) * P1];
+                    for (int d = -2; d <= 2; ++d) {
+                        CHECK(L[w.lc + d] == tag(w.i + d, w.j, p1, 0), "pair stage-1 x tap");
+                        CHECK(L[w.lc + d * T::LX] == tag(w.i, w.j + d, p1, 0), "pair stage-1 y tap");
+                        CHECK(qa[t * 5 + 2 + d] == tag(w.i, w.j, p1 + d, 0), "pair stage-1 z tap");
+                    }
+                    const int lx = t % TXE, ly = t / TXE;
+                    ring2[mod3h(p1) * P2 + ly * TXE + lx] = tag(w.i, w.j, p1, 1);
+                    for (int d = 0; d < 4; ++d)
+                        qb[t * 5 + d] = qb[t * 5 + d + 1];
+                    qb[t * 5 + 4] = tag(w.i, w.j, p1, 1);
+                }
+            }
+            // second stage at p2, output lanes
+            for (int t = 0; t < T::NT; ++t) {
+                const auto &w = W[t];
+                const int lx = t % TXE, ly = t / TXE;
+                const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < nx && w.j < ny;
+                if (!(out && p2 >= P.z0 && p2 < P.z1))
+                    continue;
+                CHECK(w.i >= 0 && w.j >= 0, "output lane outside the box");
+                const int l2 = ly * TXE + lx;
+                const int64_t *L = &ring2[mod3h(p2) * P2];
+                for (int d = -2; d <= 2; ++d) {
+                    CHECK(L[l2 + d] == tag(w.i + d, w.j, p2, 1), "pair stage-2 x tap");
+                    CHECK(L[l2 + d * TXE] == tag(w.i, w.j + d, p2, 1), "pair stage-2 y tap");
+                    CHECK(qb[t * 5 + 2 + d] == tag(w.i, w.j, p2 + d, 1), "pair stage-2 z tap");
+                }
+                CHECK(qa[t * 5 + 0] == tag(w.i, w.j, p2, 0), "pair u_n at the output plane");
+                const int64_t c = w.point(B, p2);
+                CHECK(c == elem(B, w.i, w.j, p2), "pair store offset");
+                written[c]++;
+            }
+        }
+    }
+    for (int k = -g; k < nz + g; ++k)
+        for (int j = -g; j < ny + g; ++j)
+            for (int i = -g; i < nx + g; ++i) {
+                const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+                CHECK(written[elem(B, i, j, k)] == (in ? 1 : 0), "pair point (%d,%d,%d) stored %d times", i, j, k,
+                      written[elem(B, i, j, k)]);
+            }
+}
+
 // the ghost-fill enumeration: every ghost point of the shell exactly once,
 // never an interior point, and every source an interior point
 static void ghost_shell(int nx, int ny, int nz, int g)
@@ -301,6 +416,14 @@ int main()
     const int G[][4] = {{32, 32, 32, 2}, {5, 7, 6, 3}, {70, 9, 5, 3}, {2, 2, 2, 2}, {3, 17, 4, 3}, {1, 1, 1, 2}};
     for (auto &s : G)
         ghost_shell(s[0], s[1], s[2], s[3]);
+    const int PS[][6] = {{32, 32, 32, 2, 0, 16}, {37, 19, 23, 2, 3, 8}, {5, 7, 3, 2, 0, 2}, {1, 2, 1, 2, 0, 0},
+                         {70, 9, 5, 3, 6, 64}, {28, 12, 17, 2, 0, 32}};
+    for (auto &s : PS) {
+        run_pair<32, 8>(s[0], s[1], s[2], s[3], s[4], s[5]);
+        run_pair<64, 8>(s[0], s[1], s[2], s[3], s[4], s[5]);
+        run_pair<64, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
+        run_pair<32, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
+    }
     shapes<64, 4>();
     shapes<64, 8>();
     shapes<32, 4>();

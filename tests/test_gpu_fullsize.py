@@ -37,6 +37,25 @@ def test_wave256_rk4_100_steps_vs_oracle(ctx):
     assert rel(host(r), wr, g) <= 1e-12
 
 
+def test_wave256_fused_pairs_match_stage_kernels(ctx):
+    """Every fused stage-pair candidate against the per-stage kernels, bit for bit, at 256^3."""
+    d = W.wave256()
+    g, n = d["ghost"], d["n"]
+    u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
+    b = S.box_of(u, g, d["dx"])
+    nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, 2)
+    S.s4_rk4(ctx, b, [u], [r], None, d["dt"], 6, "graph")
+    ref = (host(u), host(r))
+    for cand in range(30, nc):
+        u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
+        S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
+        S.s4_rk4(ctx, b, [u], [r], None, d["dt"], 6, "graph")
+        np.testing.assert_array_equal(host(u), ref[0], err_msg=f"candidate {cand}")
+        np.testing.assert_array_equal(host(r), ref[1], err_msg=f"candidate {cand}")
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+
+
 def test_wave256_pure_mode_closed_form(ctx):
     """u0 = sin(2 pi x) sin(2 pi y) sin(2 pi z), rho0 = 0: after N steps
     (u, rho) = P^N (1, 0) S with P the RK4 polynomial of dt [[0, 1], [lam, 0]]

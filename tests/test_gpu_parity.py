@@ -106,20 +106,39 @@ def test_rk4_modes_and_candidates_bitwise(ctx):
     c2d = dev(c2, g)
     ref = None
     b = None
-    for cand in [None, 0, 7, 13, 21, 29]:
+    nc = None
+    for cand in [None, 0, 7, 13, 21, 29, "fused"]:
         for mode in ["perbox", "graph"]:
             u, r = dev(u0, g), dev(r0, g)
             b = S.box_of(u, g, dx)
-            if cand is not None:
-                S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
-            S.s4_rk4(ctx, b, [u], [r], [c2d], dt, 3, mode)
-            got = (host(u), host(r))
-            if ref is None:
-                ref = got
-                assert rel(got[0], wu, g) <= TOL and rel(got[1], wr, g) <= TOL
-            np.testing.assert_array_equal(got[0], ref[0])
-            np.testing.assert_array_equal(got[1], ref[1])
+            nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
+            cl = list(range(30, nc)) if cand == "fused" else [cand]
+            for cc in cl:
+                u, r = dev(u0, g), dev(r0, g)
+                if cc is not None:
+                    S.s4_set_choice(ctx, S.S4_OP_RK4, b, cc)
+                S.s4_rk4(ctx, b, [u], [r], [c2d], dt, 3, mode)  # odd: fused pair + one stage-kernel step
+                got = (host(u), host(r))
+                if ref is None:
+                    ref = got
+                    assert rel(got[0], wu, g) <= TOL and rel(got[1], wr, g) <= TOL
+                np.testing.assert_array_equal(got[0], ref[0], err_msg=f"candidate {cc} {mode}")
+                np.testing.assert_array_equal(got[1], ref[1], err_msg=f"candidate {cc} {mode}")
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    # even step counts end in the caller's buffers after fused pairs only
+    wu4, wr4 = O.rk4(u0, r0, g, dx, dt, 4, c2)
+    res = []
+    for cc in [0, 30, nc - 1]:
+        u, r = dev(u0, g), dev(r0, g)
+        S.s4_set_choice(ctx, S.S4_OP_RK4, b, cc)
+        S.s4_rk4(ctx, b, [u], [r], [c2d], dt, 4, "graph")
+        res.append((host(u), host(r)))
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    assert rel(res[0][0], wu4, g) <= TOL and rel(res[0][1], wr4, g) <= TOL
+    for a in res[1:]:
+        np.testing.assert_array_equal(a[0], res[0][0])
+        np.testing.assert_array_equal(a[1], res[0][1])
+        assert ghosts_untouched(a[0], g) and ghosts_untouched(a[1], g)
 
 
 def small_bboxset(seed=7, nbox=9):
@@ -243,6 +262,23 @@ def test_copy_probe(ctx):
     dst = torch.empty_like(src)
     S.s4_copy(ctx, dst, src)
     assert torch.equal(dst, src)
+
+
+def test_fused_candidates_only_for_single_box_rk4(ctx):
+    n, g = (16, 16, 16), 2
+    u = S.alloc_field(n, g, fill=0.0)
+    b = S.box_of(u, g, 0.1)
+    nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
+    for op in (S.S4_OP_WAVE_RHS, S.S4_OP_DERIV_MIXED, S.S4_OP_ADJOINT_STEP):
+        with pytest.raises(S.Sten4Error) as e:
+            S.s4_set_choice(ctx, op, b, nc - 1)
+        assert e.value.code == S.S4_ENOTSUP
+    with pytest.raises(S.Sten4Error) as e:
+        S.s4_set_choice(ctx, S.S4_OP_RK4, [b, b], nc - 1)
+    assert e.value.code == S.S4_ENOTSUP
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, nc - 1)
+    assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["kernel_op"] == 100
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
 
 
 def test_errors_on_device_calls(ctx):
