@@ -10,6 +10,8 @@ once in a hipGraph and replayed, or the two fused stage-pair kernels when the
 tuner picks them.  value = interior points x RK4 steps / s.
 
 The same JSON line also reports, each on its own workload:
+  tuning   the RK4 tile choice from the heuristic, from the library's on-line
+           random-restart hill climber after 60 calls, and from the sweep
   rhs      one 4th-order Laplacian RHS on the 256^3 box (ghosts read), with
            four rotating buffer sets so no pass finds its data in the
            256 MB last-level cache
@@ -73,7 +75,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="rk4,rhs,copy,mixed,batched,adjoint,cpu")
+    ap.add_argument("--sections", default="rk4,tuning,rhs,copy,mixed,batched,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
     args = ap.parse_args()
@@ -159,6 +161,48 @@ def main():
             "bytes_per_point_step": 8 * sum(launch_bytes), "launches_per_step": nlaunch,
             "kernel_set": "fused stage pairs" if fused else "one kernel per stage"}
     del u, rho, ws
+
+    # ------------------------------------------------------------------ tile choice: heuristic, on-line, sweep
+    if "tuning" in sections:
+        # the paper's LoopControl comparison on this loop: the heuristic start,
+        # the on-line random-restart hill climber after a fixed number of calls,
+        # and the offline sweep, each timed afterwards on the same data
+        uu, rr = to_dev(d["u"]), to_dev(d["rho"])
+        wst = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
+        heur = S.s4_get_choice(S.Context(0), S.S4_OP_RK4, box)["candidate"]
+        on = S.Context(0)
+        S.s4_set_online_tuning(on, True, 0.02, 1)
+        ncalls, spc = 60, 4
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ncalls):
+            S.s4_rk4(on, box, [uu], [rr], None, d["dt"], spc, "graph", ws=wst)
+        torch.cuda.synchronize()
+        online_total = time.perf_counter() - t0
+        onc = S.s4_get_choice(on, S.S4_OP_RK4, box)["candidate"]
+
+        def per_step(cand):
+            S.s4_set_choice(ctx, S.S4_OP_RK4, box, cand)
+            S.s4_rk4(ctx, box, [uu], [rr], None, d["dt"], 4, "graph", ws=wst)
+            ts = []
+            for _ in range(5):
+                e0.record(stream)
+                S.s4_rk4(ctx, box, [uu], [rr], None, d["dt"], 10, "graph", ws=wst)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) / 10)
+            S.s4_set_choice(ctx, S.S4_OP_RK4, box, -1)
+            return sorted(ts)[2]
+
+        sweep = choice["candidate"] if choice["tuned"] else None
+        out["tuning"] = {"workload": "wave256 RK4 step", "heuristic": {"candidate": heur, "ms_per_step": round(per_step(heur), 4)},
+                         "online": {"candidate": onc, "ms_per_step": round(per_step(onc), 4), "calls": ncalls,
+                                    "steps_per_call": spc,
+                                    "ms_per_step_during_search": round(online_total * 1e3 / (ncalls * spc), 4)}}
+        if sweep is not None:
+            out["tuning"]["sweep"] = {"candidate": sweep, "ms_per_step": round(per_step(sweep), 4)}
+        log(f"[bench] tuning: {out['tuning']}")
+        del uu, rr, wst
 
     # ------------------------------------------------------------------ RHS 256^3, rotating buffers
     if "rhs" in sections:

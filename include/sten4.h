@@ -208,8 +208,10 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
 
 /* The tile choice the library would use for `op` on box b (or on the set):
  * out[0] variant id, out[1] tile x, out[2] tile y, out[3] z chunk,
- * out[4] threads per workgroup, out[5] 1 if it came from tuning,
- * out[6] candidate index, out[7] number of candidates this op may use on
+ * out[4] threads per workgroup, out[5] 1 if it came from s4_tune, 2 if
+ * on-line tuning is active,
+ * out[6] candidate index (with on-line tuning: the best setting so far),
+ * out[7] number of candidates this op may use on
  * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 when the choice is
  * the fused stage-pair kernel set of RK4. */
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
@@ -218,6 +220,28 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
  * setup, or -1 to drop the forced choice.  For tests that compare
  * candidates bit for bit, and for benchmark sweeps. */
 int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate);
+
+/* On-line tuning: the paper's run-time random-restart hill climbing
+ * (Sec. III-B).  With enable != 0 every call of an op times its own launches
+ * with HIP events (read back at a later call, never waited for) and the tile
+ * choice of its loop setup moves: the neighbourhood of the best setting so
+ * far is tried one setting per call, the best moves to any faster
+ * neighbour, and once no neighbour is left a random setting is tried with
+ * probability restart_prob per call (then its neighbourhood), abandoned after
+ * one call if it is more than 1.5x slower than the best.  seed seeds the
+ * random restarts.  A forced choice (s4_set_choice) is never changed; a
+ * tuned one (s4_tune) is the starting point.  S4_TUNE=online in the
+ * environment enables it at s4_create with restart_prob 0.02. */
+int s4_set_online_tuning(s4_ctx *ctx, int enable, double restart_prob, uint64_t seed);
+
+/* Host-only simulation of the on-line tuner for one loop setup of `op` on
+ * these boxes, for testing its search: cost[i] is the time of candidate i
+ * (ncost = the number of candidates), each timing is perturbed by a factor
+ * in [1 - noise, 1 + noise] from a seeded generator and reaches the tuner
+ * `lag` calls after the call it times (as device timings do).  Writes the
+ * candidate used at each of the ncalls calls to trace.  No device call. */
+int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, int ncost, double noise,
+                       double restart_prob, uint64_t seed, int lag, int ncalls, int *trace);
 
 /* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned):
  * the streaming-copy probe that calibrates achievable HBM bandwidth and the

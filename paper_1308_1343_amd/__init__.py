@@ -32,7 +32,7 @@ MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
            "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
            "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
-           "s4_copy")
+           "s4_set_online_tuning", "s4_online_simulate", "s4_copy")
 
 
 class S4Box(ctypes.Structure):
@@ -81,6 +81,9 @@ def lib():
     L.s4_get_choice.argtypes = [vp, i, BP, i, ctypes.POINTER(i)]
     L.s4_set_choice.argtypes = [vp, i, BP, i, i]
     L.s4_copy.argtypes = [vp, vp, vp, sz, vp]
+    L.s4_set_online_tuning.argtypes = [vp, i, d, ctypes.c_uint64]
+    L.s4_online_simulate.argtypes = [i, BP, i, ctypes.POINTER(d), i, d, d, ctypes.c_uint64, i, i,
+                                     ctypes.POINTER(i)]
     for name in EXPORTS:
         if name not in ("s4_destroy", "s4_last_error"):
             getattr(L, name).restype = i
@@ -294,6 +297,20 @@ def s4_get_choice(ctx, op, boxes) -> dict:
 def s4_set_choice(ctx, op, boxes, candidate):
     arr, n = _boxes(boxes)
     _check(lib().s4_set_choice(ctx.handle, op, arr, n, int(candidate)))
+
+
+def s4_set_online_tuning(ctx, enable=True, restart_prob=0.02, seed=1):
+    _check(lib().s4_set_online_tuning(ctx.handle, int(bool(enable)), float(restart_prob), int(seed)))
+
+
+def s4_online_simulate(op, boxes, cost, noise=0.0, restart_prob=0.02, seed=1, lag=1, ncalls=100):
+    """Trace of candidates the on-line tuner picks against synthetic costs (host only)."""
+    arr, n = _boxes(boxes)
+    c = (ctypes.c_double * len(cost))(*[float(v) for v in cost])
+    trace = (ctypes.c_int * ncalls)()
+    _check(lib().s4_online_simulate(op, arr, n, c, len(cost), float(noise), float(restart_prob), int(seed),
+                                    int(lag), int(ncalls), trace))
+    return list(trace)
 
 
 def s4_copy(ctx, dst, src, nbytes=None, stream=None):

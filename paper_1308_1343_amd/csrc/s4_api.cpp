@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -121,6 +122,110 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
+// ---------------------------------------------------------------------------
+// On-line tuning of one loop setup: the paper's run-time random-restart hill
+// climbing (Sec. III-B).  Starting from the heuristic setting, each timing
+// of a call is fed back; the neighbourhood of the best setting so far is
+// tried one setting per call, the best moves to any neighbour that is
+// faster, and once the neighbourhood is exhausted a random setting is tried
+// with a small probability per call and its neighbourhood explored.  A trial
+// that is much slower than the best is abandoned after that one call, so
+// excursions stay cheap: the aim is a short total run time, not the optimum.
+
+// position of a candidate's parameters in their value orders
+static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : 2; }
+static int ord_nw(int nw) { return nw == 4 ? 0 : nw == 8 ? 1 : 2; }
+static int ord_tz(int tz) { return tz == 8 ? 0 : tz == 16 ? 1 : tz == 32 ? 2 : tz == 64 ? 3 : 4; }
+
+struct Hill {
+    std::vector<int> allowed;     // candidates this setup may use
+    int best = -1;                // best setting so far and its time per unit
+    double best_t = 0.0;
+    std::vector<int> todo;        // neighbours still to try
+    bool excursion = false;       // exploring around a random restart
+    double restart_prob = 0.02;
+    double improve = 0.02;        // a move needs this relative gain (timing noise)
+    double abort_ratio = 1.5;     // a trial this much slower than the best ends an excursion
+    uint64_t rng = 0x9E3779B97F4A7C15ull;
+    std::map<int, double> seen;   // fastest time measured per setting
+    int start = 0;
+
+    double uniform()
+    {
+        // splitmix64 step (Steele, Lea and Flood 2014)
+        uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    }
+
+    // settings one step away: one parameter moved to its neighbouring value,
+    // or the other kernel set with the same z chunk
+    std::vector<int> neighbours(int c) const;
+
+    int next()
+    {
+        if (best < 0)
+            return start;
+        while (!todo.empty()) {
+            const int c = todo.back();
+            todo.pop_back();
+            if (!seen.count(c))
+                return c;
+        }
+        excursion = false;
+        if (allowed.size() > 1 && uniform() < restart_prob) {
+            const int r = allowed[(size_t)(uniform() * allowed.size()) % allowed.size()];
+            if (r != best) {
+                excursion = true;
+                todo = neighbours(r);
+                return r;
+            }
+        }
+        return best;
+    }
+
+    void measured(int c, double t)
+    {
+        auto it = seen.find(c);
+        seen[c] = it == seen.end() ? t : std::min(it->second, t);
+        if (best < 0) {
+            best = c;
+            best_t = t;
+            todo = neighbours(c);
+            return;
+        }
+        if (c == best) {
+            best_t = std::min(best_t, t);
+            return;
+        }
+        if (t < best_t * (1.0 - improve)) { // move uphill
+            best = c;
+            best_t = t;
+            todo = neighbours(c);
+            excursion = false;
+            return;
+        }
+        if (excursion && t > best_t * abort_ratio) { // abandon a bad excursion at once
+            todo.clear();
+            excursion = false;
+        }
+    }
+};
+
+struct OnlinePending {
+    hipEvent_t a, b;
+    int cand;
+    double units;
+};
+
+struct OnlineSetup {
+    Hill hill;
+    std::deque<OnlinePending> pending;
+    std::vector<hipEvent_t> pool;
+};
+
 struct s4_ctx {
     int device = 0;
     int ncu = 256;
@@ -131,6 +236,10 @@ struct s4_ctx {
     std::map<std::string, int> tuned;
     std::map<std::string, int> forced;
     std::map<std::string, GraphEntry> graphs;
+    bool online = false; // on-line hill climbing of every loop setup
+    double restart_prob = 0.02;
+    uint64_t seed = 1;
+    std::map<std::string, OnlineSetup> online_state;
     std::mutex mu;
 };
 
@@ -187,23 +296,155 @@ static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
     return cand_index(tx, nw, 8);
 }
 
+// settings one step away: one parameter moved to its neighbouring value in
+// the same kernel set, and the nearest settings of the other kernel set
+std::vector<int> Hill::neighbours(int c) const
+{
+    const Cand &a = cands()[c];
+    auto dist = [&](const Cand &e) {
+        return std::abs(ord_tx(e.tx) - ord_tx(a.tx)) + std::abs(ord_nw(e.nw) - ord_nw(a.nw)) +
+               std::abs(ord_tz(e.tz) - ord_tz(a.tz));
+    };
+    std::vector<int> out;
+    int nearest = 1 << 30;
+    for (int d : allowed)
+        if (cands()[d].variant != a.variant)
+            nearest = std::min(nearest, dist(cands()[d]));
+    for (int d : allowed) {
+        if (d == c)
+            continue;
+        const Cand &e = cands()[d];
+        if (e.variant == a.variant ? dist(e) == 1 : dist(e) == nearest)
+            out.push_back(d);
+    }
+    return out;
+}
+
+static std::vector<int> allowed_cands(int op, int nbox)
+{
+    std::vector<int> v;
+    for (int i = 0; i < (int)cands().size(); ++i)
+        if (cand_allowed(cands()[i], op, nbox))
+            v.push_back(i);
+    return v;
+}
+
 struct Choice {
     int cand;
-    int tuned;
+    int tuned; // 0 heuristic or forced, 1 from s4_tune, 2 on-line
+    std::string key;
 };
 
-static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox)
+static void online_harvest(OnlineSetup &st);
+
+// caller holds ctx->mu
+static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox)
+{
+    auto it = ctx->online_state.find(key);
+    if (it != ctx->online_state.end())
+        return it->second;
+    OnlineSetup &st = ctx->online_state[key];
+    st.hill.allowed = allowed_cands(op, nbox);
+    auto t = ctx->tuned.find(key);
+    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, b, nbox);
+    st.hill.restart_prob = ctx->restart_prob;
+    st.hill.rng ^= ctx->seed * 0xD1342543DE82EF95ull + std::hash<std::string>()(key);
+    return st;
+}
+
+// peek: report the choice without advancing the on-line tuner
+static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
     const std::string key = setup_key(ctx, op, b, nbox);
     auto f = ctx->forced.find(key);
     if (f != ctx->forced.end())
-        return {f->second, 0};
+        return {f->second, 0, key};
+    if (ctx->online) {
+        OnlineSetup &st = online_setup(ctx, key, op, b, nbox);
+        online_harvest(st);
+        if (peek)
+            return {st.hill.best >= 0 ? st.hill.best : st.hill.start, 2, key};
+        return {st.hill.next(), 2, key};
+    }
     auto t = ctx->tuned.find(key);
     if (t != ctx->tuned.end())
-        return {t->second, 1};
-    return {heuristic(ctx, b, nbox), 0};
+        return {t->second, 1, key};
+    return {heuristic(ctx, b, nbox), 0, key};
 }
+
+// Timing of one call for the on-line tuner: events around the call's
+// launches on its stream, read back lazily by a later call of the same setup
+// (never waited for).
+static void online_harvest(OnlineSetup &st)
+{
+    while (!st.pending.empty()) {
+        OnlinePending &p = st.pending.front();
+        if (hipEventQuery(p.b) != hipSuccess)
+            break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess && p.units > 0)
+            st.hill.measured(p.cand, ms / p.units);
+        st.pool.push_back(p.a);
+        st.pool.push_back(p.b);
+        st.pending.pop_front();
+    }
+    (void)hipGetLastError();
+}
+
+struct OnlineTimer {
+    s4_ctx *ctx = nullptr;
+    std::string key;
+    int cand = -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s = nullptr;
+
+    OnlineTimer(s4_ctx *c, const Choice &ch, hipStream_t stream)
+    {
+        if (ch.tuned != 2)
+            return;
+        std::lock_guard<std::mutex> lk(c->mu);
+        OnlineSetup &st = c->online_state[ch.key];
+        if (st.pending.size() > 64) // results not coming back: stop adding timers
+            return;
+        for (hipEvent_t *e : {&a, &b}) {
+            if (!st.pool.empty()) {
+                *e = st.pool.back();
+                st.pool.pop_back();
+            } else if (hipEventCreate(e) != hipSuccess) {
+                *e = nullptr;
+            }
+        }
+        if (!a || !b || hipEventRecord(a, stream) != hipSuccess) {
+            for (hipEvent_t e : {a, b})
+                if (e)
+                    st.pool.push_back(e);
+            a = b = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        ctx = c;
+        key = ch.key;
+        cand = ch.cand;
+        s = stream;
+    }
+    // after the call's launches; units: what one time is divided by (RK4 steps)
+    void stop(double units)
+    {
+        if (!ctx)
+            return;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        OnlineSetup &st = ctx->online_state[key];
+        if (hipEventRecord(b, s) != hipSuccess) {
+            st.pool.push_back(a);
+            st.pool.push_back(b);
+            (void)hipGetLastError();
+        } else {
+            st.pending.push_back({a, b, cand, units});
+        }
+        ctx = nullptr;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // validation (host only, before anything is launched)
@@ -505,7 +746,58 @@ int s4_create(int device, s4_ctx **out)
         c->cache_path = cp;
         load_cache(c);
     }
+    const char *tm = getenv("S4_TUNE");
+    if (tm && std::string(tm) == "online")
+        c->online = true;
     *out = c;
+    return S4_OK;
+}
+
+int s4_set_online_tuning(s4_ctx *ctx, int enable, double restart_prob, uint64_t seed)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    if (!(restart_prob >= 0.0 && restart_prob <= 1.0))
+        return fail(S4_EINVAL, "restart_prob must be in [0, 1]");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->online = enable != 0;
+    ctx->restart_prob = restart_prob;
+    ctx->seed = seed;
+    for (auto &kv : ctx->online_state)
+        kv.second.hill.restart_prob = restart_prob;
+    return S4_OK;
+}
+
+int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, int ncost, double noise,
+                       double restart_prob, uint64_t seed, int lag, int ncalls, int *trace)
+{
+    int r = s4_check_boxes(b, nbox, op);
+    if (r)
+        return r;
+    if (!cost || !trace || ncalls < 0 || lag < 0 || lag > 64)
+        return fail(S4_EINVAL, "bad simulation arguments");
+    if (ncost != (int)cands().size())
+        return fail(S4_EINVAL, "cost needs one entry per candidate (%d)", (int)cands().size());
+    if (!(noise >= 0.0 && noise < 1.0) || !(restart_prob >= 0.0 && restart_prob <= 1.0))
+        return fail(S4_EINVAL, "noise in [0, 1) and restart_prob in [0, 1]");
+    s4_ctx sim; // host-only: the heuristic needs the CU count only
+    Hill h;
+    h.allowed = allowed_cands(op, nbox);
+    h.start = heuristic(&sim, b, nbox);
+    h.restart_prob = restart_prob;
+    h.rng ^= seed * 0xD1342543DE82EF95ull;
+    Hill noise_rng;
+    noise_rng.rng = seed + 12345;
+    std::deque<std::pair<int, double>> inflight; // timings arrive `lag` calls later
+    for (int i = 0; i < ncalls; ++i) {
+        const int c = h.next();
+        trace[i] = c;
+        inflight.push_back({c, cost[c] * (1.0 + noise * (2.0 * noise_rng.uniform() - 1.0))});
+        if ((int)inflight.size() > lag) {
+            h.measured(inflight.front().first, inflight.front().second);
+            inflight.pop_front();
+        }
+    }
     return S4_OK;
 }
 
@@ -513,6 +805,14 @@ void s4_destroy(s4_ctx *ctx)
 {
     if (!ctx)
         return;
+    for (auto &kv : ctx->online_state) {
+        for (auto &p : kv.second.pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (hipEvent_t e : kv.second.pool)
+            (void)hipEventDestroy(e);
+    }
     for (auto &kv : ctx->graphs) {
         if (kv.second.exec)
             (void)hipGraphExecDestroy(kv.second.exec);
@@ -531,7 +831,7 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
     int r = s4_check_boxes(b, nbox, op);
     if (r)
         return r;
-    const Choice ch = choose(ctx, op, b, nbox);
+    const Choice ch = choose(ctx, op, b, nbox, true);
     const Cand &c = cands()[ch.cand];
     out[0] = c.variant == 1 ? 100 : kernel_op(op); // 100: fused RK4 stage pairs
     out[1] = c.tx;
@@ -611,7 +911,9 @@ int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u, 
         all.push_back(w);
     if ((r = check_disjoint(wr, all)))
         return r;
-    const Cand &c = cands()[choose(ctx, S4_OP_WAVE_RHS, b, nbox).cand];
+    const Choice ch = choose(ctx, S4_OP_WAVE_RHS, b, nbox);
+    const Cand &c = cands()[ch.cand];
+    OnlineTimer tm(ctx, ch, (hipStream_t)stream);
     StageCoef K{};
     K.scale = 1.0;
     for (int i = 0; i < nbox; ++i) {
@@ -622,6 +924,7 @@ int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u, 
         if ((r = launch_one(ctx, OP_RHS, c, D, K, (hipStream_t)stream)))
             return r;
     }
+    tm.stop(1.0);
     return S4_OK;
 }
 
@@ -685,11 +988,16 @@ int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const
         all.push_back(w);
     if ((r = check_disjoint(wr, all)))
         return r;
-    const Cand &c = cands()[choose(ctx, S4_OP_DERIV_MIXED, b, 1).cand];
+    const Choice ch = choose(ctx, S4_OP_DERIV_MIXED, b, 1);
+    const Cand &c = cands()[ch.cand];
     const MixArgs M = mix_args(b[0], c, A);
     if ((int64_t)M.items * 8 > 0x7fffffff)
         return fail(S4_EINVAL, "too many work items");
-    return launch_mixed_fields(ctx, c, M, nfield, g, out, (hipStream_t)stream);
+    OnlineTimer tm(ctx, ch, (hipStream_t)stream);
+    if ((r = launch_mixed_fields(ctx, c, M, nfield, g, out, (hipStream_t)stream)))
+        return r;
+    tm.stop((double)nfield);
+    return S4_OK;
 }
 
 // RK4 stage tables for all boxes: stage s reads u_s (stencil) and writes the
@@ -839,6 +1147,9 @@ static std::string graph_key(const s4_box *b, int nbox, double *const *u, double
     return o.str();
 }
 
+static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                   const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s);
+
 int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho, const double *const *c2,
            double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream)
 {
@@ -881,6 +1192,19 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
 
     hipStream_t s = (hipStream_t)stream;
     const Choice ch = choose(ctx, S4_OP_RK4, b, nbox);
+    OnlineTimer tm(ctx, ch, s);
+    r = rk4_run(ctx, ch, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, s);
+    if (r)
+        return r;
+    tm.stop((double)nsteps);
+    return S4_OK;
+}
+
+// the launches of s4_rk4 for choice ch (arguments already validated)
+static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                   const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s)
+{
+    int r;
     char *ws = (char *)workspace;
     if (cands()[ch.cand].variant == 1 && nbox == 1) {
         // fused stage pairs: pairs of steps, an odd last step with the stage kernels
@@ -1028,7 +1352,9 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
         all.push_back(w);
     if ((r = check_disjoint(wr, all)))
         return r;
-    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_RHS, b, nbox).cand];
+    const Choice ch = choose(ctx, S4_OP_ADJOINT_RHS, b, nbox);
+    const Cand &c = cands()[ch.cand];
+    OnlineTimer tm(ctx, ch, (hipStream_t)stream);
     StageCoef K{};
     K.scale = 1.0;
     for (int i = 0; i < nbox; ++i) {
@@ -1041,6 +1367,7 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
         if ((r = launch_one(ctx, OP_ADJRHS, c, D, K, (hipStream_t)stream)))
             return r;
     }
+    tm.stop(1.0);
     return S4_OK;
 }
 
@@ -1151,9 +1478,14 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
     if ((r = check_disjoint(wr, all)))
         return r;
 
-    const Cand &c = cands()[choose(ctx, S4_OP_ADJOINT_STEP, b, 1).cand];
-    return adjoint_step_launch(ctx, c, b[0], u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, (char *)workspace,
-                               (hipStream_t)stream);
+    const Choice ch = choose(ctx, S4_OP_ADJOINT_STEP, b, 1);
+    const Cand &c = cands()[ch.cand];
+    OnlineTimer tm(ctx, ch, (hipStream_t)stream);
+    if ((r = adjoint_step_launch(ctx, c, b[0], u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, (char *)workspace,
+                                 (hipStream_t)stream)))
+        return r;
+    tm.stop(1.0);
+    return S4_OK;
 }
 
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)

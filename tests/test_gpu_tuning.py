@@ -1,0 +1,70 @@
+"""Tuning on the device: the on-line hill climber reaches a setting close to
+the offline sweep's, and results do not depend on the settings it visits."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1308_1343_amd as S
+import workload as W
+from _gpu import host
+
+pytestmark = pytest.mark.gpu
+
+
+def time_choice(ctx, b, u, r, ws, cand, steps=8):
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
+    S.s4_rk4(ctx, b, [u], [r], None, 1e-6, 2, "graph", ws=ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(5):
+        e0.record()
+        S.s4_rk4(ctx, b, [u], [r], None, 1e-6, steps, "graph", ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / steps)
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    return sorted(ts)[2]
+
+
+def test_online_tuning_close_to_offline_sweep():
+    n, g = (128, 128, 128), 2
+    u, r = S.alloc_field(n, g, fill=0.25), S.alloc_field(n, g, fill=0.5)
+    b = S.box_of(u, g, 1 / 128)
+    ws = S.workspace(S.s4_workspace_size(b, S.S4_OP_RK4, S.S4_GRAPH))
+    on = S.Context(0)
+    S.s4_set_online_tuning(on, True, 0.0, 1)
+    for _ in range(80):
+        S.s4_rk4(on, b, [u], [r], None, 1e-6, 4, "graph", ws=ws)
+        torch.cuda.synchronize()  # let every timing come back before the next call
+    ch = S.s4_get_choice(on, S.S4_OP_RK4, b)
+    assert ch["tuned"] == 2
+    off = S.Context(0)
+    S.s4_tune(off, S.S4_OP_RK4, b, flags=1)
+    ref = S.s4_get_choice(off, S.S4_OP_RK4, b)
+    t_on = time_choice(off, b, u, r, ws, ch["candidate"])
+    t_off = time_choice(off, b, u, r, ws, ref["candidate"])
+    t_heur = time_choice(off, b, u, r, ws, S.s4_get_choice(S.Context(0), S.S4_OP_RK4, b)["candidate"])
+    assert t_on <= 1.15 * t_off, (ch, ref, t_on, t_off, t_heur)
+
+
+def test_results_independent_of_online_search():
+    d = W.wave_cube(40, 3, "gauss")
+    g = d["ghost"]
+
+    def run(ctx, calls):
+        u = S.alloc_field(d["n"], g, fill=0.0)
+        r = S.alloc_field(d["n"], g, fill=0.0)
+        S.interior(u, g).copy_(torch.from_numpy(d["u"]))
+        S.interior(r, g).copy_(torch.from_numpy(d["rho"]))
+        b = S.box_of(u, g, d["dx"])
+        for _ in range(calls):
+            S.s4_rk4(ctx, b, [u], [r], None, d["dt"], 2, "graph")
+            torch.cuda.synchronize()
+        return host(u), host(r)
+
+    on = S.Context(0)
+    S.s4_set_online_tuning(on, True, 0.3, 9)  # frequent restarts: many settings visited
+    a = run(on, 25)
+    ref = run(S.Context(0), 25)
+    np.testing.assert_array_equal(a[0], ref[0])
+    np.testing.assert_array_equal(a[1], ref[1])

@@ -1,0 +1,93 @@
+"""The on-line tuner's search (the paper's random-restart hill climbing,
+Sec. III-B), driven on the host against synthetic per-candidate costs
+through s4_online_simulate: it converges on a smooth landscape, leaves a
+local optimum only through random restarts, keeps the cost of its
+excursions small, tolerates timing noise and is deterministic per seed."""
+import numpy as np
+
+import paper_1308_1343_amd as S
+
+# the library's candidate list, in its order: one kernel per stage, then fused stage pairs
+CANDS = [(0, tx, nw, tz) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0, 64, 32, 16, 8)] + \
+        [(1, tx, nw, tz) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
+ORD_TX = {16: 0, 32: 1, 64: 2}
+ORD_NW = {4: 0, 8: 1, 16: 2}
+ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 0: 4}
+BOX = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
+
+
+def dist(a, b):
+    return abs(ORD_TX[a[1]] - ORD_TX[b[1]]) + abs(ORD_NW[a[2]] - ORD_NW[b[2]]) + abs(ORD_TZ[a[3]] - ORD_TZ[b[3]])
+
+
+def bowl(center, slope=0.05, other_variant=2.0):
+    c = CANDS[center]
+    return [1.0 + slope * dist(c, d) if d[0] == c[0] else other_variant for d in CANDS]
+
+
+def test_candidate_table_matches_library():
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), ncalls=3)
+    assert all(0 <= t < len(CANDS) for t in tr)
+    for op, n in ((S.S4_OP_WAVE_RHS, 30), (S.S4_OP_RK4, 42)):
+        tr = S.s4_online_simulate(op, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400, restart_prob=0.2)
+        assert max(tr) < n  # fused stage pairs only for single-box RK4
+
+
+def test_converges_on_a_smooth_landscape():
+    target = CANDS.index((0, 16, 4, 32))
+    cost = bowl(target)
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=120)
+    assert tr[0] != target
+    assert all(t == target for t in tr[-30:])
+    # hill climbing: it walks, it does not enumerate all candidates
+    assert len(set(tr)) < 30
+
+
+def test_restarts_escape_a_local_optimum():
+    start = S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), ncalls=1)[0]
+    glob = CANDS.index((1, 32, 16, 16))
+    cost = [1.5] * len(CANDS)
+    cost[start] = 1.0  # an isolated local optimum at the starting setting
+    for i, d in enumerate(CANDS):  # a good basin around the global optimum
+        if d[0] == 1 and dist(d, CANDS[glob]) <= 1:
+            cost[i] = 0.75
+    cost[glob] = 0.7
+    stuck = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=500)
+    assert all(t == start for t in stuck[-100:])
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.05, seed=3, ncalls=3000)
+    assert np.mean([t == glob for t in tr[-300:]]) > 0.85
+
+
+def test_excursions_are_cheap():
+    target = CANDS.index((1, 64, 16, 64))
+    cost = bowl(target, slope=0.3, other_variant=3.0)
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.02, seed=5, ncalls=4000)
+    steady = np.mean([cost[t] for t in tr[-2000:]])
+    assert steady <= 1.05 * cost[target]  # random restarts cost at most a few per cent
+
+
+def test_noise_tolerance_and_determinism():
+    target = CANDS.index((0, 32, 8, 16))
+    cost = bowl(target, slope=0.1)
+    a = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, noise=0.03, restart_prob=0.01, seed=7, ncalls=600)
+    b = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, noise=0.03, restart_prob=0.01, seed=7, ncalls=600)
+    assert a == b
+    final = max(set(a[-100:]), key=a[-100:].count)
+    assert cost[final] <= 1.05 * cost[target]
+
+
+def test_simulation_rejects_bad_arguments():
+    import pytest
+    with pytest.raises(S.Sten4Error):
+        S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * 5, ncalls=3)
+    with pytest.raises(S.Sten4Error):
+        S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), noise=2.0, ncalls=3)
+
+
+def test_moves_between_kernel_sets():
+    """A per-stage basin whose best z chunk (8) has no fused-pair counterpart
+    must still lead to a better fused-pair setting without random restarts."""
+    stage_best, pair_best = (0, 32, 8, 8), (1, 32, 16, 16)
+    cost = [(1.0 + 0.05 * dist(d, stage_best)) if d[0] == 0 else (0.85 + 0.05 * dist(d, pair_best)) for d in CANDS]
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=200)
+    assert all(CANDS[t] == pair_best for t in tr[-30:])
