@@ -79,6 +79,17 @@ extern "C" {
 #define S4_OP_DERIV_MIXED 4
 #define S4_OP_ADJOINT_RHS 5
 #define S4_OP_ADJOINT_STEP 6
+#define S4_OP_LEVEL_SYNC 7
+
+/* bboxset operations (s4_bset_op) */
+#define S4_SET_UNION 0
+#define S4_SET_INTERSECTION 1
+#define S4_SET_DIFFERENCE 2
+#define S4_SET_SYMDIFF 3
+
+/* ghost-exchange shapes (s4_level_create) */
+#define S4_SYNC_FULL 0  /* the whole ghost shell of the given width: faces, edges, corners */
+#define S4_SYNC_FACES 1 /* only points beside a face (what axis-aligned stencils read) */
 
 typedef struct s4_ctx s4_ctx;
 
@@ -242,6 +253,131 @@ int s4_set_online_tuning(s4_ctx *ctx, int enable, double restart_prob, uint64_t 
  * candidate used at each of the ncalls calls to trace.  No device call. */
 int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, int ncost, double noise,
                        double restart_prob, uint64_t seed, int lag, int ncalls, int *trace);
+
+/* ---------------------------------------------------------------------------
+ * bboxsets (Sec. II-B, II-C).  A bboxset is a set of points of the integer
+ * grid Z^dim, dim = 1, 2 or 3, held on the host as its discrete derivative:
+ * along the last axis, the coordinates where the (dim-1)-dimensional
+ * cross-section changes and each change (the xor of the sections on both
+ * sides), recursively down to single booleans.  The derivative is the
+ * leftward mod-2 difference d_a R(p) = R(p) xor R(p - e_a); the set is
+ * recovered by xor-scanning each axis from low to high coordinates.  The
+ * fully unrolled derivative d_0 d_1 ... R of one bbox is its 2^dim corners
+ * (8 for a cuboid); an L-shaped 2D region has 6.  These "key points" are
+ * what is stored.  Set operations sweep the last axis as in the paper's
+ * traversal algorithm (Fig. 2) and recurse on cross-sections.
+ *
+ * Boxes are half-open: box k of an array spans lo[k*dim + a] <= p[a] <
+ * hi[k*dim + a]; a box with hi <= lo on any axis is empty.  Coordinates must
+ * satisfy |c| <= 2^40.  Handles are owned by the caller and freed with
+ * s4_bset_free; every function leaves its inputs unchanged and returns
+ * S4_OK or S4_EINVAL (NULL argument, bad dim/op/axis, coordinate out of
+ * range, mismatched dims, a point count beyond int64).  No device call. */
+typedef struct s4_bset s4_bset;
+
+/* The union of nbox boxes (nbox == 0: the empty set). */
+int s4_bset_from_boxes(int dim, const int64_t *lo, const int64_t *hi, int64_t nbox, s4_bset **out);
+
+/* Free a set; NULL is ignored. */
+void s4_bset_free(s4_bset *s);
+
+/* out = a op b, op one of S4_SET_UNION, S4_SET_INTERSECTION,
+ * S4_SET_DIFFERENCE (a minus b), S4_SET_SYMDIFF. */
+int s4_bset_op(int op, const s4_bset *a, const s4_bset *b, s4_bset **out);
+
+/* out = a moved by the vector v (dim entries): p in out iff p - v in a. */
+int s4_bset_shift(const s4_bset *a, const int64_t *v, s4_bset **out);
+
+/* out = every point of a grown by lo[k] points downward and hi[k] upward
+ * along axis k (lo, hi >= 0, <= 2^20): the Minkowski sum with [-lo, hi]. */
+int s4_bset_expand(const s4_bset *a, const int64_t *lo, const int64_t *hi, s4_bset **out);
+
+/* out = d_axis a = a xor (a moved by +e_axis). */
+int s4_bset_derivative(const s4_bset *a, int axis, s4_bset **out);
+
+/* info[0] dim, info[1] number of points, info[2] number of key points (of
+ * the full derivative), info[3] number of boxes s4_bset_boxes returns. */
+int s4_bset_info(const s4_bset *a, int64_t info[4]);
+
+/* The key points, dim coordinates each, in lexicographic order of
+ * (last axis, ..., axis 0); writes min(count, max) points to out and the
+ * total to *count. */
+int s4_bset_keys(const s4_bset *a, int64_t *out, int64_t max, int64_t *count);
+
+/* Pairwise disjoint boxes whose union is a (one run of boxes per interval
+ * of constant cross-section along the last axis, recursively); writes
+ * min(count, max) boxes to lo/hi (dim entries each) and the total to *count. */
+int s4_bset_boxes(const s4_bset *a, int64_t *lo, int64_t *hi, int64_t max, int64_t *count);
+
+/* *out = 1 if point p (dim entries) is in a, else 0. */
+int s4_bset_contains(const s4_bset *a, const int64_t *p, int *out);
+
+/* *out = 1 if a and b hold the same points (same dim), else 0. */
+int s4_bset_equal(const s4_bset *a, const s4_bset *b, int *out);
+
+/* ---------------------------------------------------------------------------
+ * One refinement level as a set of boxes that fill each other's ghost zones
+ * (Sec. II: ghost zones hold copies of neighbouring points; on one level
+ * they come from the boxes beside them).  Box i's interior occupies the
+ * global index range [lo[3i+a], lo[3i+a] + b[i].n[a]) on axis a; interiors
+ * must not overlap and all boxes share one grid spacing.  domain[a] > 0
+ * makes axis a periodic with that extent (every box then lies inside
+ * [0, domain[a]) and a point p stands for p mod domain[a]); domain[a] == 0
+ * leaves it open (ghost points beyond the level stay uncovered, for the
+ * physical boundary or a coarser level to fill).
+ *
+ * s4_level_create builds, on the host, the exchange schedule of `width`
+ * ghost layers (1 <= width <= every box's ghost) in shape S4_SYNC_FULL or
+ * S4_SYNC_FACES with the bboxset algebra: per box, the ghost region it needs
+ * (the grown interior minus the interior), intersected with every other
+ * box's interior and its periodic images, cut into disjoint copy pieces.
+ * Returns S4_EINVAL for inconsistent boxes (overlap, outside the periodic
+ * domain, spacings differ, width > a periodic extent), S4_EGHOST for a
+ * width outside [1, ghost], and the codes of s4_check_boxes.  The level is
+ * a host object owned by the caller (s4_level_destroy); it keeps copies of
+ * the boxes and origins. */
+typedef struct s4_level s4_level;
+
+int s4_level_create(const s4_box *b, const int64_t *lo, int nbox, const int64_t domain[3], int width, int shape,
+                    s4_level **out);
+
+void s4_level_destroy(s4_level *L);
+
+/* info[0] boxes, info[1] copy pieces, info[2] ghost points the exchange
+ * fills, info[3] ghost points of the requested shape that no box covers,
+ * info[4] interior points of the level, info[5] width, info[6] shape. */
+int s4_level_info(const s4_level *L, int64_t info[7]);
+
+/* The copy pieces: 11 int64 each, (dst box, src box, dst start x y z, src
+ * start x y z, extent x y z), starts in box-local interior coordinates
+ * (negative = ghost).  Writes min(count, max) pieces and the total to *count. */
+int s4_level_pieces(const s4_level *L, int64_t *out, int64_t max, int64_t *count);
+
+/* Workspace bytes of s4_level_sync (op S4_OP_LEVEL_SYNC) or s4_level_rk4
+ * (op S4_OP_RK4, any mode). */
+int s4_level_workspace_size(const s4_level *L, int op, size_t *bytes);
+
+/* Fill the ghost points of field f[i] of every box i by the level's
+ * schedule: each gets the value at the same grid point (periodically
+ * wrapped) in the interior of the box that owns it; ghost points no box
+ * covers are left as they are.  One kernel launch; interiors are only read.
+ * f[i] use box i's layout and must not overlap each other.  The schedule
+ * is copied into the caller's workspace (>= s4_level_workspace_size bytes,
+ * 256-byte aligned) and `stream` is synchronised once before the launch. */
+int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *workspace, size_t ws_bytes,
+                  void *stream);
+
+/* s4_rk4 on a level whose boxes are coupled through their ghost zones:
+ * before every evaluation of F the stage's u is exchanged by the level's
+ * schedule (which must cover every ghost point of its shape: S4_EGHOST
+ * otherwise, and have width >= 2), then the stage kernels read stencil
+ * neighbours from the ghost zones.  On a periodic level that tiles its
+ * domain the result equals s4_rk4 on one box spanning the domain.  u's
+ * ghost points are overwritten by the exchange; everything else as for
+ * s4_rk4 (modes, c2, in-place update, graph cache keyed additionally by
+ * the schedule). */
+int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,
+                 double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream);
 
 /* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned):
  * the streaming-copy probe that calibrates achievable HBM bandwidth and the

@@ -153,13 +153,20 @@ def disjoint_cover(boxes, chi, wlo):
 
 # --------------------------------------------------------------------------- one level of boxes
 
+def level_extent(lo, n, domain):
+    """Extent of the owner map: the periodic extent on periodic axes
+    (domain[a] > 0), the level's upper bound on open axes (domain[a] == 0)."""
+    return tuple(int(domain[a]) if domain[a] > 0 else max(l[a] + m[a] for l, m in zip(lo, n)) for a in range(3))
+
+
 def level_owner(lo, n, domain):
-    """Owner map of a level inside a periodic domain [0, domain): owner[x, y, z]
-    = index of the box whose interior holds the point, -1 where none does.
-    Boxes must lie inside the domain and must not overlap (AssertionError)."""
-    own = np.full(tuple(domain), -1, dtype=np.int64)
+    """Owner map of a level over [0, level_extent): owner[x, y, z] = index of
+    the box whose interior holds the point, -1 where none does.  Boxes must
+    lie inside [0, extent) and must not overlap (AssertionError)."""
+    ext = level_extent(lo, n, domain)
+    own = np.full(ext, -1, dtype=np.int64)
     for b, (l, m) in enumerate(zip(lo, n)):
-        assert all(0 <= l[a] and l[a] + m[a] <= domain[a] for a in range(3)), "box outside the domain"
+        assert all(0 <= l[a] and l[a] + m[a] <= ext[a] for a in range(3)), "box outside the domain"
         sl = tuple(slice(l[a], l[a] + m[a]) for a in range(3))
         assert (own[sl] < 0).all(), "boxes overlap"
         own[sl] = b
@@ -193,17 +200,23 @@ def sync_mask(n, g, width, shape):
 
 def sync_sources(lo, n, g, domain, width, shape):
     """For every box b, the map of its ghost points to their sources under a
-    same-level exchange on a periodic domain: a list of (ghost point local
-    coords, owner box, owner-local coords) for the points that some box's
-    interior covers, and the list of ghost points no box covers.  A ghost
-    point p of box b stands for the grid point (lo_b + p) mod domain."""
+    same-level exchange: arrays (ghost point local coords, owner box or -1,
+    owner-local coords).  A ghost point p of box b is the grid point
+    lo_b + p, taken modulo domain[a] on periodic axes (domain[a] > 0); on an
+    open axis (domain[a] == 0) a point outside the level's extent has no
+    owner."""
     own = level_owner(lo, n, domain)
+    ext = np.asarray(own.shape)
+    per = np.asarray([d > 0 for d in domain])
     out = []
     for b in range(len(lo)):
         m = sync_mask(n[b], g, width, shape)
         pts = np.argwhere(m) - g                      # local coords
-        glob = (pts + np.asarray(lo[b])) % np.asarray(domain)
-        who = own[glob[:, 0], glob[:, 1], glob[:, 2]]
+        glob = pts + np.asarray(lo[b])
+        glob = np.where(per, glob % np.where(per, ext, 1), glob)
+        inside = ((glob >= 0) & (glob < ext)).all(axis=1)
+        safe = np.where(inside[:, None], glob, 0)
+        who = np.where(inside, own[safe[:, 0], safe[:, 1], safe[:, 2]], -1)
         src = glob - np.asarray(lo)[np.maximum(who, 0)]
         out.append((pts, who, src))
     return out

@@ -26,13 +26,23 @@ LIB_PATH = os.path.join(_HERE, "libsten4.so")
 S4_OK, S4_EINVAL, S4_EGHOST, S4_ELAYOUT, S4_EALIAS, S4_EDEVICE, S4_ENOMEM, S4_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 S4_PERBOX, S4_BATCHED, S4_GRAPH = 0, 1, 2
 S4_OP_FILL, S4_OP_WAVE_RHS, S4_OP_RK4, S4_OP_DERIV_MIXED, S4_OP_ADJOINT_RHS, S4_OP_ADJOINT_STEP = 1, 2, 3, 4, 5, 6
+S4_OP_LEVEL_SYNC = 7
+S4_SET_UNION, S4_SET_INTERSECTION, S4_SET_DIFFERENCE, S4_SET_SYMDIFF = 0, 1, 2, 3
+SET_OPS = {"union": S4_SET_UNION, "intersection": S4_SET_INTERSECTION, "difference": S4_SET_DIFFERENCE,
+           "symmetric_difference": S4_SET_SYMDIFF}
+S4_SYNC_FULL, S4_SYNC_FACES = 0, 1
+SYNC_SHAPES = {"full": S4_SYNC_FULL, "faces": S4_SYNC_FACES}
 MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 
 # the entry points include/sten4.h declares
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
            "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
            "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
-           "s4_set_online_tuning", "s4_online_simulate", "s4_copy")
+           "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
+           "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
+           "s4_bset_derivative", "s4_bset_info", "s4_bset_keys", "s4_bset_boxes", "s4_bset_contains",
+           "s4_bset_equal", "s4_level_create", "s4_level_destroy", "s4_level_info", "s4_level_pieces",
+           "s4_level_workspace_size", "s4_level_sync", "s4_level_rk4")
 
 
 class S4Box(ctypes.Structure):
@@ -84,8 +94,29 @@ def lib():
     L.s4_set_online_tuning.argtypes = [vp, i, d, ctypes.c_uint64]
     L.s4_online_simulate.argtypes = [i, BP, i, ctypes.POINTER(d), i, d, d, ctypes.c_uint64, i, i,
                                      ctypes.POINTER(i)]
+    I64P = ctypes.POINTER(ctypes.c_int64)
+    L.s4_bset_from_boxes.argtypes = [i, I64P, I64P, ctypes.c_int64, ctypes.POINTER(vp)]
+    L.s4_bset_free.argtypes = [vp]
+    L.s4_bset_free.restype = None
+    L.s4_bset_op.argtypes = [i, vp, vp, ctypes.POINTER(vp)]
+    L.s4_bset_shift.argtypes = [vp, I64P, ctypes.POINTER(vp)]
+    L.s4_bset_expand.argtypes = [vp, I64P, I64P, ctypes.POINTER(vp)]
+    L.s4_bset_derivative.argtypes = [vp, i, ctypes.POINTER(vp)]
+    L.s4_bset_info.argtypes = [vp, I64P]
+    L.s4_bset_keys.argtypes = [vp, I64P, ctypes.c_int64, I64P]
+    L.s4_bset_boxes.argtypes = [vp, I64P, I64P, ctypes.c_int64, I64P]
+    L.s4_bset_contains.argtypes = [vp, I64P, ctypes.POINTER(i)]
+    L.s4_bset_equal.argtypes = [vp, vp, ctypes.POINTER(i)]
+    L.s4_level_create.argtypes = [BP, I64P, i, I64P, i, i, ctypes.POINTER(vp)]
+    L.s4_level_destroy.argtypes = [vp]
+    L.s4_level_destroy.restype = None
+    L.s4_level_info.argtypes = [vp, I64P]
+    L.s4_level_pieces.argtypes = [vp, I64P, ctypes.c_int64, I64P]
+    L.s4_level_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
+    L.s4_level_sync.argtypes = [vp, vp, PP, vp, sz, vp]
+    L.s4_level_rk4.argtypes = [vp, vp, PP, PP, PP, d, i, i, vp, sz, vp]
     for name in EXPORTS:
-        if name not in ("s4_destroy", "s4_last_error"):
+        if name not in ("s4_destroy", "s4_last_error", "s4_bset_free", "s4_level_destroy"):
             getattr(L, name).restype = i
     _lib = L
     return L
@@ -316,6 +347,164 @@ def s4_online_simulate(op, boxes, cost, noise=0.0, restart_prob=0.02, seed=1, la
 def s4_copy(ctx, dst, src, nbytes=None, stream=None):
     nb = dst.numel() * dst.element_size() if nbytes is None else int(nbytes)
     _check(lib().s4_copy(ctx.handle, _ptr(dst), _ptr(src), nb, _stream(stream)))
+
+
+# --------------------------------------------------------------------------- bboxsets and levels
+
+def _i64(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int64 * max(1, len(vals)))(*vals)
+
+
+class BSet:
+    """Owner of an s4_bset handle (freed with the object)."""
+
+    def __init__(self, handle, dim):
+        self.handle = handle
+        self.dim = dim
+        self._free = lib().s4_bset_free  # kept: module globals may be gone at interpreter exit
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._free(h)
+            self.handle = None
+
+
+def _new_bset(fn, dim, *args):
+    h = ctypes.c_void_p()
+    _check(fn(*args, ctypes.byref(h)))
+    return BSet(h, dim)
+
+
+def s4_bset_from_boxes(dim, boxes) -> BSet:
+    """boxes: iterable of (lo, hi) half-open integer boxes of `dim` coordinates."""
+    boxes = list(boxes)
+    lo = _i64([c for b in boxes for c in b[0]])
+    hi = _i64([c for b in boxes for c in b[1]])
+    return _new_bset(lib().s4_bset_from_boxes, dim, int(dim), lo, hi, len(boxes))
+
+
+def s4_bset_op(op, a: BSet, b: BSet) -> BSet:
+    return _new_bset(lib().s4_bset_op, a.dim, int(SET_OPS.get(op, op)), a.handle, b.handle)
+
+
+def s4_bset_shift(a: BSet, v) -> BSet:
+    return _new_bset(lib().s4_bset_shift, a.dim, a.handle, _i64(v))
+
+
+def s4_bset_expand(a: BSet, lo, hi) -> BSet:
+    return _new_bset(lib().s4_bset_expand, a.dim, a.handle, _i64(lo), _i64(hi))
+
+
+def s4_bset_derivative(a: BSet, axis) -> BSet:
+    return _new_bset(lib().s4_bset_derivative, a.dim, a.handle, int(axis))
+
+
+def s4_bset_info(a: BSet) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().s4_bset_info(a.handle, out))
+    return dict(zip(("dim", "points", "keys", "boxes"), list(out)))
+
+
+def s4_bset_keys(a: BSet) -> list:
+    cnt = ctypes.c_int64()
+    _check(lib().s4_bset_keys(a.handle, None, 0, ctypes.byref(cnt)))
+    out = (ctypes.c_int64 * max(1, cnt.value * a.dim))()
+    _check(lib().s4_bset_keys(a.handle, out, cnt.value, ctypes.byref(cnt)))
+    return [tuple(out[k * a.dim:(k + 1) * a.dim]) for k in range(cnt.value)]
+
+
+def s4_bset_boxes(a: BSet) -> list:
+    cnt = ctypes.c_int64()
+    _check(lib().s4_bset_boxes(a.handle, None, None, 0, ctypes.byref(cnt)))
+    lo = (ctypes.c_int64 * max(1, cnt.value * a.dim))()
+    hi = (ctypes.c_int64 * max(1, cnt.value * a.dim))()
+    _check(lib().s4_bset_boxes(a.handle, lo, hi, cnt.value, ctypes.byref(cnt)))
+    d = a.dim
+    return [(tuple(lo[k * d:(k + 1) * d]), tuple(hi[k * d:(k + 1) * d])) for k in range(cnt.value)]
+
+
+def s4_bset_contains(a: BSet, p) -> bool:
+    out = ctypes.c_int()
+    _check(lib().s4_bset_contains(a.handle, _i64(p), ctypes.byref(out)))
+    return bool(out.value)
+
+
+def s4_bset_equal(a: BSet, b: BSet) -> bool:
+    out = ctypes.c_int()
+    _check(lib().s4_bset_equal(a.handle, b.handle, ctypes.byref(out)))
+    return bool(out.value)
+
+
+class Level:
+    """Owner of an s4_level handle (freed with the object) and the boxes it was built for."""
+
+    def __init__(self, handle, boxes):
+        self.handle = handle
+        self.boxes = boxes
+        self._free = lib().s4_level_destroy
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._free(h)
+            self.handle = None
+
+
+def s4_level_create(boxes, lo, domain, width, shape="faces") -> Level:
+    """boxes: s4_box descriptors; lo: global (x, y, z) origin of each interior;
+    domain: periodic extents (0 = open axis)."""
+    arr, n = _boxes(boxes)
+    h = ctypes.c_void_p()
+    _check(lib().s4_level_create(arr, _i64([c for l in lo for c in l]), n, _i64(domain), int(width),
+                                 int(SYNC_SHAPES.get(shape, shape)), ctypes.byref(h)))
+    return Level(h, list(boxes) if not isinstance(boxes, S4Box) else [boxes])
+
+
+def s4_level_destroy(level: Level):
+    level.__del__()
+
+
+def s4_level_info(level: Level) -> dict:
+    out = (ctypes.c_int64 * 7)()
+    _check(lib().s4_level_info(level.handle, out))
+    return dict(zip(("boxes", "pieces", "filled", "uncovered", "points", "width", "shape"), list(out)))
+
+
+def s4_level_pieces(level: Level) -> list:
+    """[(dst, src, dst start xyz, src start xyz, extent xyz)] in box-local interior coordinates."""
+    cnt = ctypes.c_int64()
+    _check(lib().s4_level_pieces(level.handle, None, 0, ctypes.byref(cnt)))
+    out = (ctypes.c_int64 * max(1, 11 * cnt.value))()
+    _check(lib().s4_level_pieces(level.handle, out, cnt.value, ctypes.byref(cnt)))
+    res = []
+    for k in range(cnt.value):
+        o = out[11 * k:11 * k + 11]
+        res.append((o[0], o[1], tuple(o[2:5]), tuple(o[5:8]), tuple(o[8:11])))
+    return res
+
+
+def s4_level_workspace_size(level: Level, op) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().s4_level_workspace_size(level.handle, int(op), ctypes.byref(out)))
+    return out.value
+
+
+def s4_level_sync(ctx, level: Level, f, ws=None, stream=None):
+    if ws is None:
+        ws = workspace(s4_level_workspace_size(level, S4_OP_LEVEL_SYNC), f[0].device)
+    _check(lib().s4_level_sync(ctx.handle, level.handle, _ptrs(f), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def s4_level_rk4(ctx, level: Level, u, rho, c2, dt, nsteps, mode=S4_GRAPH, ws=None, stream=None):
+    mode = MODES.get(mode, mode)
+    if ws is None:
+        ws = workspace(s4_level_workspace_size(level, S4_OP_RK4), u[0].device)
+    _check(lib().s4_level_rk4(ctx.handle, level.handle, _ptrs(u), _ptrs(rho), None if c2 is None else _ptrs(c2),
+                              float(dt), int(nsteps), int(mode), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
 
 
 lib()  # fail at import when the HIP library is missing: there is no other implementation

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsten4.so")
-SOURCES = [os.path.join(CSRC, "s4_kernels.hip"), os.path.join(CSRC, "s4_api.cpp")]
+SOURCES = [os.path.join(CSRC, "s4_kernels.hip"), os.path.join(CSRC, "s4_api.cpp"), os.path.join(CSRC, "s4_bboxset.cpp")]
 
 # -ffp-contract=off: only the explicit fma() calls in the kernels fuse, so all
 # tile shapes and launch modes round identically.  Packed-FP32 instructions

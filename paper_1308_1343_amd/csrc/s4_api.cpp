@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -26,6 +27,7 @@
 #include <string>
 #include <vector>
 
+#include "s4_bboxset.h"
 #include "s4_internal.h"
 #include "s4_launch.h"
 #include "sten4.h"
@@ -47,6 +49,19 @@ static int fail(int code, const char *fmt, ...)
     g_err = buf;
     return code;
 }
+
+namespace s4 {
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+} // namespace s4
 
 static int hip_fail(hipError_t e, const char *where)
 {
@@ -591,18 +606,19 @@ static int64_t dev_items(const DevBox &D)
     return (int64_t)D.tiles[0] * D.tiles[1] * D.tiles[2];
 }
 
-static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const StageCoef &K, hipStream_t s)
+static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const StageCoef &K, hipStream_t s,
+                      bool ghosted = false)
 {
     const int64_t items = dev_items(D);
-    hipError_t e = launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s);
+    hipError_t e = launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s, ghosted);
     if (e != hipSuccess)
         return hip_fail(e, "stencil launch");
     return S4_OK;
 }
 
-static int persistent_grid(s4_ctx *ctx, int op, const Cand &c, int64_t nitems)
+static int persistent_grid(s4_ctx *ctx, int op, const Cand &c, int64_t nitems, bool ghosted = false)
 {
-    int per = max_blocks_per_cu(op, c.tx, c.nw);
+    int per = max_blocks_per_cu(op, c.tx, c.nw, ghosted);
     if (per <= 0)
         per = 2;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
@@ -1052,21 +1068,37 @@ static StageCoef rk4_coef(int s, double dt)
     return K;
 }
 
-// launch the four stages of one RK4 step (batched: nbox > 1 and table in ws)
+// Ghost exchange run before every stage of a level's RK4 step: the device
+// piece table and one table of per-box stage-input pointers per stage.
+struct SyncArgs {
+    const SyncPiece *P;
+    int npiece, nblocks;
+    double *const *F; // 4 * nbox entries, stage-major
+};
+
+// launch the four stages of one RK4 step (batched: nbox > 1 and table in ws);
+// with sy, each stage first exchanges its input's ghosts and then reads them
 static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, int nbox, bool batched,
-                    DevBox *dtab, int *counters, int64_t nitems, double dt, hipStream_t s)
+                    DevBox *dtab, int *counters, int64_t nitems, double dt, hipStream_t s,
+                    const SyncArgs *sy = nullptr)
 {
+    const bool gh = sy != nullptr;
     for (int st = 0; st < 4; ++st) {
         const StageCoef K = rk4_coef(st, dt);
+        if (sy) {
+            hipError_t e = launch_sync(sy->P, sy->npiece, sy->F + (size_t)st * nbox, sy->nblocks, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "ghost exchange launch");
+        }
         if (batched) {
-            const int grid = persistent_grid(ctx, OP_STAGE, c, nitems);
+            const int grid = persistent_grid(ctx, OP_STAGE, c, nitems, gh);
             hipError_t e = launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox,
-                                                (int)nitems, counters + 2 * st, grid, K, s);
+                                                (int)nitems, counters + 2 * st, grid, K, s, gh);
             if (e != hipSuccess)
                 return hip_fail(e, "batched stage launch");
         } else {
             for (int i = 0; i < nbox; ++i) {
-                int r = launch_one(ctx, OP_STAGE, c, tab[(size_t)st * nbox + i], K, s);
+                int r = launch_one(ctx, OP_STAGE, c, tab[(size_t)st * nbox + i], K, s, gh);
                 if (r)
                     return r;
             }
@@ -1147,11 +1179,59 @@ static std::string graph_key(const s4_box *b, int nbox, double *const *u, double
     return o.str();
 }
 
+// Replay a captured piece of work nrep times on stream s.  The capture is
+// made once per key (recorded on the context's private stream) and cached
+// in the context; the cache is bounded by dropping every entry at 64.
+static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<int(hipStream_t)> &record, int nrep,
+                     hipStream_t s)
+{
+    GraphEntry ge;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->graphs.find(key);
+        if (it != ctx->graphs.end())
+            ge = it->second;
+    }
+    if (!ge.exec) {
+        S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        int r = record(ctx->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+        if (r) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ge.graph = g;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->graphs.size() >= 64) {
+            for (auto &kv : ctx->graphs) {
+                (void)hipGraphExecDestroy(kv.second.exec);
+                (void)hipGraphDestroy(kv.second.graph);
+            }
+            ctx->graphs.clear();
+        }
+        ctx->graphs[key] = ge;
+    }
+    for (int k = 0; k < nrep; ++k)
+        S4_HIP(hipGraphLaunch(ge.exec, s));
+    return S4_OK;
+}
+
 static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, double *const *u, double *const *rho,
                    const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s);
 
-int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho, const double *const *c2,
-           double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream)
+// argument checks shared by s4_rk4 and s4_level_rk4 (need: workspace bytes)
+static int rk4_check(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                     const double *const *c2, double dt, int nsteps, int mode, void *workspace, size_t ws_bytes,
+                     size_t need)
 {
     if (!ctx || !u || !rho)
         return fail(S4_EINVAL, "NULL argument");
@@ -1164,7 +1244,6 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
         return fail(S4_EINVAL, "nsteps < 0");
     if (mode < S4_PERBOX || mode > S4_GRAPH)
         return fail(S4_EINVAL, "unknown mode %d", mode);
-    size_t need = rk4_fields_bytes(b, nbox) + rk4_table_bytes(nbox);
     std::vector<Range> wr, all;
     for (int i = 0; i < nbox; ++i) {
         if ((r = check_ptr(u[i], "u", i)) || (r = check_ptr(rho[i], "rho", i)) ||
@@ -1187,9 +1266,18 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
     wr.push_back({workspace, need, "workspace", 0});
     for (auto &w : wr)
         all.push_back(w);
-    if ((r = check_disjoint(wr, all)))
-        return r;
+    return check_disjoint(wr, all);
+}
 
+int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho, const double *const *c2,
+           double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!b || nbox <= 0 || nbox > (1 << 20))
+        return check_boxes(b, nbox, S4_OP_RK4);
+    const size_t need = rk4_fields_bytes(b, nbox) + rk4_table_bytes(nbox);
+    int r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, ws_bytes, need);
+    if (r || nsteps == 0)
+        return r;
     hipStream_t s = (hipStream_t)stream;
     const Choice ch = choose(ctx, S4_OP_RK4, b, nbox);
     OnlineTimer tm(ctx, ch, s);
@@ -1219,40 +1307,12 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
                         return r;
             } else {
                 const std::string key = "pair|" + graph_key(b, nbox, u, rho, c2, dt, workspace, ch.cand, false);
-                GraphEntry ge;
-                {
-                    std::lock_guard<std::mutex> lk(ctx->mu);
-                    auto it = ctx->graphs.find(key);
-                    if (it != ctx->graphs.end())
-                        ge = it->second;
-                }
-                if (!ge.exec) {
-                    S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-                    r = rk4_pair_double_step(ctx, cp, b[0], u[0], rho[0], c2b, W, dt, ctx->cap);
-                    hipGraph_t g = nullptr;
-                    hipError_t e = hipStreamEndCapture(ctx->cap, &g);
-                    if (r)
-                        return r;
-                    if (e != hipSuccess)
-                        return hip_fail(e, "hipStreamEndCapture");
-                    e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
-                    if (e != hipSuccess) {
-                        (void)hipGraphDestroy(g);
-                        return hip_fail(e, "hipGraphInstantiate");
-                    }
-                    ge.graph = g;
-                    std::lock_guard<std::mutex> lk(ctx->mu);
-                    if (ctx->graphs.size() >= 64) {
-                        for (auto &kv : ctx->graphs) {
-                            (void)hipGraphExecDestroy(kv.second.exec);
-                            (void)hipGraphDestroy(kv.second.graph);
-                        }
-                        ctx->graphs.clear();
-                    }
-                    ctx->graphs[key] = ge;
-                }
-                for (int k = 0; k < pairs; ++k)
-                    S4_HIP(hipGraphLaunch(ge.exec, s));
+                r = graph_run(
+                    ctx, key,
+                    [&](hipStream_t cs) { return rk4_pair_double_step(ctx, cp, b[0], u[0], rho[0], c2b, W, dt, cs); },
+                    pairs, s);
+                if (r)
+                    return r;
             }
         }
         if (nsteps % 2 == 0)
@@ -1288,41 +1348,10 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
         return S4_OK;
     }
     const std::string key = graph_key(b, nbox, u, rho, c2, dt, workspace, ch.cand, batched);
-    GraphEntry ge;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->graphs.find(key);
-        if (it != ctx->graphs.end())
-            ge = it->second;
-    }
-    if (!ge.exec) {
-        S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-        r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, ctx->cap);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(ctx->cap, &g);
-        if (r)
-            return r;
-        if (e != hipSuccess)
-            return hip_fail(e, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        ge.graph = g;
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->graphs.size() >= 64) { // bounded cache: drop every captured step
-            for (auto &kv : ctx->graphs) {
-                (void)hipGraphExecDestroy(kv.second.exec);
-                (void)hipGraphDestroy(kv.second.graph);
-            }
-            ctx->graphs.clear();
-        }
-        ctx->graphs[key] = ge;
-    }
-    for (int step = 0; step < nsteps; ++step)
-        S4_HIP(hipGraphLaunch(ge.exec, s));
-    return S4_OK;
+    return graph_run(
+        ctx, key,
+        [&](hipStream_t cs) { return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, cs); }, nsteps,
+        s);
 }
 
 int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *lu,
@@ -1486,6 +1515,186 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
         return r;
     tm.stop(1.0);
     return S4_OK;
+}
+
+// ---------------------------------------------------------------------------
+// level: ghost exchange between the boxes of one refinement level
+
+static size_t sync_pieces_bytes(const s4_level *L)
+{
+    return round256(std::max<size_t>(1, L->pieces.size()) * sizeof(SyncPiece));
+}
+
+static size_t ptr_table_bytes(int nbox, int ntab)
+{
+    return round256((size_t)ntab * nbox * sizeof(double *));
+}
+
+// device form of the schedule; returns the launch's workgroup count (< 0: too large)
+static int64_t sync_table(const s4_level *L, std::vector<SyncPiece> &out)
+{
+    out.clear();
+    int64_t blk = 0;
+    for (const LevelPiece &P : L->pieces) {
+        const s4_box &d = L->boxes[(size_t)P.dst], &sb = L->boxes[(size_t)P.src];
+        SyncPiece q;
+        memset(&q, 0, sizeof q);
+        q.dst = P.dst;
+        q.src = P.src;
+        for (int a = 0; a < 3; ++a)
+            q.n[a] = (int32_t)P.n[a];
+        q.blk0 = (int32_t)blk;
+        q.doff = (P.d0[0] + d.ghost) + (P.d0[1] + d.ghost) * d.stride[1] + (P.d0[2] + d.ghost) * d.stride[2];
+        q.soff = (P.s0[0] + sb.ghost) + (P.s0[1] + sb.ghost) * sb.stride[1] + (P.s0[2] + sb.ghost) * sb.stride[2];
+        q.dsy = d.stride[1];
+        q.dsz = d.stride[2];
+        q.ssy = sb.stride[1];
+        q.ssz = sb.stride[2];
+        out.push_back(q);
+        blk += (P.n[0] * P.n[1] * P.n[2] + 255) / 256;
+        if (blk > 0x7fffffff)
+            return -1;
+    }
+    return blk;
+}
+
+static int level_check(const s4_level *L)
+{
+    if (!L)
+        return fail(S4_EINVAL, "level is NULL");
+    return check_boxes(L->boxes.data(), (int)L->boxes.size(), S4_OP_RK4);
+}
+
+int s4_level_workspace_size(const s4_level *L, int op, size_t *bytes)
+{
+    if (!bytes)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = level_check(L);
+    if (r)
+        return r;
+    const int nbox = (int)L->boxes.size();
+    if (op == S4_OP_LEVEL_SYNC)
+        *bytes = sync_pieces_bytes(L) + ptr_table_bytes(nbox, 1);
+    else if (op == S4_OP_RK4)
+        *bytes = rk4_fields_bytes(L->boxes.data(), nbox) + rk4_table_bytes(nbox) + sync_pieces_bytes(L) +
+                 ptr_table_bytes(nbox, 4);
+    else
+        return fail(S4_EINVAL, "op %d has no level workspace", op);
+    return S4_OK;
+}
+
+int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !f)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = level_check(L);
+    if (r)
+        return r;
+    const int nbox = (int)L->boxes.size();
+    std::vector<Range> wr;
+    for (int i = 0; i < nbox; ++i) {
+        if ((r = check_ptr(f[i], "f", i)))
+            return r;
+        wr.push_back({f[i], (size_t)box_elems(L->boxes[(size_t)i]) * 8, "f", i});
+    }
+    const size_t need = sync_pieces_bytes(L) + ptr_table_bytes(nbox, 1);
+    if (!workspace)
+        return fail(S4_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255)
+        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    std::vector<Range> all = wr;
+    all.push_back({workspace, need, "workspace", 0});
+    wr.push_back(all.back());
+    if ((r = check_disjoint(wr, all)))
+        return r;
+    std::vector<SyncPiece> tab;
+    const int64_t nblocks = sync_table(L, tab);
+    if (nblocks < 0)
+        return fail(S4_EINVAL, "ghost exchange too large for one launch");
+    if (tab.empty())
+        return S4_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<char> bytes(need, 0);
+    memcpy(bytes.data(), tab.data(), tab.size() * sizeof(SyncPiece));
+    memcpy(bytes.data() + sync_pieces_bytes(L), f, (size_t)nbox * sizeof(double *));
+    if ((r = upload_table(workspace, bytes, s)))
+        return r;
+    const SyncPiece *P = (const SyncPiece *)workspace;
+    double *const *F = (double *const *)((char *)workspace + sync_pieces_bytes(L));
+    hipError_t e = launch_sync(P, (int)tab.size(), F, (int)nblocks, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "ghost exchange launch");
+    return S4_OK;
+}
+
+int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,
+                 double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream)
+{
+    int r = level_check(L);
+    if (r)
+        return r;
+    const s4_box *b = L->boxes.data();
+    const int nbox = (int)L->boxes.size();
+    if (L->width < 2)
+        return fail(S4_EGHOST, "level exchange width %d < 2 (stencil radius)", L->width);
+    if (L->uncovered > 0)
+        return fail(S4_EGHOST, "%lld ghost points of the level are not covered by any box",
+                    (long long)L->uncovered);
+    size_t need = 0;
+    if ((r = s4_level_workspace_size(L, S4_OP_RK4, &need)))
+        return r;
+    if ((r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, ws_bytes, need)) || nsteps == 0)
+        return r;
+    hipStream_t s = (hipStream_t)stream;
+    // the per-stage kernel set only (the fused pairs wrap around one box)
+    int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
+    if (cands()[ci].variant != 0)
+        ci = heuristic(ctx, b, nbox);
+    const Cand &c = cands()[ci];
+    char *ws = (char *)workspace;
+    std::vector<DevBox> tab;
+    rk4_tables(b, nbox, u, rho, c2, ws, c, tab);
+    int64_t nitems = 0;
+    for (int i = 0; i < nbox; ++i)
+        nitems += dev_items(tab[i]);
+    if (nitems > 0x3fffffff)
+        return fail(S4_EINVAL, "too many work items");
+    std::vector<SyncPiece> pieces;
+    const int64_t nblocks = sync_table(L, pieces);
+    if (nblocks < 0)
+        return fail(S4_EINVAL, "ghost exchange too large for one launch");
+
+    // [stage tables | item counters | exchange pieces | stage-input pointers], uploaded at once
+    const size_t tb = rk4_table_bytes(nbox), pb = sync_pieces_bytes(L), fb = ptr_table_bytes(nbox, 4);
+    char *dbase = ws + rk4_fields_bytes(b, nbox);
+    std::vector<char> bytes(tb + pb + fb, 0);
+    memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+    memcpy(bytes.data() + tb, pieces.data(), pieces.size() * sizeof(SyncPiece));
+    double **F = (double **)(bytes.data() + tb + pb);
+    for (int st = 0; st < 4; ++st)
+        for (int i = 0; i < nbox; ++i)
+            F[(size_t)st * nbox + i] = const_cast<double *>(tab[(size_t)st * nbox + i].in);
+    if ((r = upload_table(dbase, bytes, s)))
+        return r;
+    DevBox *dtab = (DevBox *)dbase;
+    int *counters = (int *)(dbase + round256(4 * (size_t)nbox * sizeof(DevBox)));
+    const SyncArgs sy{(const SyncPiece *)(dbase + tb), (int)pieces.size(), (int)nblocks,
+                      (double *const *)(dbase + tb + pb)};
+    const bool batched = nbox > 1 && mode != S4_PERBOX;
+    if (mode != S4_GRAPH) {
+        for (int step = 0; step < nsteps; ++step)
+            if ((r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s, &sy)))
+                return r;
+        return S4_OK;
+    }
+    const std::string key = "level|" + std::to_string(L->serial) + "|" +
+                            graph_key(b, nbox, u, rho, c2, dt, workspace, ci, batched);
+    return graph_run(
+        ctx, key,
+        [&](hipStream_t cs) { return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, cs, &sy); },
+        nsteps, s);
 }
 
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)

@@ -339,6 +339,18 @@ S4_HD inline int wrap_index(int p, int n)
     return r < 0 ? r + n : r;
 }
 
+// One copy piece of a level's ghost exchange as the sync kernel sees it:
+// n[0] x n[1] x n[2] points from field F[src] at element offset soff (then
+// strides ssy, ssz) to field F[dst] at doff (strides dsy, dsz).  The piece
+// owns workgroups blk0 .. blk0 + ceil(volume / 256) - 1 of the launch.
+struct SyncPiece {
+    int32_t dst, src;
+    int32_t n[3];
+    int32_t blk0;
+    int64_t doff, soff;
+    int64_t dsy, dsz, ssy, ssz;
+};
+
 // split a launch of `nblocks` workgroups so that the hardware's round-robin
 // placement (block b runs on XCD b % nxcd) gives each XCD a contiguous range
 // of logical items: neighbouring tiles then share that XCD's L2.

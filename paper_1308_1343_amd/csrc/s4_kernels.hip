@@ -591,6 +591,37 @@ __global__ __launch_bounds__(256) void k_fill_periodic(DevBox B)
 }
 
 // ---------------------------------------------------------------------------
+// level ghost exchange: every workgroup copies up to 256 points of one piece
+// (the piece whose block range holds blockIdx.x, found by a binary search
+// over the pieces' first blocks), x fastest so rows of a piece coalesce.
+// Sources are interior points and destinations ghost points, so the pieces
+// of one launch never read what another writes.
+
+__global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, int npiece,
+                                              double *const *__restrict__ F)
+{
+    const int blk = blockIdx.x;
+    int lo = 0, hi = npiece - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P[mid].blk0 <= blk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SyncPiece &q = P[lo];
+    const int64_t t = (int64_t)(blk - q.blk0) * 256 + threadIdx.x;
+    const int nx = q.n[0], ny = q.n[1];
+    if (t >= (int64_t)nx * ny * q.n[2])
+        return;
+    const int i = (int)(t % nx);
+    const int64_t r = t / nx;
+    const int j = (int)(r % ny), k = (int)(r / ny);
+    const double v = F[q.src][q.soff + i + j * q.ssy + k * q.ssz];
+    F[q.dst][q.doff + i + j * q.dsy + k * q.dsz] = v;
+}
+
+// ---------------------------------------------------------------------------
 // streaming copy probe (16-byte vectors, grid stride)
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -628,6 +659,7 @@ static hipError_t launch_batched_t(const DevBox *tab, int nbox, int nitems, int 
 #define S4_FOR_OPS(X, TX, NW)                                                                          \
     X(TX, NW, false, OP_RHS)                                                                           \
     X(TX, NW, true, OP_STAGE)                                                                          \
+    X(TX, NW, false, OP_STAGE)                                                                         \
     X(TX, NW, true, OP_ADJRHS)                                                                         \
     X(TX, NW, true, OP_FWDREC)                                                                         \
     X(TX, NW, true, OP_ADJSTAGE)
@@ -640,15 +672,17 @@ static hipError_t launch_batched_t(const DevBox *tab, int nbox, int nitems, int 
     S4_FOR_OPS(X, 16, 4)                                                                               \
     S4_FOR_OPS(X, 16, 8)
 
-static bool wrap_of(int op)
+// periodic addressing for every op but the RHS, unless the caller's ghost
+// zones hold the neighbours (a level whose boxes exchange ghosts)
+static bool wrap_of(int op, bool ghosted)
 {
-    return op != OP_RHS;
+    return op != OP_RHS && !ghosted;
 }
 
 hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const StageCoef &K, int nitems,
-                               int nxcd, hipStream_t s)
+                               int nxcd, hipStream_t s, bool ghosted)
 {
-    const bool wrap = wrap_of(op);
+    const bool wrap = wrap_of(op, ghosted);
 #define X(TX_, NW_, W_, O_)                                                                            \
     if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
         return launch_single_t<TX_, NW_, W_, O_>(B, K, nitems, nxcd, s);
@@ -658,9 +692,9 @@ hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const St
 }
 
 hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
-                                int *counter, int grid, const StageCoef &K, hipStream_t s)
+                                int *counter, int grid, const StageCoef &K, hipStream_t s, bool ghosted)
 {
-    const bool wrap = wrap_of(op);
+    const bool wrap = wrap_of(op, ghosted);
 #define X(TX_, NW_, W_, O_)                                                                            \
     if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
         return launch_batched_t<TX_, NW_, W_, O_>(tab, nbox, nitems, counter, grid, K, s);
@@ -669,9 +703,9 @@ hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int n
     return hipErrorInvalidValue;
 }
 
-int max_blocks_per_cu(int op, int tx, int nw)
+int max_blocks_per_cu(int op, int tx, int nw, bool ghosted)
 {
-    const bool wrap = wrap_of(op);
+    const bool wrap = wrap_of(op, ghosted);
     int nb = 0;
 #define X(TX_, NW_, W_, O_)                                                                            \
     if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_) {                                            \
@@ -730,6 +764,14 @@ hipError_t launch_fill(const DevBox &B, hipStream_t s)
     if (nblk > 0x7fffffff)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_periodic, dim3((unsigned)nblk), dim3(256), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_sync(const SyncPiece *P, int npiece, double *const *F, int nblocks, hipStream_t s)
+{
+    if (npiece <= 0 || nblocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_sync, dim3((unsigned)nblocks), dim3(256), 0, s, P, npiece, F);
     return hipGetLastError();
 }
 

@@ -8,18 +8,19 @@
 namespace s4 {
 
 // One box, one workgroup per work item (grid = nitems); nxcd > 1 spreads
-// contiguous item ranges over the XCDs.
+// contiguous item ranges over the XCDs.  ghosted: OP_STAGE reads stencil
+// neighbours from the stencil input's ghost zones instead of wrapping.
 hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const StageCoef &K, int nitems,
-                               int nxcd, hipStream_t s);
+                               int nxcd, hipStream_t s, bool ghosted = false);
 
 // All boxes of a device table in one persistent launch of `grid` workgroups
 // over a shared item counter (counter[0..1] must be zero before the first
 // launch; each launch leaves them zero).
 hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
-                                int *counter, int grid, const StageCoef &K, hipStream_t s);
+                                int *counter, int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
 
 // Resident workgroups per CU of the batched kernel for this shape (0 if unknown).
-int max_blocks_per_cu(int op, int tx, int nw);
+int max_blocks_per_cu(int op, int tx, int nw, bool ghosted = false);
 
 // Multi-field mixed-derivative kernel over fields [0, nfield) of M (nfield <= 8);
 // one workgroup per (field, tile) item.
@@ -32,6 +33,11 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
+
+// Level ghost exchange: npiece pieces (device table, blk0 ascending, piece 0
+// at block 0) over nblocks workgroups of 256 threads; F is a device table of
+// one field pointer per box.
+hipError_t launch_sync(const SyncPiece *P, int npiece, double *const *F, int nblocks, hipStream_t s);
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s);
 

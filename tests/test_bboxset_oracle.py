@@ -210,3 +210,14 @@ def test_level_owner_rejects_overlap():
         B.level_owner([(0, 0, 0), (1, 0, 0)], [(2, 2, 2), (2, 2, 2)], (4, 4, 4))
     with pytest.raises(AssertionError):
         B.level_owner([(3, 0, 0)], [(2, 2, 2)], (4, 4, 4))
+
+
+def test_sync_sources_open_axis_by_hand():
+    # the two-slab level with x open: the outer x faces have no source, the inner ones face each other
+    lo, n, dom = [(0, 0, 0), (4, 0, 0)], [(4, 4, 4), (4, 4, 4)], (0, 4, 4)
+    src = B.sync_sources(lo, n, 2, dom, 2, "faces")
+    t0 = {tuple(p): int(w) for p, w in zip(src[0][0], src[0][1])}
+    t1 = {tuple(p): int(w) for p, w in zip(src[1][0], src[1][1])}
+    assert t0[(-1, 0, 0)] == -1 and t0[(4, 0, 0)] == 1 and t0[(0, -1, 0)] == 0
+    assert t1[(4, 2, 2)] == -1 and t1[(-2, 3, 1)] == 0
+    assert sum(w == -1 for w in t0.values()) == 2 * 16 and sum(w == -1 for w in t1.values()) == 2 * 16

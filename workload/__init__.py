@@ -36,6 +36,7 @@ SEEDS = {
     "mixed192": 1308_2,
     "bboxset60": 1308_3,
     "adjoint128": 1308_4,
+    "level60": 1308_5,
 }
 
 
@@ -251,6 +252,59 @@ def bboxset(seed: int = SEEDS["bboxset60"], nlevels: int = 3, per_level: int = 2
         us.append(uniform_pm1(seed, 100 + 2 * i, (nz, ny, nx)))
         rhos.append(uniform_pm1(seed, 101 + 2 * i, (nz, ny, nx)))
     return dict(boxes=boxes, ghost=ghost, dt=0.25 * hmin, u=us, rho=rhos, seed=seed, nsteps=1)
+
+
+def _partition(seq: Sequence, total: int, parts: int, smin: int, smax: int):
+    """`parts` integer lengths in [smin, smax] that sum to `total`: the first
+    parts - 1 uniform, the last the remainder, all redrawn until it fits."""
+    for _ in range(100000):
+        lens = [seq.integer(smin, smax) for _ in range(parts - 1)]
+        last = total - sum(lens)
+        if smin <= last <= smax:
+            return lens + [last]
+    raise RuntimeError("no partition found")
+
+
+def level_tiling(seed: int = SEEDS["level60"], counts=(5, 4, 3), smin: int = 16, smax: int = 96,
+                 ghost: int = 3, domain=None, h: float = 1.0 / 256):
+    """One refinement level tiling a periodic domain with counts[0]*counts[1]*counts[2] boxes.
+
+    z is cut into counts[2] slabs, every slab's y extent into counts[1] rows
+    and every row's x extent into counts[0] boxes, each cut at seeded
+    positions with box sides in [smin, smax].  Cuts differ between slabs and
+    rows, so box faces meet in T-junctions and a ghost zone spans several
+    neighbours.  The domain defaults to counts * (smin + smax) / 2 points.
+    Spacing h on every axis, dt = h / 4.  u = U + S and rho = U' on the whole
+    domain, with U, U' uniform in [-1, 1) and S a sine mode of one period
+    along every axis of the domain; each box's interior is its slice.
+    Returns boxes (dicts with lo (x, y, z) and n), domain (x, y, z), ghost,
+    dx, dt and the global (z, y, x) arrays u, rho.
+    """
+    if domain is None:
+        domain = tuple(c * (smin + smax) // 2 for c in counts)
+    Nx, Ny, Nz = (int(v) for v in domain)
+    seq = Sequence(seed, 7)
+    boxes = []
+    z0 = 0
+    for lz in _partition(seq, Nz, counts[2], smin, smax):
+        y0 = 0
+        for ly in _partition(seq, Ny, counts[1], smin, smax):
+            x0 = 0
+            for lx in _partition(seq, Nx, counts[0], smin, smax):
+                boxes.append(dict(lo=(x0, y0, z0), n=(lx, ly, lz)))
+                x0 += lx
+            y0 += ly
+        z0 += lz
+    u = uniform_pm1(seed, 1, (Nz, Ny, Nx)) + sine_mode_111((Nx, Ny, Nz))
+    rho = uniform_pm1(seed, 2, (Nz, Ny, Nx))
+    return dict(boxes=boxes, domain=(Nx, Ny, Nz), ghost=ghost, dx=(h, h, h), dt=0.25 * h, u=u, rho=rho,
+                seed=seed)
+
+
+def box_slice(b):
+    """(z, y, x) slice of a global array holding box b's interior."""
+    (x, y, z), (nx, ny, nz) = b["lo"], b["n"]
+    return np.s_[z:z + nz, y:y + ny, x:x + nx]
 
 
 def _overlap(lo1, n1, lo2, n2):
