@@ -19,6 +19,11 @@ The same JSON line also reports, each on its own workload:
   batched  one RK4 step over a 60-box, 3-level bboxset (sides 16..96, 3
            ghosts) in per-box launches, one persistent batched launch per
            stage, and the batched step replayed as a hipGraph
+  level    60 boxes (sides 16..96, 3 ghosts) tiling a 280 x 224 x 168
+           periodic domain as one refinement level: the host build of the
+           ghost-exchange schedule with derivative bboxsets, one exchange,
+           and RK4 steps with an exchange before every stage in the three
+           launch modes, beside one box spanning the same domain
   adjoint  loss and gradient through 50 RK4 steps on a 128^3 box with
            variable c^2, checkpoint every 10 steps
 and, on rank 0 at N=1, the CPU oracle timed on a bounded sample.
@@ -75,7 +80,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--sections", default="rk4,tuning,rhs,copy,mixed,batched,adjoint,cpu")
+    ap.add_argument("--sections", default="rk4,tuning,rhs,copy,mixed,batched,level,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
     args = ap.parse_args()
@@ -169,8 +174,15 @@ def main():
         # and the offline sweep, each timed afterwards on the same data
         uu, rr = to_dev(d["u"]), to_dev(d["rho"])
         wst = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
-        heur = S.s4_get_choice(S.Context(0), S.S4_OP_RK4, box)["candidate"]
-        on = S.Context(0)
+        # fresh contexts that do not load the tuned choices: the heuristic start
+        # and the on-line search from that start
+        saved = os.environ.pop("S4_TUNE_CACHE", None)
+        try:
+            heur = S.s4_get_choice(S.Context(0), S.S4_OP_RK4, box)["candidate"]
+            on = S.Context(0)
+        finally:
+            if saved is not None:
+                os.environ["S4_TUNE_CACHE"] = saved
         S.s4_set_online_tuning(on, True, 0.02, 1)
         ncalls, spc = 60, 4
         torch.cuda.synchronize()
@@ -331,6 +343,81 @@ def main():
                           "launches_per_step": {"perbox": 4 * len(boxes), "batched": 4, "graph": 1}}
         log(f"[bench] batched: {out['batched']}")
         del fields, us_, rs_, wsb
+
+    # ------------------------------------------------------------------ level with ghost exchange
+    if "level" in sections:
+        ld = W.level_tiling()
+        gl = ld["ghost"]
+        lus, lrs, lboxes = [], [], []
+        for bx in ld["boxes"]:
+            sl = W.box_slice(bx)
+            fu = S.alloc_field(bx["n"], gl, fill=0.0)
+            fr = S.alloc_field(bx["n"], gl, fill=0.0)
+            S.interior(fu, gl).copy_(torch.from_numpy(np.ascontiguousarray(ld["u"][sl])))
+            S.interior(fr, gl).copy_(torch.from_numpy(np.ascontiguousarray(ld["rho"][sl])))
+            lus.append(fu)
+            lrs.append(fr)
+            lboxes.append(S.box_of(fu, gl, ld["dx"]))
+        llo = [bx["lo"] for bx in ld["boxes"]]
+        t0 = time.perf_counter()
+        lev = S.s4_level_create(lboxes, llo, ld["domain"], 2, "faces")
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        info = S.s4_level_info(lev)
+        lpts = info["points"]
+        if not args.no_tune:
+            S.s4_tune(ctx, S.S4_OP_RK4, lboxes, flags=1)
+            torch.cuda.empty_cache()
+        wsl = S.workspace(S.s4_level_workspace_size(lev, S.S4_OP_RK4))
+        kl = max(10, K // 5)
+        res = {}
+        for mode in ("perbox", "batched", "graph"):
+            S.s4_level_rk4(ctx, lev, lus, lrs, None, ld["dt"], 3, mode, ws=wsl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            S.s4_level_rk4(ctx, lev, lus, lrs, None, ld["dt"], kl, mode, ws=wsl)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            w_ = time.perf_counter() - t0
+            res[mode] = {"ms_per_step": round(w_ * 1e3 / kl, 4), "gpoint_steps_per_s": round(lpts * kl / w_ / 1e9, 2),
+                         "event_ms_per_step": round(e0.elapsed_time(e1) / kl, 4)}
+        # one exchange per call (the call uploads its schedule and synchronises first)
+        wss = S.workspace(S.s4_level_workspace_size(lev, S.S4_OP_LEVEL_SYNC))
+        S.s4_level_sync(ctx, lev, lus, ws=wss)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            S.s4_level_sync(ctx, lev, lus, ws=wss)
+        torch.cuda.synchronize()
+        sync_ms = (time.perf_counter() - t0) * 1e3 / 20
+        del wsl, wss, lus, lrs
+        torch.cuda.empty_cache()
+        # the same domain as one periodic box (no exchange: wrapped addressing)
+        one_u = S.alloc_field(ld["domain"], 2, fill=0.0)
+        one_r = S.alloc_field(ld["domain"], 2, fill=0.0)
+        S.interior(one_u, 2).copy_(torch.from_numpy(ld["u"]))
+        S.interior(one_r, 2).copy_(torch.from_numpy(ld["rho"]))
+        ob = S.box_of(one_u, 2, ld["dx"])
+        wso = S.s4_rk4(ctx, ob, [one_u], [one_r], None, ld["dt"], 4, "graph")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.s4_rk4(ctx, ob, [one_u], [one_r], None, ld["dt"], kl, "graph", ws=wso)
+        torch.cuda.synchronize()
+        one_ms = (time.perf_counter() - t0) * 1e3 / kl
+        del one_u, one_r, wso
+        ch = S.s4_get_choice(ctx, S.S4_OP_RK4, lboxes)
+        out["level"] = {"workload": "level60: 60 boxes, sides U[16,96], g=3, tiling a 280x224x168 periodic domain, "
+                                    "face exchange of width 2 before every RK4 stage",
+                        "interior_points": lpts, "steps": kl, "modes": res,
+                        "schedule_build_ms": round(plan_ms, 2), "schedule_pieces": info["pieces"],
+                        "ghost_points_per_exchange": info["filled"],
+                        "exchange_call_ms": round(sync_ms, 4),
+                        "exchange_bytes": 16 * info["filled"],
+                        "single_box_same_domain_ms_per_step": round(one_ms, 4),
+                        "level_graph_over_single_box": round(res["graph"]["ms_per_step"] / one_ms, 3),
+                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                        "launches_per_step": {"perbox": 4 * (len(lboxes) + 1), "batched": 8, "graph": 1}}
+        log(f"[bench] level: {out['level']}")
 
     # ------------------------------------------------------------------ adjoint
     if "adjoint" in sections:

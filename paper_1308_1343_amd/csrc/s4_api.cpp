@@ -1,14 +1,16 @@
 // s4_api.cpp -- the C ABI of libsten4 (declared in include/sten4.h): argument
 // validation, workspace layout, tile choice and tuning, box tables for the
-// persistent batched launch, and the hipGraph cache of one RK4 step.
+// persistent batched launch, the hipGraph cache of one RK4 step, and the
+// device side of a level's ghost exchange (s4_level_sync, s4_level_rk4).
 //
 // Tile choice follows the paper's LoopControl (Sec. III-B): every "loop
 // setup" (operation, box sizes, ghost width, strides, device) gets initial
 // execution parameters from a heuristic fed by the device's properties, and
-// measured timings replace them with the fastest candidate.  Here the search
-// is an explicit sweep (s4_tune) rather than on-line hill climbing, and its
-// results persist in a JSON file (the paper's "save and restore execution
-// parameter settings", Sec. III-C).
+// measured timings replace them with faster candidates: either an explicit
+// sweep (s4_tune) or, as in the paper, on-line random-restart hill climbing
+// inside the calls (s4_set_online_tuning).  Sweep results persist in a JSON
+// file (the paper's "save and restore execution parameter settings",
+// Sec. III-C).
 
 #include <hip/hip_runtime.h>
 
@@ -1072,7 +1074,8 @@ static StageCoef rk4_coef(int s, double dt)
 // piece table and one table of per-box stage-input pointers per stage.
 struct SyncArgs {
     const SyncPiece *P;
-    int npiece, nblocks;
+    const int *W; // piece of each workgroup
+    int nblocks;
     double *const *F; // 4 * nbox entries, stage-major
 };
 
@@ -1086,7 +1089,7 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
     for (int st = 0; st < 4; ++st) {
         const StageCoef K = rk4_coef(st, dt);
         if (sy) {
-            hipError_t e = launch_sync(sy->P, sy->npiece, sy->F + (size_t)st * nbox, sy->nblocks, s);
+            hipError_t e = launch_sync(sy->P, sy->W, sy->F + (size_t)st * nbox, sy->nblocks, s);
             if (e != hipSuccess)
                 return hip_fail(e, "ghost exchange launch");
         }
@@ -1520,9 +1523,19 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
 // ---------------------------------------------------------------------------
 // level: ghost exchange between the boxes of one refinement level
 
+static int64_t sync_blocks(const s4_level *L)
+{
+    int64_t blk = 0;
+    for (const LevelPiece &P : L->pieces)
+        blk += (P.n[0] * P.n[1] * P.n[2] + 255) / 256;
+    return blk;
+}
+
+// bytes of the device schedule: the pieces, then one piece index per workgroup
 static size_t sync_pieces_bytes(const s4_level *L)
 {
-    return round256(std::max<size_t>(1, L->pieces.size()) * sizeof(SyncPiece));
+    return round256(std::max<size_t>(1, L->pieces.size()) * sizeof(SyncPiece)) +
+           round256((size_t)std::max<int64_t>(1, sync_blocks(L)) * sizeof(int));
 }
 
 static size_t ptr_table_bytes(int nbox, int ntab)
@@ -1530,12 +1543,14 @@ static size_t ptr_table_bytes(int nbox, int ntab)
     return round256((size_t)ntab * nbox * sizeof(double *));
 }
 
-// device form of the schedule; returns the launch's workgroup count (< 0: too large)
-static int64_t sync_table(const s4_level *L, std::vector<SyncPiece> &out)
+// the device schedule's bytes (sync_pieces_bytes long) at dst
+static void sync_table(const s4_level *L, char *dst)
 {
-    out.clear();
+    SyncPiece *out = (SyncPiece *)dst;
+    int *W = (int *)(dst + round256(std::max<size_t>(1, L->pieces.size()) * sizeof(SyncPiece)));
     int64_t blk = 0;
-    for (const LevelPiece &P : L->pieces) {
+    for (size_t p = 0; p < L->pieces.size(); ++p) {
+        const LevelPiece &P = L->pieces[p];
         const s4_box &d = L->boxes[(size_t)P.dst], &sb = L->boxes[(size_t)P.src];
         SyncPiece q;
         memset(&q, 0, sizeof q);
@@ -1550,19 +1565,33 @@ static int64_t sync_table(const s4_level *L, std::vector<SyncPiece> &out)
         q.dsz = d.stride[2];
         q.ssy = sb.stride[1];
         q.ssz = sb.stride[2];
-        out.push_back(q);
-        blk += (P.n[0] * P.n[1] * P.n[2] + 255) / 256;
-        if (blk > 0x7fffffff)
-            return -1;
+        out[p] = q;
+        const int64_t nb = (P.n[0] * P.n[1] * P.n[2] + 255) / 256;
+        for (int64_t k = 0; k < nb; ++k)
+            W[blk + k] = (int)p;
+        blk += nb;
     }
-    return blk;
+}
+
+static const int *sync_block_table(const s4_level *L, const void *dev)
+{
+    return (const int *)((const char *)dev + round256(std::max<size_t>(1, L->pieces.size()) * sizeof(SyncPiece)));
 }
 
 static int level_check(const s4_level *L)
 {
     if (!L)
         return fail(S4_EINVAL, "level is NULL");
-    return check_boxes(L->boxes.data(), (int)L->boxes.size(), S4_OP_RK4);
+    int r = check_boxes(L->boxes.data(), (int)L->boxes.size(), S4_OP_RK4);
+    if (r)
+        return r;
+    if (sync_blocks(L) > 0x7fffffff)
+        return fail(S4_EINVAL, "ghost exchange too large for one launch");
+    for (const LevelPiece &P : L->pieces)
+        if (P.n[0] * P.n[1] * P.n[2] >= ((int64_t)1 << 31))
+            return fail(S4_EINVAL, "ghost exchange piece of %lld points is too large",
+                        (long long)(P.n[0] * P.n[1] * P.n[2]));
+    return S4_OK;
 }
 
 int s4_level_workspace_size(const s4_level *L, int op, size_t *bytes)
@@ -1609,21 +1638,18 @@ int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *worksp
     wr.push_back(all.back());
     if ((r = check_disjoint(wr, all)))
         return r;
-    std::vector<SyncPiece> tab;
-    const int64_t nblocks = sync_table(L, tab);
-    if (nblocks < 0)
-        return fail(S4_EINVAL, "ghost exchange too large for one launch");
-    if (tab.empty())
+    const int64_t nblocks = sync_blocks(L);
+    if (nblocks == 0)
         return S4_OK;
     hipStream_t s = (hipStream_t)stream;
     std::vector<char> bytes(need, 0);
-    memcpy(bytes.data(), tab.data(), tab.size() * sizeof(SyncPiece));
+    sync_table(L, bytes.data());
     memcpy(bytes.data() + sync_pieces_bytes(L), f, (size_t)nbox * sizeof(double *));
     if ((r = upload_table(workspace, bytes, s)))
         return r;
     const SyncPiece *P = (const SyncPiece *)workspace;
     double *const *F = (double *const *)((char *)workspace + sync_pieces_bytes(L));
-    hipError_t e = launch_sync(P, (int)tab.size(), F, (int)nblocks, s);
+    hipError_t e = launch_sync(P, sync_block_table(L, workspace), F, (int)nblocks, s);
     if (e != hipSuccess)
         return hip_fail(e, "ghost exchange launch");
     return S4_OK;
@@ -1661,17 +1687,14 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
         nitems += dev_items(tab[i]);
     if (nitems > 0x3fffffff)
         return fail(S4_EINVAL, "too many work items");
-    std::vector<SyncPiece> pieces;
-    const int64_t nblocks = sync_table(L, pieces);
-    if (nblocks < 0)
-        return fail(S4_EINVAL, "ghost exchange too large for one launch");
+    const int64_t nblocks = sync_blocks(L);
 
-    // [stage tables | item counters | exchange pieces | stage-input pointers], uploaded at once
+    // [stage tables | item counters | exchange schedule | stage-input pointers], uploaded at once
     const size_t tb = rk4_table_bytes(nbox), pb = sync_pieces_bytes(L), fb = ptr_table_bytes(nbox, 4);
     char *dbase = ws + rk4_fields_bytes(b, nbox);
     std::vector<char> bytes(tb + pb + fb, 0);
     memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
-    memcpy(bytes.data() + tb, pieces.data(), pieces.size() * sizeof(SyncPiece));
+    sync_table(L, bytes.data() + tb);
     double **F = (double **)(bytes.data() + tb + pb);
     for (int st = 0; st < 4; ++st)
         for (int i = 0; i < nbox; ++i)
@@ -1680,7 +1703,7 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
         return r;
     DevBox *dtab = (DevBox *)dbase;
     int *counters = (int *)(dbase + round256(4 * (size_t)nbox * sizeof(DevBox)));
-    const SyncArgs sy{(const SyncPiece *)(dbase + tb), (int)pieces.size(), (int)nblocks,
+    const SyncArgs sy{(const SyncPiece *)(dbase + tb), sync_block_table(L, dbase + tb), (int)nblocks,
                       (double *const *)(dbase + tb + pb)};
     const bool batched = nbox > 1 && mode != S4_PERBOX;
     if (mode != S4_GRAPH) {

@@ -337,20 +337,53 @@ int s4_level_create(const s4_box *b, const int64_t *lo, int nbox, const int64_t 
     }
     L->points = (int64_t)total;
 
-    // periodic images of the domain that a ghost zone of this width can reach
-    std::vector<std::array<coord, 3>> images;
-    for (int z = -1; z <= 1; ++z)
-        for (int y = -1; y <= 1; ++y)
-            for (int x = -1; x <= 1; ++x) {
-                const int t[3] = {x, y, z};
-                bool ok = true;
-                for (int a = 0; a < 3; ++a)
-                    ok = ok && (t[a] == 0 || domain[a] > 0);
-                if (ok)
-                    images.push_back({t[0] * domain[0], t[1] * domain[1], t[2] * domain[2]});
-            }
-
+    // Box interiors and their periodic images that a ghost zone can reach (the
+    // images meeting [-width, domain + width) on periodic axes), registered in a
+    // coarse grid of cells at least as wide as any ghosted box, so that each box
+    // finds its neighbours among the few images sharing its cells instead of
+    // among all of them.
     const coord w = width;
+    struct Image {
+        int box;
+        std::array<coord, 3> t, lo, hi;
+    };
+    std::vector<Image> imgs;
+    for (int c = 0; c < nbox; ++c)
+        for (int z = -1; z <= 1; ++z)
+            for (int y = -1; y <= 1; ++y)
+                for (int x = -1; x <= 1; ++x) {
+                    const int k[3] = {x, y, z};
+                    Image im;
+                    im.box = c;
+                    bool ok = true;
+                    for (int a = 0; a < 3; ++a) {
+                        ok = ok && (k[a] == 0 || domain[a] > 0);
+                        im.t[a] = k[a] * domain[a];
+                        im.lo[a] = ilo[(size_t)c][a] + im.t[a];
+                        im.hi[a] = ihi[(size_t)c][a] + im.t[a];
+                        if (k[a] != 0)
+                            ok = ok && im.lo[a] < domain[a] + w && -w < im.hi[a];
+                    }
+                    if (ok)
+                        imgs.push_back(im);
+                }
+    std::array<coord, 3> cell{};
+    for (int a = 0; a < 3; ++a) {
+        coord m = 1;
+        for (int c = 0; c < nbox; ++c)
+            m = std::max<coord>(m, b[c].n[a]);
+        cell[a] = m + 2 * w;
+    }
+    auto cell_of = [&](coord x, int a) { return x >= 0 ? x / cell[a] : -((-x + cell[a] - 1) / cell[a]); };
+    std::map<std::array<coord, 3>, std::vector<int>> grid;
+    for (int k = 0; k < (int)imgs.size(); ++k) {
+        const Image &im = imgs[(size_t)k];
+        for (coord cz = cell_of(im.lo[2], 2); cz <= cell_of(im.hi[2] - 1, 2); ++cz)
+            for (coord cy = cell_of(im.lo[1], 1); cy <= cell_of(im.hi[1] - 1, 1); ++cy)
+                for (coord cx = cell_of(im.lo[0], 0); cx <= cell_of(im.hi[0] - 1, 0); ++cx)
+                    grid[{cx, cy, cz}].push_back(k);
+    }
+
     for (int i = 0; i < nbox; ++i) {
         const auto &bl = ilo[(size_t)i], &bh = ihi[(size_t)i];
         // the ghost region box i needs
@@ -369,37 +402,43 @@ int s4_level_create(const s4_box *b, const int64_t *lo, int nbox, const int64_t 
             grown = bs::union_all<3>(std::move(faces));
         }
         const Set<3> need = bs::combine<3>(bs::DIFFERENCE, grown, interior[(size_t)i]);
+        std::vector<int> near;
+        for (coord cz = cell_of(bl[2] - w, 2); cz <= cell_of(bh[2] + w - 1, 2); ++cz)
+            for (coord cy = cell_of(bl[1] - w, 1); cy <= cell_of(bh[1] + w - 1, 1); ++cy)
+                for (coord cx = cell_of(bl[0] - w, 0); cx <= cell_of(bh[0] + w - 1, 0); ++cx) {
+                    auto it = grid.find({cx, cy, cz});
+                    if (it != grid.end())
+                        near.insert(near.end(), it->second.begin(), it->second.end());
+                }
+        std::sort(near.begin(), near.end());
+        near.erase(std::unique(near.begin(), near.end()), near.end());
         std::vector<Set<3>> got;
-        for (const auto &t : images)
-            for (int c = 0; c < nbox; ++c) {
-                std::array<coord, 3> sl, sh;
-                bool touch = true;
+        for (int k : near) {
+            const Image &im = imgs[(size_t)k];
+            bool touch = true;
+            for (int a = 0; a < 3; ++a)
+                touch = touch && im.lo[a] < bh[a] + w && bl[a] - w < im.hi[a];
+            if (!touch)
+                continue;
+            Set<3> piece = bs::combine<3>(bs::INTERSECTION, need, bs::box<3>(im.lo.data(), im.hi.data()));
+            if (bs::empty<3>(piece))
+                continue;
+            std::array<coord, 3> pl{}, ph{};
+            bs::BoxList<3> boxes;
+            bs::boxes<3, 3>(piece, pl, ph, boxes);
+            for (const auto &bx : boxes) {
+                LevelPiece P;
+                P.dst = i;
+                P.src = im.box;
                 for (int a = 0; a < 3; ++a) {
-                    sl[a] = ilo[(size_t)c][a] + t[a];
-                    sh[a] = ihi[(size_t)c][a] + t[a];
-                    touch = touch && sl[a] < bh[a] + w && bl[a] - w < sh[a];
+                    P.d0[a] = bx.first[a] - bl[a];
+                    P.s0[a] = bx.first[a] - im.t[a] - ilo[(size_t)im.box][a];
+                    P.n[a] = bx.second[a] - bx.first[a];
                 }
-                if (!touch)
-                    continue;
-                Set<3> piece = bs::combine<3>(bs::INTERSECTION, need, bs::box<3>(sl.data(), sh.data()));
-                if (bs::empty<3>(piece))
-                    continue;
-                std::array<coord, 3> pl{}, ph{};
-                bs::BoxList<3> boxes;
-                bs::boxes<3, 3>(piece, pl, ph, boxes);
-                for (const auto &bx : boxes) {
-                    LevelPiece P;
-                    P.dst = i;
-                    P.src = c;
-                    for (int a = 0; a < 3; ++a) {
-                        P.d0[a] = bx.first[a] - bl[a];
-                        P.s0[a] = bx.first[a] - t[a] - ilo[(size_t)c][a];
-                        P.n[a] = bx.second[a] - bx.first[a];
-                    }
-                    L->pieces.push_back(P);
-                }
-                got.push_back(std::move(piece));
+                L->pieces.push_back(P);
             }
+            got.push_back(std::move(piece));
+        }
         const Set<3> covered = bs::union_all<3>(std::move(got));
         L->filled += (int64_t)bs::size<3>(covered);
         L->uncovered += (int64_t)bs::size<3>(bs::combine<3>(bs::DIFFERENCE, need, covered));

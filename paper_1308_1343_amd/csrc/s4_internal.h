@@ -342,7 +342,8 @@ S4_HD inline int wrap_index(int p, int n)
 // One copy piece of a level's ghost exchange as the sync kernel sees it:
 // n[0] x n[1] x n[2] points from field F[src] at element offset soff (then
 // strides ssy, ssz) to field F[dst] at doff (strides dsy, dsz).  The piece
-// owns workgroups blk0 .. blk0 + ceil(volume / 256) - 1 of the launch.
+// owns workgroups blk0 .. blk0 + ceil(volume / 256) - 1 of the launch (a
+// table of one piece index per workgroup maps them back).
 struct SyncPiece {
     int32_t dst, src;
     int32_t n[3];

@@ -592,33 +592,23 @@ __global__ __launch_bounds__(256) void k_fill_periodic(DevBox B)
 
 // ---------------------------------------------------------------------------
 // level ghost exchange: every workgroup copies up to 256 points of one piece
-// (the piece whose block range holds blockIdx.x, found by a binary search
-// over the pieces' first blocks), x fastest so rows of a piece coalesce.
-// Sources are interior points and destinations ghost points, so the pieces
-// of one launch never read what another writes.
+// (W[blockIdx.x] names it), x fastest so rows of a piece coalesce.  Sources
+// are interior points and destinations ghost points, so the pieces of one
+// launch never read what another writes.
 
-__global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, int npiece,
+__global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, const int *__restrict__ W,
                                               double *const *__restrict__ F)
 {
-    const int blk = blockIdx.x;
-    int lo = 0, hi = npiece - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (P[mid].blk0 <= blk)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const SyncPiece &q = P[lo];
-    const int64_t t = (int64_t)(blk - q.blk0) * 256 + threadIdx.x;
-    const int nx = q.n[0], ny = q.n[1];
-    if (t >= (int64_t)nx * ny * q.n[2])
+    const SyncPiece &q = P[W[blockIdx.x]];
+    // piece volumes are below 2^31 (checked on the host): 32-bit index arithmetic
+    const unsigned t = (unsigned)(blockIdx.x - q.blk0) * 256u + threadIdx.x;
+    const unsigned nx = (unsigned)q.n[0], ny = (unsigned)q.n[1];
+    if (t >= nx * ny * (unsigned)q.n[2])
         return;
-    const int i = (int)(t % nx);
-    const int64_t r = t / nx;
-    const int j = (int)(r % ny), k = (int)(r / ny);
-    const double v = F[q.src][q.soff + i + j * q.ssy + k * q.ssz];
-    F[q.dst][q.doff + i + j * q.dsy + k * q.dsz] = v;
+    const unsigned r = t / nx, i = t - r * nx;
+    const unsigned k = r / ny, j = r - k * ny;
+    const double v = F[q.src][q.soff + i + (int64_t)j * q.ssy + (int64_t)k * q.ssz];
+    F[q.dst][q.doff + i + (int64_t)j * q.dsy + (int64_t)k * q.dsz] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -767,11 +757,11 @@ hipError_t launch_fill(const DevBox &B, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sync(const SyncPiece *P, int npiece, double *const *F, int nblocks, hipStream_t s)
+hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nblocks, hipStream_t s)
 {
-    if (npiece <= 0 || nblocks <= 0)
+    if (nblocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_sync, dim3((unsigned)nblocks), dim3(256), 0, s, P, npiece, F);
+    hipLaunchKernelGGL(k_sync, dim3((unsigned)nblocks), dim3(256), 0, s, P, W, F);
     return hipGetLastError();
 }
 

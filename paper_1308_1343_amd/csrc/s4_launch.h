@@ -34,10 +34,10 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 
-// Level ghost exchange: npiece pieces (device table, blk0 ascending, piece 0
-// at block 0) over nblocks workgroups of 256 threads; F is a device table of
-// one field pointer per box.
-hipError_t launch_sync(const SyncPiece *P, int npiece, double *const *F, int nblocks, hipStream_t s);
+// Level ghost exchange over nblocks workgroups of 256 threads: W[b] is the
+// piece (in device table P) that workgroup b copies from; F is a device table
+// of one field pointer per box.
+hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nblocks, hipStream_t s);
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s);
 

@@ -190,3 +190,15 @@ def test_level_errors():
     other = list(boxes)
     other[2] = S.make_box(d["boxes"][2]["n"], d["ghost"], tuple(boxes[2].stride), 0.5)
     assert code(boxes=other) == S.S4_EINVAL                        # two spacings on one level
+
+
+@pytest.mark.parametrize("shape", ["faces", "full"])
+def test_schedule_many_small_boxes(shape):
+    # 216 boxes of sides 3..8: boxes narrower than the ghost zone reach past their neighbours
+    d = W.level_tiling(counts=(6, 6, 6), smin=3, smax=8)
+    lo = [b["lo"] for b in d["boxes"]]
+    n = [b["n"] for b in d["boxes"]]
+    L = S.s4_level_create(level_boxes(d), lo, d["domain"], 3, shape)
+    info = S.s4_level_info(L)
+    filled, unc = B.check_pieces(S.s4_level_pieces(L), lo, n, d["ghost"], d["domain"], 3, shape)
+    assert unc == 0 and info["uncovered"] == 0 and info["filled"] == filled
