@@ -82,13 +82,18 @@ static int hip_fail(hipError_t e, const char *where)
 
 // A candidate is a kernel set and its tile (the paper's "execution
 // parameters" plus its future-work choice between sets of loop kernels,
-// Sec. III-C).  variant 0: one kernel per operation or RK4 stage, tile
-// tx x (nw*64/tx); variant 1 (RK4 on one box only): two fused stage-pair
-// kernels per step, workgroup tx x (nw*64/tx) lanes, output tile
-// (tx-4) x (nw*64/tx - 4).  tz is the z chunk (0 = whole box).
+// Sec. III-C).  variant 0: one kernel per operation or RK4 stage on the LDS
+// tile traversal, tile tx x (nw*64/tx); variant 2: the same kernels on the
+// row-register traversal, nw = 4 wavefronts of which tx/64 lie along x,
+// each holding ry rows (item tx x ry*nw*64/tx); variant 1 (RK4 on one box
+// only): two fused stage-pair kernels per step, workgroup tx x (nw*64/tx)
+// lanes, output tile (tx-4) x (nw*64/tx - 4).  tz is the z chunk (0 = whole
+// box).  The list is ordered so that the candidates any op may use form a
+// prefix of it.
 struct Cand {
     int tx, nw, tz;
     int variant;
+    int ry;
 };
 
 static const std::vector<Cand> &cands()
@@ -98,20 +103,24 @@ static const std::vector<Cand> &cands()
         for (int tx : {64, 32, 16})
             for (int nw : {8, 4})
                 for (int tz : {0, 64, 32, 16, 8})
-                    c.push_back({tx, nw, tz, 0});
+                    c.push_back({tx, nw, tz, 0, 0});
+        for (int tx : {256, 128, 64})
+            for (int ry : {4, 2})
+                for (int tz : {64, 32, 16})
+                    c.push_back({tx, 4, tz, 2, ry});
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})
-                c.push_back({tn.first, tn.second, tz, 1});
+                c.push_back({tn.first, tn.second, tz, 1, 0});
         return c;
     }();
     return v;
 }
 
-static int cand_index(int tx, int nw, int tz, int variant = 0)
+static int cand_index(int tx, int nw, int tz, int variant = 0, int ry = 0)
 {
     const auto &c = cands();
     for (size_t i = 0; i < c.size(); ++i)
-        if (c[i].tx == tx && c[i].nw == nw && c[i].tz == tz && c[i].variant == variant)
+        if (c[i].tx == tx && c[i].nw == nw && c[i].tz == tz && c[i].variant == variant && c[i].ry == ry)
             return (int)i;
     return 0;
 }
@@ -119,7 +128,11 @@ static int cand_index(int tx, int nw, int tz, int variant = 0)
 // whether candidate c may run op on nbox boxes
 static bool cand_allowed(const Cand &c, int op, int nbox)
 {
-    return c.variant == 0 || (op == S4_OP_RK4 && nbox == 1);
+    if (c.variant == 0)
+        return true;
+    if (c.variant == 2)
+        return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
+    return op == S4_OP_RK4 && nbox == 1;
 }
 
 static int kernel_op(int op)
@@ -150,7 +163,8 @@ struct GraphEntry {
 // excursions stay cheap: the aim is a short total run time, not the optimum.
 
 // position of a candidate's parameters in their value orders
-static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : 2; }
+static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : tx == 64 ? 2 : tx == 128 ? 3 : 4; }
+static int ord_ry(int ry) { return ry == 4 ? 1 : 0; }
 static int ord_nw(int nw) { return nw == 4 ? 0 : nw == 8 ? 1 : 2; }
 static int ord_tz(int tz) { return tz == 8 ? 0 : tz == 16 ? 1 : tz == 32 ? 2 : tz == 64 ? 3 : 4; }
 
@@ -272,6 +286,8 @@ static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbo
 
 static int tile_ty(const Cand &c)
 {
+    if (c.variant == 2)
+        return c.ry * (c.nw * 64 / c.tx);
     return c.nw * 64 / c.tx;
 }
 
@@ -306,7 +322,7 @@ static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
     for (int tz : {0, 64, 32, 16}) {
         int64_t items = 0;
         for (int i = 0; i < nbox; ++i)
-            items += items_of(b[i], {tx, nw, tz});
+            items += items_of(b[i], {tx, nw, tz, 0, 0});
         if (items >= 4 * (int64_t)ctx->ncu)
             return cand_index(tx, nw, tz);
     }
@@ -320,7 +336,7 @@ std::vector<int> Hill::neighbours(int c) const
     const Cand &a = cands()[c];
     auto dist = [&](const Cand &e) {
         return std::abs(ord_tx(e.tx) - ord_tx(a.tx)) + std::abs(ord_nw(e.nw) - ord_nw(a.nw)) +
-               std::abs(ord_tz(e.tz) - ord_tz(a.tz));
+               std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry));
     };
     std::vector<int> out;
     int nearest = 1 << 30;
@@ -612,7 +628,8 @@ static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const
                       bool ghosted = false)
 {
     const int64_t items = dev_items(D);
-    hipError_t e = launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s, ghosted);
+    hipError_t e = c.variant == 2 ? launch_rows_single(op, c.tx / 64, c.ry, D, K, (int)items, ctx->nxcd, s, ghosted)
+                                  : launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s, ghosted);
     if (e != hipSuccess)
         return hip_fail(e, "stencil launch");
     return S4_OK;
@@ -620,7 +637,7 @@ static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const
 
 static int persistent_grid(s4_ctx *ctx, int op, const Cand &c, int64_t nitems, bool ghosted = false)
 {
-    int per = max_blocks_per_cu(op, c.tx, c.nw, ghosted);
+    int per = c.variant == 2 ? max_blocks_rows(op, c.tx / 64, c.ry, ghosted) : max_blocks_per_cu(op, c.tx, c.nw, ghosted);
     if (per <= 0)
         per = 2;
     return (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
@@ -851,7 +868,8 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
         return r;
     const Choice ch = choose(ctx, op, b, nbox, true);
     const Cand &c = cands()[ch.cand];
-    out[0] = c.variant == 1 ? 100 : kernel_op(op); // 100: fused RK4 stage pairs
+    // 100: fused RK4 stage pairs; 200 + op: the op's kernels on the row-register traversal
+    out[0] = c.variant == 1 ? 100 : c.variant == 2 ? 200 + kernel_op(op) : kernel_op(op);
     out[1] = c.tx;
     out[2] = tile_ty(c);
     out[3] = c.tz;
@@ -1095,8 +1113,12 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
         }
         if (batched) {
             const int grid = persistent_grid(ctx, OP_STAGE, c, nitems, gh);
-            hipError_t e = launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox,
-                                                (int)nitems, counters + 2 * st, grid, K, s, gh);
+            hipError_t e =
+                c.variant == 2
+                    ? launch_rows_batched(OP_STAGE, c.tx / 64, c.ry, dtab + (size_t)st * nbox, nbox, (int)nitems,
+                                          counters + 2 * st, grid, K, s, gh)
+                    : launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox, (int)nitems,
+                                           counters + 2 * st, grid, K, s, gh);
             if (e != hipSuccess)
                 return hip_fail(e, "batched stage launch");
         } else {
@@ -1676,7 +1698,7 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     hipStream_t s = (hipStream_t)stream;
     // the per-stage kernel set only (the fused pairs wrap around one box)
     int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
-    if (cands()[ci].variant != 0)
+    if (cands()[ci].variant == 1)
         ci = heuristic(ctx, b, nbox);
     const Cand &c = cands()[ci];
     char *ws = (char *)workspace;

@@ -197,6 +197,62 @@ struct Walker {
     }
 };
 
+
+// ---------------------------------------------------------------------------
+// Row-register traversal (the third kernel set).  A work item is an x extent
+// of 64*WX points, a y extent of RY*WY rows and a z chunk; its WX x WY
+// wavefronts work independently (no LDS, no barriers).  A wavefront owns 64
+// consecutive x points (one per lane) of RY consecutive rows and marches
+// along z keeping, per row, the five z values of its column in registers.
+// Per plane it loads its RY rows, the two rows on either side (the y taps of
+// the outer rows) and, on lanes 0..3, the x points x0-2, x0-1, x0+64, x0+65;
+// x taps travel between lanes by wavefront-wide shifts.  Every lane loads
+// the readable point of its own column (clamped or wrapped like the tile
+// traversal), so the shifted values are the true taps of every lane inside
+// the box.
+
+template <int WX, int WY, int RY, bool WRAP>
+struct RowWalker {
+    static constexpr int NW = WX * WY;
+    static constexpr int TXE = 64 * WX; // item x extent
+    static constexpr int TYE = RY * WY; // item y extent
+    int i;            // this lane's x
+    int j0;           // first row of the wavefront
+    bool active_x;    // lane inside the box along x
+    bool live;        // the wavefront has points in the box
+    int64_t xc;       // x part of the lane's column offset
+    int64_t hx;       // x part of the halo point of lanes 0..3 (x0 on other lanes)
+    int64_t roff[RY + 4]; // y parts of rows j0-2 .. j0+RY+1
+    int nz, ny, g;
+    int64_t sz;
+
+    S4_HD RowWalker(const DevBox &B, const ItemPos &P, int wave, int lane)
+    {
+        const int nx = B.n[0];
+        ny = B.n[1];
+        nz = B.n[2];
+        g = B.g;
+        sz = B.sz;
+        const int x0 = P.x0 + 64 * (wave % WX);
+        j0 = P.y0 + RY * (wave / WX);
+        live = x0 < nx && j0 < ny;
+        i = x0 + lane;
+        active_x = i < nx;
+        xc = (int64_t)(readable(i, nx, WRAP) + g);
+        const int h = lane < 2 ? x0 - 2 + lane : lane < 4 ? x0 + 62 + lane : x0;
+        hx = (int64_t)(readable(h, nx, WRAP) + g);
+        for (int t = 0; t < RY + 4; ++t)
+            roff[t] = (int64_t)(readable(j0 - 2 + t, ny, WRAP) + g) * B.sy;
+    }
+    S4_HD int64_t zoff(int k) const { return (int64_t)(readable(k, nz, WRAP) + g) * sz; }
+    // element offset of the lane's point in row j0 + r, plane k (inside the box only)
+    S4_HD int64_t point(const DevBox &B, int r, int k) const
+    {
+        return (int64_t)(i + g) + (int64_t)(j0 + r + g) * B.sy + (int64_t)(k + g) * sz;
+    }
+    S4_HD bool row_in(int r) const { return j0 + r < ny; }
+};
+
 // ---------------------------------------------------------------------------
 // Mixed-derivative traversal.  The LDS plane holds the plane being loaded
 // with a full 5x5 neighbourhood (corners included, which the xy cross

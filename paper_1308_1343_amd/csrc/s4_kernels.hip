@@ -311,6 +311,191 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restr
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Row-register traversal (RowWalker): x taps by wavefront-wide DPP shifts,
+// y taps from the rows a wavefront holds (plus two rows either side), z taps
+// from per-row register queues; the loads of planes k+1 and k+2 are in
+// flight while plane k is computed (three plane buffers that rotate with a
+// three-fold unrolled loop, so no buffer is copied).
+
+// a double moved across the wavefront by one lane; lanes whose source lies
+// outside the wavefront take `edge`
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double edge, double src)
+{
+    const uint64_t o = __builtin_bit_cast(uint64_t, edge), v = __builtin_bit_cast(uint64_t, src);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+constexpr int DPP_WAVE_SHL1 = 0x130; // lane l reads lane l + 1
+constexpr int DPP_WAVE_SHR1 = 0x138; // lane l reads lane l - 1
+
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int RY, int OPK>
+struct RowPlane {
+    double c[RY];    // rows j0 .. j0+RY-1 at plane p+2 (transformed)
+    double craw[RY]; // their raw values (adjoint stage only)
+    double ym[2];    // rows j0-2, j0-1 at plane p
+    double yp[2];    // rows j0+RY, j0+RY+1 at plane p
+    double h[RY];    // x halo of each row at plane p (lanes 0..3)
+    PW pw[RY];       // pointwise streams of each row at plane p
+};
+
+template <int WX, int WY, int RY, bool WRAP, int OPK>
+__device__ __forceinline__ void run_rows(const DevBox &B, const ItemPos &P, const StageCoef &K, int wave, int lane)
+{
+    const RowWalker<WX, WY, RY, WRAP> w(B, P, wave, lane);
+    if (!w.live)
+        return;
+    const double *in = B.in;
+    const double *mul = B.inmul;
+    const double scale = K.scale;
+    auto ldw = [&](int64_t e, double &raw) -> double {
+        double v = in[e];
+        if (OPK == OP_ADJSTAGE)
+            v = scale * v;
+        raw = v;
+        if (mul)
+            v = mul[e] * v;
+        return v;
+    };
+    auto load = [&](int p, RowPlane<RY, OPK> &L) {
+        const int64_t z2 = w.zoff(p + 2), z0 = w.zoff(p);
+        double rd;
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            L.c[r] = ldw(w.xc + w.roff[r + 2] + z2, L.craw[r]);
+        L.ym[0] = ldw(w.xc + w.roff[0] + z0, rd);
+        L.ym[1] = ldw(w.xc + w.roff[1] + z0, rd);
+        L.yp[0] = ldw(w.xc + w.roff[RY + 2] + z0, rd);
+        L.yp[1] = ldw(w.xc + w.roff[RY + 3] + z0, rd);
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            L.h[r] = lane < 4 ? ldw(w.hx + w.roff[r + 2] + z0, rd) : 0.0;
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            if (w.active_x && w.row_in(r))
+                pw_load<OPK>(B, K, w.point(B, r, p), L.pw[r]);
+    };
+    // per-row z queues of the transformed input (planes k-2 .. k+2) and, for
+    // the adjoint stage, of the raw input (planes k .. k+2)
+    double q[RY][5], rq[RY][3];
+    {
+        double rd;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            q[r][1] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 2), rd);
+            q[r][2] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 1), rd);
+            q[r][3] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0), rq[r][1]);
+            q[r][4] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 + 1), rq[r][2]);
+        }
+    }
+    auto compute = [&](int k, const RowPlane<RY, OPK> &L) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                q[r][d] = q[r][d + 1];
+            q[r][4] = L.c[r];
+            rq[r][0] = rq[r][1];
+            rq[r][1] = rq[r][2];
+            rq[r][2] = L.craw[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const double c0 = q[r][2];
+            const double xm1 = dpp_shift<DPP_WAVE_SHR1>(lane_value(L.h[r], 1), c0);
+            const double xm2 = dpp_shift<DPP_WAVE_SHR1>(lane_value(L.h[r], 0), xm1);
+            const double xp1 = dpp_shift<DPP_WAVE_SHL1>(lane_value(L.h[r], 2), c0);
+            const double xp2 = dpp_shift<DPP_WAVE_SHL1>(lane_value(L.h[r], 3), xp1);
+            const double ym2 = r >= 2 ? q[r >= 2 ? r - 2 : 0][2] : L.ym[r < 2 ? r : 0];
+            const double ym1 = r >= 1 ? q[r >= 1 ? r - 1 : 0][2] : L.ym[1];
+            const double yp1 = r + 1 < RY ? q[r + 1 < RY ? r + 1 : 0][2] : L.yp[r + 1 - RY >= 0 ? r + 1 - RY : 0];
+            const double yp2 = r + 2 < RY ? q[r + 2 < RY ? r + 2 : 0][2] : L.yp[r + 2 - RY >= 0 ? r + 2 - RY : 0];
+            const double lap = lap4(B, c0, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2, q[r][0], q[r][1], q[r][3], q[r][4]);
+            if (w.active_x && w.row_in(r))
+                pw_apply<OPK>(B, K, w.point(B, r, k), c0, rq[r][0], lap, L.pw[r]);
+        }
+    };
+    const int z0 = P.z0, z1 = P.z1;
+    RowPlane<RY, OPK> b0, b1, b2;
+    load(z0, b0);
+    if (z0 + 1 < z1)
+        load(z0 + 1, b1);
+    for (int k = z0; k < z1; k += 3) {
+        if (k + 2 < z1)
+            load(k + 2, b2);
+        compute(k, b0);
+        if (k + 1 >= z1)
+            break;
+        if (k + 3 < z1)
+            load(k + 3, b0);
+        compute(k + 1, b1);
+        if (k + 2 >= z1)
+            break;
+        if (k + 4 < z1)
+            load(k + 4, b1);
+        compute(k + 2, b2);
+    }
+}
+
+template <int WX, int WY, int RY, bool WRAP, int OPK>
+__global__ __launch_bounds__(WX *WY * 64) void k_rows_single(DevBox B, StageCoef K, int nxcd)
+{
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, 64 * WX, RY * WY);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    run_rows<WX, WY, RY, WRAP, OPK>(B, P, K, wave, threadIdx.x % 64);
+}
+
+// persistent form over a (box, item) queue, as k_tiles_batched
+template <int WX, int WY, int RY, bool WRAP, int OPK>
+__global__ __launch_bounds__(WX *WY * 64) void k_rows_batched(const DevBox *__restrict__ tab, int nbox, int nitems,
+                                                             int *counter, StageCoef K)
+{
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(&counter[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= nitems)
+            break;
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevBox B = tab[lo];
+        const ItemPos P = item_pos(B, item - B.item0, 64 * WX, RY * WY);
+        run_rows<WX, WY, RY, WRAP, OPK>(B, P, K, wave, threadIdx.x % 64);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counter[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&counter[0], 0);
+            atomicExch(&counter[1], 0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Two RK4 stages fused in one pass (temporal blocking by a stage pair).
 //
@@ -705,6 +890,79 @@ int max_blocks_per_cu(int op, int tx, int nw, bool ghosted)
         return nb;                                                                                     \
     }
     S4_FOR_SHAPES(X)
+#undef X
+    return 0;
+}
+
+
+// row-register kernels: (WX, RY) with WX * WY = 4 wavefronts
+template <int WX, int RY, bool WRAP, int OPK>
+static hipError_t launch_rows_single_t(const DevBox &B, const StageCoef &K, int nitems, int nxcd, hipStream_t s)
+{
+    constexpr int WY = 4 / WX;
+    hipLaunchKernelGGL((k_rows_single<WX, WY, RY, WRAP, OPK>), dim3(nitems), dim3(WX * WY * 64), 0, s, B, K, nxcd);
+    return hipGetLastError();
+}
+
+template <int WX, int RY, bool WRAP, int OPK>
+static hipError_t launch_rows_batched_t(const DevBox *tab, int nbox, int nitems, int *counter, int grid,
+                                        const StageCoef &K, hipStream_t s)
+{
+    constexpr int WY = 4 / WX;
+    hipLaunchKernelGGL((k_rows_batched<WX, WY, RY, WRAP, OPK>), dim3(grid), dim3(WX * WY * 64), 0, s, tab, nbox,
+                       nitems, counter, K);
+    return hipGetLastError();
+}
+
+#define S4_ROW_OPS(X, WX, RY)                                                                          \
+    X(WX, RY, false, OP_RHS)                                                                           \
+    X(WX, RY, true, OP_STAGE)                                                                          \
+    X(WX, RY, false, OP_STAGE)
+
+#define S4_ROW_SHAPES(X)                                                                               \
+    S4_ROW_OPS(X, 4, 4)                                                                                \
+    S4_ROW_OPS(X, 4, 2)                                                                                \
+    S4_ROW_OPS(X, 2, 4)                                                                                \
+    S4_ROW_OPS(X, 2, 2)                                                                                \
+    S4_ROW_OPS(X, 1, 4)                                                                                \
+    S4_ROW_OPS(X, 1, 2)
+
+hipError_t launch_rows_single(int op, int wx, int ry, const DevBox &B, const StageCoef &K, int nitems, int nxcd,
+                              hipStream_t s, bool ghosted)
+{
+    const bool wrap = wrap_of(op, ghosted);
+#define X(WX_, RY_, W_, O_)                                                                            \
+    if (wx == WX_ && ry == RY_ && wrap == W_ && op == O_)                                              \
+        return launch_rows_single_t<WX_, RY_, W_, O_>(B, K, nitems, nxcd, s);
+    S4_ROW_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, int nitems, int *counter,
+                               int grid, const StageCoef &K, hipStream_t s, bool ghosted)
+{
+    const bool wrap = wrap_of(op, ghosted);
+#define X(WX_, RY_, W_, O_)                                                                            \
+    if (wx == WX_ && ry == RY_ && wrap == W_ && op == O_)                                              \
+        return launch_rows_batched_t<WX_, RY_, W_, O_>(tab, nbox, nitems, counter, grid, K, s);
+    S4_ROW_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int max_blocks_rows(int op, int wx, int ry, bool ghosted)
+{
+    const bool wrap = wrap_of(op, ghosted);
+    int nb = 0;
+#define X(WX_, RY_, W_, O_)                                                                            \
+    if (wx == WX_ && ry == RY_ && wrap == W_ && op == O_) {                                            \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rows_batched<WX_, 4 / WX_, RY_, W_, O_>, \
+                                                         256, 0) != hipSuccess)                        \
+            return 0;                                                                                  \
+        return nb;                                                                                     \
+    }
+    S4_ROW_SHAPES(X)
 #undef X
     return 0;
 }

@@ -22,6 +22,14 @@ hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int n
 // Resident workgroups per CU of the batched kernel for this shape (0 if unknown).
 int max_blocks_per_cu(int op, int tx, int nw, bool ghosted = false);
 
+// Row-register kernels (4 wavefronts: wx along x times 4/wx along y, ry rows
+// each) for OP_RHS and OP_STAGE, single box and persistent batched forms.
+hipError_t launch_rows_single(int op, int wx, int ry, const DevBox &B, const StageCoef &K, int nitems, int nxcd,
+                              hipStream_t s, bool ghosted = false);
+hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, int nitems, int *counter,
+                               int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
+int max_blocks_rows(int op, int wx, int ry, bool ghosted = false);
+
 // Multi-field mixed-derivative kernel over fields [0, nfield) of M (nfield <= 8);
 // one workgroup per (field, tile) item.
 hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, hipStream_t s);

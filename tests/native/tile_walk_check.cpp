@@ -394,6 +394,162 @@ static void ghost_shell(int nx, int ny, int nz, int g)
             }
 }
 
+
+// the row-register traversal: per item and wavefront, the loads of every
+// plane (RY rows at plane p+2, two rows either side at plane p, the x halo
+// on lanes 0..3), the wavefront-wide shifts that hand x taps between lanes,
+// the per-row z queues and the stores
+template <int WX, int WY, int RY, bool WRAP>
+static void run_rows_check(int nx, int ny, int nz, int g, int padx, int pady, int tz_req)
+{
+    using RW = RowWalker<WX, WY, RY, WRAP>;
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.g = g;
+    B.sy = nx + 2 * g + padx;
+    B.sz = B.sy * (ny + 2 * g + pady);
+    B.tz = tz_req > 0 && tz_req < nz ? tz_req : nz;
+    B.tiles[0] = (nx + RW::TXE - 1) / RW::TXE;
+    B.tiles[1] = (ny + RW::TYE - 1) / RW::TYE;
+    B.tiles[2] = (nz + B.tz - 1) / B.tz;
+    const int64_t total = B.sz * (nz + 2 * g);
+    std::vector<int> written(total, 0);
+    const int nitems = B.tiles[0] * B.tiles[1] * B.tiles[2];
+    auto expect = [&](int i, int j, int k) -> int64_t {
+        if (WRAP)
+            return elem(B, wrapi(i, nx), wrapi(j, ny), wrapi(k, nz));
+        return elem(B, i, j, k);
+    };
+    auto check_read = [&](int64_t e, const char *what) {
+        CHECK(e >= 0 && e < total, "rows: %s read %lld outside [0,%lld)", what, (long long)e, (long long)total);
+        if (e < 0 || e >= total)
+            return;
+        const int k = (int)(e / B.sz) - g, j = (int)(e % B.sz / B.sy) - g, i = (int)(e % B.sy) - g;
+        if (WRAP)
+            CHECK(i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz, "rows: %s read a ghost (%d,%d,%d)", what, i,
+                  j, k);
+        else
+            CHECK(i >= -2 && i < nx + 2 && j >= -2 && j < ny + 2 && k >= -2 && k < nz + 2,
+                  "rows: %s read beyond the radius-2 shell (%d,%d,%d)", what, i, j, k);
+    };
+    for (int item = 0; item < nitems; ++item) {
+        const ItemPos P = item_pos(B, item, RW::TXE, RW::TYE);
+        CHECK(P.z0 < P.z1 && P.z1 <= nz, "rows: empty or overlong z range");
+        for (int wave = 0; wave < RW::NW; ++wave) {
+            std::vector<RW> L;
+            for (int lane = 0; lane < 64; ++lane)
+                L.emplace_back(B, P, wave, lane);
+            bool live = L[0].live;
+            for (int lane = 1; lane < 64; ++lane)
+                CHECK(L[lane].live == live && L[lane].j0 == L[0].j0, "rows: wavefront-uniform values differ");
+            if (!live)
+                continue;
+            // tags: q[lane][r][0..4], per-plane buffers
+            std::vector<int64_t> q(64 * RY * 5, -1);
+            auto Q = [&](int lane, int r, int d) -> int64_t & { return q[(lane * RY + r) * 5 + d]; };
+            for (int lane = 0; lane < 64; ++lane)
+                for (int r = 0; r < RY; ++r)
+                    for (int d = 0; d < 4; ++d) {
+                        const int64_t e = L[lane].xc + L[lane].roff[r + 2] + L[lane].zoff(P.z0 - 2 + d);
+                        check_read(e, "queue warm-up");
+                        Q(lane, r, d + 1) = e;
+                    }
+            for (int k = P.z0; k < P.z1; ++k) {
+                // loads of plane k (the kernel issues them two planes ahead; the addresses are these)
+                std::vector<int64_t> c(64 * RY), ym(64 * 2), yp(64 * 2), h(64 * RY, -1);
+                for (int lane = 0; lane < 64; ++lane) {
+                    const RW &w = L[lane];
+                    for (int r = 0; r < RY; ++r) {
+                        c[lane * RY + r] = w.xc + w.roff[r + 2] + w.zoff(k + 2);
+                        check_read(c[lane * RY + r], "row");
+                        if (lane < 4) {
+                            h[lane * RY + r] = w.hx + w.roff[r + 2] + w.zoff(k);
+                            check_read(h[lane * RY + r], "x halo");
+                        }
+                        if (w.active_x && w.row_in(r)) {
+                            const int64_t pt = w.point(B, r, k);
+                            CHECK(pt == elem(B, w.i, w.j0 + r, k), "rows: pointwise offset");
+                        }
+                    }
+                    for (int t = 0; t < 2; ++t) {
+                        ym[lane * 2 + t] = w.xc + w.roff[t] + w.zoff(k);
+                        yp[lane * 2 + t] = w.xc + w.roff[RY + 2 + t] + w.zoff(k);
+                        check_read(ym[lane * 2 + t], "y halo");
+                        check_read(yp[lane * 2 + t], "y halo");
+                    }
+                }
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int r = 0; r < RY; ++r) {
+                        for (int d = 0; d < 4; ++d)
+                            Q(lane, r, d) = Q(lane, r, d + 1);
+                        Q(lane, r, 4) = c[lane * RY + r];
+                    }
+                for (int r = 0; r < RY; ++r) {
+                    // wavefront shifts: lane l reads lane l-1 (shr) or l+1 (shl); edge lanes take the halo
+                    std::vector<int64_t> xm1(64), xm2(64), xp1(64), xp2(64);
+                    for (int l = 0; l < 64; ++l)
+                        xm1[l] = l >= 1 ? Q(l - 1, r, 2) : h[1 * RY + r];
+                    for (int l = 0; l < 64; ++l)
+                        xm2[l] = l >= 1 ? xm1[l - 1] : h[0 * RY + r];
+                    for (int l = 0; l < 64; ++l)
+                        xp1[l] = l <= 62 ? Q(l + 1, r, 2) : h[2 * RY + r];
+                    for (int l = 0; l < 64; ++l)
+                        xp2[l] = l <= 62 ? xp1[l + 1] : h[3 * RY + r];
+                    for (int l = 0; l < 64; ++l) {
+                        const RW &w = L[l];
+                        if (!(w.active_x && w.row_in(r)))
+                            continue;
+                        const int i = w.i, j = w.j0 + r;
+                        const int64_t ym2 = r >= 2 ? Q(l, r - 2, 2) : ym[l * 2 + r];
+                        const int64_t ym1 = r >= 1 ? Q(l, r - 1, 2) : ym[l * 2 + 1];
+                        const int64_t yp1 = r + 1 < RY ? Q(l, r + 1, 2) : yp[l * 2 + (r + 1 - RY)];
+                        const int64_t yp2 = r + 2 < RY ? Q(l, r + 2, 2) : yp[l * 2 + (r + 2 - RY)];
+                        CHECK(Q(l, r, 2) == expect(i, j, k), "rows: centre tag at (%d,%d,%d)", i, j, k);
+                        CHECK(xm1[l] == expect(i - 1, j, k) && xm2[l] == expect(i - 2, j, k), "rows: x- taps at (%d,%d,%d)",
+                              i, j, k);
+                        CHECK(xp1[l] == expect(i + 1, j, k) && xp2[l] == expect(i + 2, j, k), "rows: x+ taps at (%d,%d,%d)",
+                              i, j, k);
+                        CHECK(ym2 == expect(i, j - 2, k) && ym1 == expect(i, j - 1, k), "rows: y- taps at (%d,%d,%d)", i,
+                              j, k);
+                        CHECK(yp1 == expect(i, j + 1, k) && yp2 == expect(i, j + 2, k), "rows: y+ taps at (%d,%d,%d)", i,
+                              j, k);
+                        for (int d = -2; d <= 2; ++d)
+                            if (d)
+                                CHECK(Q(l, r, 2 + d) == expect(i, j, k + d), "rows: z tap %d at (%d,%d,%d)", d, i, j, k);
+                        const int64_t pt = w.point(B, r, k);
+                        if (pt >= 0 && pt < total)
+                            written[pt]++;
+                    }
+                }
+            }
+        }
+    }
+    for (int k = -g; k < nz + g; ++k)
+        for (int j = -g; j < ny + g; ++j)
+            for (int i = -g; i < nx + g; ++i) {
+                const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+                const int cnt = written[elem(B, i, j, k)];
+                CHECK(cnt == (in ? 1 : 0), "rows: point (%d,%d,%d) stored %d times", i, j, k, cnt);
+            }
+}
+
+template <int WX, int RY>
+static void row_shapes()
+{
+    const int S[][7] = {
+        // nx ny nz g padx pady tz
+        {32, 32, 32, 2, 0, 0, 0},  {37, 19, 23, 2, 3, 1, 16}, {5, 7, 3, 2, 0, 0, 2},  {1, 1, 1, 2, 0, 0, 0},
+        {2, 3, 2, 3, 1, 0, 1},     {70, 9, 5, 3, 6, 2, 4},    {130, 9, 7, 2, 14, 0, 5}, {300, 6, 4, 2, 4, 0, 3},
+        {64, 8, 9, 4, 0, 0, 32},   {256, 5, 6, 2, 12, 0, 16},
+    };
+    for (auto &s : S) {
+        run_rows_check<WX, 4 / WX, RY, false>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
+        run_rows_check<WX, 4 / WX, RY, true>(s[0], s[1], s[2], s[3], s[4], s[5], s[6]);
+    }
+}
+
 template <int TX, int NW>
 static void shapes()
 {
@@ -424,6 +580,12 @@ int main()
         run_pair<64, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
         run_pair<32, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
     }
+    row_shapes<4, 4>();
+    row_shapes<4, 2>();
+    row_shapes<2, 4>();
+    row_shapes<2, 2>();
+    row_shapes<1, 4>();
+    row_shapes<1, 2>();
     shapes<64, 4>();
     shapes<64, 8>();
     shapes<32, 4>();

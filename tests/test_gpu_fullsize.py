@@ -10,7 +10,7 @@ import torch
 import oracle as O
 import paper_1308_1343_amd as S
 import workload as W
-from _gpu import host, rel
+from _gpu import cands_by_kind, host, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -38,16 +38,16 @@ def test_wave256_rk4_100_steps_vs_oracle(ctx):
 
 
 def test_wave256_fused_pairs_match_stage_kernels(ctx):
-    """Every fused stage-pair candidate against the per-stage kernels, bit for bit, at 256^3."""
+    """Every fused stage-pair and row-register candidate against the per-stage tile kernels, bit for bit, at 256^3."""
     d = W.wave256()
     g, n = d["ghost"], d["n"]
     u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
     b = S.box_of(u, g, d["dx"])
-    nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
+    kinds = cands_by_kind(ctx, S.S4_OP_RK4, b)
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, 2)
     S.s4_rk4(ctx, b, [u], [r], None, d["dt"], 6, "graph")
     ref = (host(u), host(r))
-    for cand in range(30, nc):
+    for cand in kinds["fused"] + kinds["rows"]:
         u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
         S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
         S.s4_rk4(ctx, b, [u], [r], None, d["dt"], 6, "graph")

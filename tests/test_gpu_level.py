@@ -199,3 +199,20 @@ def test_level_sync_argument_errors(ctx):
     with pytest.raises(S.Sten4Error) as e:
         S.s4_level_sync(ctx, L, [fs[0]] * len(fs))
     assert e.value.code == S.S4_EALIAS
+
+
+@pytest.mark.parametrize("mode", ["perbox", "batched"])
+def test_level_rk4_row_kernels_bitwise(ctx, mode):
+    """The row-register stage kernels with ghost addressing give the tile kernels' result bit for bit."""
+    from _gpu import cands_by_kind
+    d = W.level_tiling(**SMALL)
+    ref_u, ref_r, recs = level_rk4_case(ctx, d, 3, mode)
+    L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
+    rows = cands_by_kind(ctx, S.S4_OP_RK4, boxes)["rows"]
+    for cand in (rows[0], rows[len(rows) // 2], rows[-1]):
+        L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, cand)
+        S.s4_level_rk4(ctx, L, u, r, None, d["dt"], 3, mode)
+        for a, b_ in zip([host(t) for t in u] + [host(t) for t in r], ref_u + ref_r):
+            np.testing.assert_array_equal(a[3:-3, 3:-3, 3:-3], b_[3:-3, 3:-3, 3:-3], err_msg=f"candidate {cand}")
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)

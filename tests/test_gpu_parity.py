@@ -13,7 +13,7 @@ import torch
 import oracle as O
 import paper_1308_1343_amd as S
 import workload as W
-from _gpu import NAN, dev, dev_full, ghosts_untouched, host, inner, rel
+from _gpu import cands_by_kind, NAN, dev, dev_full, ghosts_untouched, host, inner, rel
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -107,12 +107,14 @@ def test_rk4_modes_and_candidates_bitwise(ctx):
     ref = None
     b = None
     nc = None
-    for cand in [None, 0, 7, 13, 21, 29, "fused"]:
+    kinds = None
+    for cand in [None, 0, 7, 13, 21, 29, "rows", "fused"]:
         for mode in ["perbox", "graph"]:
             u, r = dev(u0, g), dev(r0, g)
             b = S.box_of(u, g, dx)
-            nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
-            cl = list(range(30, nc)) if cand == "fused" else [cand]
+            if kinds is None:
+                kinds = cands_by_kind(ctx, S.S4_OP_RK4, b)
+            cl = kinds[cand] if isinstance(cand, str) else [cand]
             for cc in cl:
                 u, r = dev(u0, g), dev(r0, g)
                 if cc is not None:
@@ -128,7 +130,7 @@ def test_rk4_modes_and_candidates_bitwise(ctx):
     # even step counts end in the caller's buffers after fused pairs only
     wu4, wr4 = O.rk4(u0, r0, g, dx, dt, 4, c2)
     res = []
-    for cc in [0, 30, nc - 1]:
+    for cc in [0, kinds["rows"][0], kinds["rows"][-1], kinds["fused"][0], kinds["fused"][-1]]:
         u, r = dev(u0, g), dev(r0, g)
         S.s4_set_choice(ctx, S.S4_OP_RK4, b, cc)
         S.s4_rk4(ctx, b, [u], [r], [c2d], dt, 4, "graph")
@@ -279,6 +281,14 @@ def test_fused_candidates_only_for_single_box_rk4(ctx):
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, nc - 1)
     assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["kernel_op"] == 100
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    # row-register candidates: RHS and RK4 only (any number of boxes)
+    rows = cands_by_kind(ctx, S.S4_OP_RK4, b)["rows"]
+    assert rows and rows == cands_by_kind(ctx, S.S4_OP_WAVE_RHS, b)["rows"]
+    assert cands_by_kind(ctx, S.S4_OP_RK4, [b, b])["rows"] == rows
+    for op in (S.S4_OP_DERIV_MIXED, S.S4_OP_ADJOINT_STEP, S.S4_OP_ADJOINT_RHS):
+        with pytest.raises(S.Sten4Error) as e:
+            S.s4_set_choice(ctx, op, b, rows[0])
+        assert e.value.code == S.S4_ENOTSUP
 
 
 def test_errors_on_device_calls(ctx):
