@@ -61,6 +61,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def kernel_set(ch):
+    """Name of the kernel set behind a tile choice (s4_get_choice's kernel op)."""
+    k = ch["kernel_op"]
+    return "stage pairs" if k == 100 else "rows" if k >= 200 else "tiles"
+
+
 def traffic_from_profile(kernel_key, tile):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source with the same tile choice; else None."""
@@ -155,16 +161,22 @@ def main():
     achieved = bytes_per_launch / launch_s / 1e9
     if fused:
         kname = f"k_rk4_pair<{choice['tile_x']},{choice['threads'] // 64},pair 0|1>"
+        tkey = "pair_wave256"
+    elif choice["kernel_op"] >= 200:
+        wx = choice["tile_x"] // 64
+        kname = f"k_rows_single<{wx},{4 // wx},{choice['tile_y'] // (4 // wx)},periodic,stage 1..4>"
+        tkey = "rows_stage_wave256"
     else:
         kname = f"k_tiles_single<{choice['tile_x']},{choice['threads'] // 64},periodic,stage 1..4>"
+        tkey = "stage_wave256"
     tile_rk4 = [choice["tile_x"], choice["tile_y"], choice["z_chunk"], choice["threads"]]
-    traffic = traffic_from_profile("pair_wave256" if fused else "stage_wave256", tile_rk4)
+    traffic = traffic_from_profile(tkey, tile_rk4)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": kname, "avg_launch_us": round(launch_s * 1e6, 2),
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "bytes_per_point_step": 8 * sum(launch_bytes), "launches_per_step": nlaunch,
-            "kernel_set": "fused stage pairs" if fused else "one kernel per stage"}
+            "kernel_set": kernel_set(choice)}
     del u, rho, ws
 
     # ------------------------------------------------------------------ tile choice: heuristic, on-line, sweep
@@ -238,7 +250,7 @@ def main():
         out["rhs"] = {"workload": "wave256 single RHS (ghosts read, c=1)", "us_per_rhs": round(ms * 1e3, 2),
                       "gpoint_per_s": round(npts / (ms / 1e3) / 1e9, 1), "achieved_GBs": round(gbs, 1),
                       "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": 16,
-                      "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                      "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch),
                       "traffic": traffic_from_profile("rhs_wave256", [ch["tile_x"], ch["tile_y"], ch["z_chunk"],
                                                                       ch["threads"]])}
         log(f"[bench] rhs: {out['rhs']}")
@@ -298,7 +310,7 @@ def main():
                         "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                         "bytes_per_point": 16 * nf,
                         "fp64_tflops_est": round(mpts * nf * MIXED_FLOPS_PER_FIELD_POINT / (ms / 1e3) / 1e12, 2),
-                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]]}
+                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch)}
         log(f"[bench] mixed: {out['mixed']}")
         del gfs, mouts
 
@@ -339,7 +351,7 @@ def main():
                           "interior_points": bpts, "steps": kb, "modes": res,
                           "speedup_batched_vs_perbox": round(res["perbox"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
                           "speedup_graph_vs_perbox": round(res["perbox"]["ms_per_step"] / res["graph"]["ms_per_step"], 3),
-                          "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                          "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch), "kernel_set": kernel_set(ch),
                           "launches_per_step": {"perbox": 4 * len(boxes), "batched": 4, "graph": 1}}
         log(f"[bench] batched: {out['batched']}")
         del fields, us_, rs_, wsb
@@ -415,7 +427,7 @@ def main():
                         "exchange_bytes": 16 * info["filled"],
                         "single_box_same_domain_ms_per_step": round(one_ms, 4),
                         "level_graph_over_single_box": round(res["graph"]["ms_per_step"] / one_ms, 3),
-                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]],
+                        "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch),
                         "launches_per_step": {"perbox": 4 * (len(lboxes) + 1), "batched": 8, "graph": 1}}
         log(f"[bench] level: {out['level']}")
 
