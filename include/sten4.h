@@ -223,8 +223,9 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
  * on-line tuning is active,
  * out[6] candidate index (with on-line tuning: the best setting so far),
  * out[7] number of candidates this op may use on
- * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 when the choice is
- * the fused stage-pair kernel set of RK4 and 200 + the kernel op when it is
+ * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 or 101 when the
+ * choice is one of RK4's two fused stage-pair kernel sets (widened tile,
+ * per-tap second stage) and 200 + the kernel op when it is
  * the row-register kernel set (out[1] is then the item's x extent, 64 per
  * wavefront along x, and out[2] its y extent). */
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);

@@ -85,11 +85,13 @@ static int hip_fail(hipError_t e, const char *where)
 // Sec. III-C).  variant 0: one kernel per operation or RK4 stage on the LDS
 // tile traversal, tile tx x (nw*64/tx); variant 2: the same kernels on the
 // row-register traversal, nw = 4 wavefronts of which tx/64 lie along x,
-// each holding ry rows (item tx x ry*nw*64/tx); variant 1 (RK4 on one box
-// only): two fused stage-pair kernels per step, workgroup tx x (nw*64/tx)
-// lanes, output tile (tx-4) x (nw*64/tx - 4).  tz is the z chunk (0 = whole
-// box).  The list is ordered so that the candidates any op may use form a
-// prefix of it.
+// each holding ry rows (item tx x ry*nw*64/tx); variants 1 and 3 (RK4 on one
+// box only): two kernels per step, each running two RK4 stages -- variant 1
+// recomputes the first stage on a widened workgroup tile tx x (nw*64/tx)
+// with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms the second
+// stage's stencil input at each tap on the plain tile tx x (nw*64/tx).  tz
+// is the z chunk (0 = whole box).  The list is ordered so that the
+// candidates any op may use form a prefix of it.
 struct Cand {
     int tx, nw, tz;
     int variant;
@@ -111,6 +113,9 @@ static const std::vector<Cand> &cands()
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 1, 0});
+        for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}})
+            for (int tz : {64, 32, 16})
+                c.push_back({tn.first, tn.second, tz, 3, 0});
         return c;
     }();
     return v;
@@ -132,7 +137,7 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
         return true;
     if (c.variant == 2)
         return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
-    return op == S4_OP_RK4 && nbox == 1;
+    return op == S4_OP_RK4 && nbox == 1; // variants 1 and 3
 }
 
 static int kernel_op(int op)
@@ -868,8 +873,8 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
         return r;
     const Choice ch = choose(ctx, op, b, nbox, true);
     const Cand &c = cands()[ch.cand];
-    // 100: fused RK4 stage pairs; 200 + op: the op's kernels on the row-register traversal
-    out[0] = c.variant == 1 ? 100 : c.variant == 2 ? 200 + kernel_op(op) : kernel_op(op);
+    // 100, 101: RK4 stage pairs (widened tile, per-tap); 200 + op: the op's kernels on the row-register traversal
+    out[0] = c.variant == 1 ? 100 : c.variant == 3 ? 101 : c.variant == 2 ? 200 + kernel_op(op) : kernel_op(op);
     out[1] = c.tx;
     out[2] = tile_ty(c);
     out[3] = c.tz;
@@ -1161,7 +1166,9 @@ static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const doub
     A.q[1] = W.R3;
     A.q[2] = W.AU;
     A.q[3] = W.AR;
-    hipError_t e = launch_rk4_pair(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s);
+    hipError_t e = c.variant == 3
+                       ? launch_pair2(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s)
+                       : launch_rk4_pair(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s);
     if (e != hipSuccess)
         return hip_fail(e, "stage-pair launch");
     DevBox Bx = D;
@@ -1174,7 +1181,8 @@ static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const doub
     Bx.p[5] = c2;
     Bx.q[0] = uo;
     Bx.q[1] = ro;
-    e = launch_rk4_pair(1, c.tx, c.nw, Bx, rk4_coef(2, dt), rk4_coef(3, dt), items, ctx->nxcd, s);
+    e = c.variant == 3 ? launch_pair2(1, c.tx, c.nw, Bx, rk4_coef(2, dt), rk4_coef(3, dt), items, ctx->nxcd, s)
+                       : launch_rk4_pair(1, c.tx, c.nw, Bx, rk4_coef(2, dt), rk4_coef(3, dt), items, ctx->nxcd, s);
     if (e != hipSuccess)
         return hip_fail(e, "stage-pair launch");
     return S4_OK;
@@ -1319,7 +1327,7 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
 {
     int r;
     char *ws = (char *)workspace;
-    if (cands()[ch.cand].variant == 1 && nbox == 1) {
+    if ((cands()[ch.cand].variant == 1 || cands()[ch.cand].variant == 3) && nbox == 1) {
         // fused stage pairs: pairs of steps, an odd last step with the stage kernels
         const Cand &cp = cands()[ch.cand];
         const PairFields W = pair_fields(b[0], ws);
@@ -1698,7 +1706,7 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     hipStream_t s = (hipStream_t)stream;
     // the per-stage kernel set only (the fused pairs wrap around one box)
     int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
-    if (cands()[ci].variant == 1)
+    if (cands()[ci].variant == 1 || cands()[ci].variant == 3)
         ci = heuristic(ctx, b, nbox);
     const Cand &c = cands()[ci];
     char *ws = (char *)workspace;
@@ -1843,7 +1851,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             const int set = rot++ % TUNE_SETS;
             switch (op) {
             case S4_OP_RK4:
-                if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
+                if (c.variant == 1 || c.variant == 3) // one fused step: (u, rho) -> ping-pong buffers, alternating
                     return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
                                          set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
                                          s);

@@ -669,6 +669,156 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Two RK4 stages in one pass without a widened tile.  In the first-order
+// wave equation the next stage's u is pointwise in the current state
+// (u_{s+1} = u_n + a_s rho_s), so the second stage's stencil input at each
+// tap is formed from taps of fields the pass already reads:
+//   pair 0 (stages 1, 2): taps of u_n give L u_n; u_2 = u_n + dt/2 rho_n at
+//     every tap (from taps of u_n and rho_n) gives L u_2;
+//   pair 1 (stages 3, 4): taps of u_3 give L u_3; u_4 = u_n + dt rho_3 at
+//     every tap (from taps of rho_3 and u_n) gives L u_4.
+// Each tap value of u_{s+1} is the fma the stage kernel stores there, so
+// results are bit for bit those of the per-stage kernels.  The traversal is
+// the tile traversal's (radius-2 halo, periodic addressing) over NF stencil
+// fields: each field's current plane sits in LDS (double buffered) and its
+// column's five z values in registers.  Reads and writes per point: pair 0
+// reads u_n, rho_n and writes u_3, rho_3, acc_u, acc_rho; pair 1 reads u_3,
+// rho_3, u_n, rho_n, acc_u, acc_rho and writes u_{n+1}, rho_{n+1} (to
+// another buffer than u_n, which neighbouring tiles still read).
+
+template <int TX, int NW, int PAIR, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
+{
+    using T = Tile<TX, NW>;
+    constexpr int NF = PAIR == 0 ? 2 : 3;
+    constexpr int PLANE = T::LY * T::LX;
+    __shared__ double lds[2 * NF * PLANE];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, TX, T::TY);
+    const Walker<TX, NW, true> w(B, P, threadIdx.x);
+    const int lc = w.lc;
+    // stencil fields: pair 0: u_n, rho_n; pair 1: u_3, rho_3, u_n
+    const double *F[3] = {B.in, B.p[0], B.p[1]};
+
+    double q[NF][5], hv[NF][T::HS];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+            q[f][d] = F[f][w.col + w.zoff(P.z0 - 2 + d)];
+        const int64_t zo = w.zoff(P.z0);
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0)
+                hv[f][s] = F[f][w.hcol[s] + zo];
+    }
+    // pointwise streams at the point: c^2; pair 1 also rho_n, acc_u, acc_rho
+    double pw[4] = {1.0, 0.0, 0.0, 0.0}, pwn[4] = {1.0, 0.0, 0.0, 0.0};
+    auto load_pw = [&](int k, double *v) {
+        const int64_t c = w.point(B, k);
+        if (HASC2)
+            v[0] = ldp(B.p[5] + c);
+        if constexpr (PAIR == 1) {
+            v[1] = ldp(B.p[2] + c);
+            v[2] = ldp(B.p[3] + c);
+            v[3] = ldp(B.p[4] + c);
+        }
+    };
+    if (w.active)
+        load_pw(P.z0, pw);
+    int buf = 0;
+    for (int k = P.z0; k < P.z1; ++k) {
+        double *L = lds + buf * NF * PLANE;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            L[f * PLANE + lc] = q[f][2];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    L[f * PLANE + w.hl[s]] = hv[f][s];
+        }
+        __syncthreads();
+        double q4n[NF], hvn[NF][T::HS];
+        if (k + 1 < P.z1) {
+            const int64_t z3 = w.zoff(k + 3), z1 = w.zoff(k + 1);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                q4n[f] = F[f][w.col + z3];
+#pragma unroll
+                for (int s = 0; s < T::HS; ++s)
+                    if (w.hl[s] >= 0)
+                        hvn[f][s] = F[f][w.hcol[s] + z1];
+            }
+            if (w.active)
+                load_pw(k + 1, pwn);
+        }
+        if (w.active) {
+            const double *L0 = L, *L1 = L + PLANE;
+            const double a1 = K1.a, a2 = K2.a;
+            const int X1 = 1, X2 = 2, Y1 = T::LX, Y2 = 2 * T::LX;
+            const double c2 = pw[0];
+            if constexpr (PAIR == 0) {
+                // stage 1: L u_n
+                const double un = q[0][2], rn = q[1][2];
+                const double lap1 = lap4(B, un, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
+                                         L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
+                const double kr1 = HASC2 ? c2 * lap1 : lap1;
+                const double u2 = fma(a1, rn, un);
+                const double r2 = fma(a1, kr1, rn);
+                // stage 2: L u_2 with u_2 = u_n + a1 rho_n at every tap
+                auto t = [&](int o) { return fma(a1, L1[lc + o], L0[lc + o]); };
+                auto tz = [&](int d) { return fma(a1, q[1][d], q[0][d]); };
+                const double lap2 = lap4(B, u2, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
+                                         tz(1), tz(3), tz(4));
+                const double kr2 = HASC2 ? c2 * lap2 : lap2;
+                const int64_t c = w.point(B, k);
+                st(B.q[0] + c, fma(a2, r2, un));
+                st(B.q[1] + c, fma(a2, kr2, rn));
+                st(B.q[2] + c, fma(K2.b, r2, fma(1.0 / 3.0, u2 - un, un)));
+                st(B.q[3] + c, fma(K2.b, kr2, fma(1.0 / 3.0, r2 - rn, rn)));
+            } else {
+                const double *L2 = L + 2 * PLANE;
+                // stage 3: L u_3
+                const double u3 = q[0][2], r3 = q[1][2], un = q[2][2];
+                const double rn = pw[1], au = pw[2], ar = pw[3];
+                const double lap3 = lap4(B, u3, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
+                                         L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
+                const double kr3 = HASC2 ? c2 * lap3 : lap3;
+                const double u4 = fma(a1, r3, un);
+                const double r4 = fma(a1, kr3, rn);
+                const double au4 = fma(K1.b, r3, au);
+                const double ar4 = fma(K1.b, kr3, ar);
+                // stage 4: L u_4 with u_4 = u_n + a3 rho_3 at every tap
+                auto t = [&](int o) { return fma(a1, L1[lc + o], L2[lc + o]); };
+                auto tz = [&](int d) { return fma(a1, q[1][d], q[2][d]); };
+                const double lap4v = lap4(B, u4, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
+                                          tz(1), tz(3), tz(4));
+                const double kr4 = HASC2 ? c2 * lap4v : lap4v;
+                const int64_t c = w.point(B, k);
+                st(B.q[0] + c, fma(K2.b, r4, au4));
+                st(B.q[1] + c, fma(K2.b, kr4, ar4));
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            q[f][0] = q[f][1];
+            q[f][1] = q[f][2];
+            q[f][2] = q[f][3];
+            q[f][3] = q[f][4];
+            q[f][4] = q4n[f];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                hv[f][s] = hvn[f][s];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            pw[v] = pwn[v];
+        buf ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // multi-field mixed-derivative kernel:
 //   out = sum_a D2_a f + sum_{a<b} D_ab f + sum_{a,b} A_ab (D1_a f)(D1_b f)
@@ -1003,6 +1153,31 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
     X(32, 8) X(64, 8) X(64, 16) X(32, 16)
 #undef X
 #undef Y
+    return hipErrorInvalidValue;
+}
+
+
+hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
+                        int nitems, int nxcd, hipStream_t s)
+{
+    const bool c2 = B.p[5] != nullptr;
+#define P2(TX_, NW_)                                                                                   \
+    if (tx == TX_ && nw == NW_) {                                                                      \
+        if (pair == 0 && !c2)                                                                          \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 0, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        else if (pair == 0)                                                                            \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 0, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        else if (!c2)                                                                                  \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 1, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 1, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        return hipGetLastError();                                                                      \
+    }
+    P2(64, 4)
+    P2(64, 8)
+    P2(32, 4)
+    P2(32, 8)
+#undef P2
     return hipErrorInvalidValue;
 }
 

@@ -39,6 +39,11 @@ hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, 
 hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
                            int nitems, int nxcd, hipStream_t s);
 
+// Two RK4 stages per pass on the plain tile (pair 0: stages 1-2, pair 1:
+// stages 3-4), workgroups of tx x (nw*64/tx) lanes, one output point each.
+hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
+                        int nitems, int nxcd, hipStream_t s);
+
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 
