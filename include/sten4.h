@@ -375,8 +375,9 @@ int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *worksp
  * schedule (which must cover every ghost point of its shape: S4_EGHOST
  * otherwise, and have width >= 2), then the stage kernels read stencil
  * neighbours from the ghost zones.  On a periodic level that tiles its
- * domain the result equals s4_rk4 on one box spanning the domain.  u's
- * ghost points are overwritten by the exchange; everything else as for
+ * domain the result equals s4_rk4 on one box spanning the domain.  The
+ * ghost points of u and rho are overwritten by the exchanges (the stage-pair
+ * kernel set exchanges both before its first pass); everything else as for
  * s4_rk4 (modes, c2, in-place update, graph cache keyed additionally by
  * the schedule). */
 int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,

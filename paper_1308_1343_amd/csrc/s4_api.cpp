@@ -86,10 +86,11 @@ static int hip_fail(hipError_t e, const char *where)
 // tile traversal, tile tx x (nw*64/tx); variant 2: the same kernels on the
 // row-register traversal, nw = 4 wavefronts of which tx/64 lie along x,
 // each holding ry rows (item tx x ry*nw*64/tx); variants 1 and 3 (RK4 on one
-// box only): two kernels per step, each running two RK4 stages -- variant 1
-// recomputes the first stage on a widened workgroup tile tx x (nw*64/tx)
-// with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms the second
-// stage's stencil input at each tap on the plain tile tx x (nw*64/tx).  tz
+// box only for variant 1): two kernels per step, each running two RK4
+// stages -- variant 1 recomputes the first stage on a widened workgroup tile
+// tx x (nw*64/tx) with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms
+// the second stage's stencil input at each tap on the plain tile
+// tx x (nw*64/tx) (any number of boxes, levels included).  tz
 // is the z chunk (0 = whole box).  The list is ordered so that the
 // candidates any op may use form a prefix of it.
 struct Cand {
@@ -110,12 +111,12 @@ static const std::vector<Cand> &cands()
             for (int ry : {4, 2})
                 for (int tz : {64, 32, 16})
                     c.push_back({tx, 4, tz, 2, ry});
-        for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
-            for (int tz : {64, 32, 16})
-                c.push_back({tn.first, tn.second, tz, 1, 0});
         for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 3, 0});
+        for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
+            for (int tz : {64, 32, 16})
+                c.push_back({tn.first, tn.second, tz, 1, 0});
         return c;
     }();
     return v;
@@ -137,7 +138,9 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
         return true;
     if (c.variant == 2)
         return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
-    return op == S4_OP_RK4 && nbox == 1; // variants 1 and 3
+    if (c.variant == 3)
+        return op == S4_OP_RK4;
+    return op == S4_OP_RK4 && nbox == 1; // variant 1
 }
 
 static int kernel_op(int op)
@@ -196,8 +199,8 @@ struct Hill {
         return (double)(z >> 11) * (1.0 / 9007199254740992.0);
     }
 
-    // settings one step away: one parameter moved to its neighbouring value,
-    // or the other kernel set with the same z chunk
+    // settings one step away: one parameter moved to its neighbouring value
+    // in the same kernel set, or the nearest settings of each other set
     std::vector<int> neighbours(int c) const;
 
     int next()
@@ -335,7 +338,7 @@ static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
 }
 
 // settings one step away: one parameter moved to its neighbouring value in
-// the same kernel set, and the nearest settings of the other kernel set
+// the same kernel set, and the nearest settings of each other kernel set
 std::vector<int> Hill::neighbours(int c) const
 {
     const Cand &a = cands()[c];
@@ -344,15 +347,15 @@ std::vector<int> Hill::neighbours(int c) const
                std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry));
     };
     std::vector<int> out;
-    int nearest = 1 << 30;
+    int nearest[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
     for (int d : allowed)
         if (cands()[d].variant != a.variant)
-            nearest = std::min(nearest, dist(cands()[d]));
+            nearest[cands()[d].variant] = std::min(nearest[cands()[d].variant], dist(cands()[d]));
     for (int d : allowed) {
         if (d == c)
             continue;
         const Cand &e = cands()[d];
-        if (e.variant == a.variant ? dist(e) == 1 : dist(e) == nearest)
+        if (e.variant == a.variant ? dist(e) == 1 : dist(e) == nearest[e.variant])
             out.push_back(d);
     }
     return out;
@@ -430,12 +433,35 @@ static void online_harvest(OnlineSetup &st)
     (void)hipGetLastError();
 }
 
+struct OnlineTimer;
+// the timer of the call running on this thread, if any (graph_run restarts it
+// after capturing a new graph, so a setting's first call is timed on its
+// launches and not on the one-off capture)
+static thread_local OnlineTimer *g_timer = nullptr;
+
 struct OnlineTimer {
     s4_ctx *ctx = nullptr;
     std::string key;
     int cand = -1;
     hipEvent_t a = nullptr, b = nullptr;
     hipStream_t s = nullptr;
+
+    void restart()
+    {
+        if (ctx && hipEventRecord(a, s) != hipSuccess)
+            (void)hipGetLastError();
+    }
+    ~OnlineTimer()
+    {
+        if (g_timer == this)
+            g_timer = nullptr;
+        if (ctx) { // never stopped (the call failed): return the events
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            OnlineSetup &st = ctx->online_state[key];
+            st.pool.push_back(a);
+            st.pool.push_back(b);
+        }
+    }
 
     OnlineTimer(s4_ctx *c, const Choice &ch, hipStream_t stream)
     {
@@ -465,6 +491,7 @@ struct OnlineTimer {
         key = ch.key;
         cand = ch.cand;
         s = stream;
+        g_timer = this;
     }
     // after the call's launches; units: what one time is divided by (RK4 steps)
     void stop(double units)
@@ -481,6 +508,8 @@ struct OnlineTimer {
             st.pending.push_back({a, b, cand, units});
         }
         ctx = nullptr;
+        if (g_timer == this)
+            g_timer = nullptr;
     }
 };
 
@@ -1112,7 +1141,7 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
     for (int st = 0; st < 4; ++st) {
         const StageCoef K = rk4_coef(st, dt);
         if (sy) {
-            hipError_t e = launch_sync(sy->P, sy->W, sy->F + (size_t)st * nbox, sy->nblocks, s);
+            hipError_t e = launch_sync(sy->P, sy->W, sy->F + (size_t)st * nbox, 1, nbox, sy->nblocks, s);
             if (e != hipSuccess)
                 return hip_fail(e, "ghost exchange launch");
         }
@@ -1243,6 +1272,8 @@ static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<in
             return hip_fail(e, "hipGraphInstantiate");
         }
         ge.graph = g;
+        if (g_timer)
+            g_timer->restart();
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (ctx->graphs.size() >= 64) {
             for (auto &kv : ctx->graphs) {
@@ -1260,6 +1291,9 @@ static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<in
 
 static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, double *const *u, double *const *rho,
                    const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s);
+static int pair_run(s4_ctx *ctx, int ci, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                    const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s,
+                    const s4_level *L);
 
 // argument checks shared by s4_rk4 and s4_level_rk4 (need: workspace bytes)
 static int rk4_check(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho,
@@ -1327,7 +1361,7 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
 {
     int r;
     char *ws = (char *)workspace;
-    if ((cands()[ch.cand].variant == 1 || cands()[ch.cand].variant == 3) && nbox == 1) {
+    if (cands()[ch.cand].variant == 1 && nbox == 1) {
         // fused stage pairs: pairs of steps, an odd last step with the stage kernels
         const Cand &cp = cands()[ch.cand];
         const PairFields W = pair_fields(b[0], ws);
@@ -1355,6 +1389,14 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
         std::vector<DevBox> tab0;
         rk4_tables(b, nbox, u, rho, c2, ws, c0, tab0);
         return rk4_step(ctx, c0, tab0, nbox, false, nullptr, nullptr, dev_items(tab0[0]), dt, s);
+    }
+    if (cands()[ch.cand].variant == 3) {
+        if ((r = pair_run(ctx, ch.cand, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, nullptr)) ||
+            nsteps % 2 == 0)
+            return r;
+        // an odd last step with the per-stage kernels (same arithmetic)
+        const Choice c0{heuristic(ctx, b, nbox), 0, ch.key};
+        return rk4_run(ctx, c0, b, nbox, u, rho, c2, dt, 1, mode == S4_GRAPH ? S4_BATCHED : mode, workspace, s);
     }
     const Cand &c = cands()[ch.cand];
     std::vector<DevBox> tab;
@@ -1636,7 +1678,7 @@ int s4_level_workspace_size(const s4_level *L, int op, size_t *bytes)
         *bytes = sync_pieces_bytes(L) + ptr_table_bytes(nbox, 1);
     else if (op == S4_OP_RK4)
         *bytes = rk4_fields_bytes(L->boxes.data(), nbox) + rk4_table_bytes(nbox) + sync_pieces_bytes(L) +
-                 ptr_table_bytes(nbox, 4);
+                 ptr_table_bytes(nbox, 8);
     else
         return fail(S4_EINVAL, "op %d has no level workspace", op);
     return S4_OK;
@@ -1679,10 +1721,208 @@ int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *worksp
         return r;
     const SyncPiece *P = (const SyncPiece *)workspace;
     double *const *F = (double *const *)((char *)workspace + sync_pieces_bytes(L));
-    hipError_t e = launch_sync(P, sync_block_table(L, workspace), F, (int)nblocks, s);
+    hipError_t e = launch_sync(P, sync_block_table(L, workspace), F, 1, nbox, (int)nblocks, s);
     if (e != hipSuccess)
         return hip_fail(e, "ghost exchange launch");
     return S4_OK;
+}
+
+// Per-stage RK4 on a level (candidate ci of variant 0 or 2): exchange the
+// stage input, then the ghost-addressed stage kernels, four times a step.
+static int level_stage_run(s4_ctx *ctx, const s4_level *L, int ci, double *const *u, double *const *rho,
+                           const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s)
+{
+    const s4_box *b = L->boxes.data();
+    const int nbox = (int)L->boxes.size();
+    const Cand &c = cands()[ci];
+    char *ws = (char *)workspace;
+    std::vector<DevBox> tab;
+    rk4_tables(b, nbox, u, rho, c2, ws, c, tab);
+    int64_t nitems = 0;
+    for (int i = 0; i < nbox; ++i)
+        nitems += dev_items(tab[i]);
+    if (nitems > 0x3fffffff)
+        return fail(S4_EINVAL, "too many work items");
+    const int64_t nblocks = sync_blocks(L);
+
+    // [stage tables | item counters | exchange schedule | stage-input pointers], uploaded at once
+    const size_t tb = rk4_table_bytes(nbox), pb = sync_pieces_bytes(L), fb = ptr_table_bytes(nbox, 8);
+    char *dbase = ws + rk4_fields_bytes(b, nbox);
+    std::vector<char> bytes(tb + pb + fb, 0);
+    memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+    sync_table(L, bytes.data() + tb);
+    double **F = (double **)(bytes.data() + tb + pb);
+    for (int st = 0; st < 4; ++st)
+        for (int i = 0; i < nbox; ++i)
+            F[(size_t)st * nbox + i] = const_cast<double *>(tab[(size_t)st * nbox + i].in);
+    int r = upload_table(dbase, bytes, s);
+    if (r)
+        return r;
+    DevBox *dtab = (DevBox *)dbase;
+    int *counters = (int *)(dbase + round256(4 * (size_t)nbox * sizeof(DevBox)));
+    const SyncArgs sy{(const SyncPiece *)(dbase + tb), sync_block_table(L, dbase + tb), (int)nblocks,
+                      (double *const *)(dbase + tb + pb)};
+    const bool batched = nbox > 1 && mode != S4_PERBOX;
+    if (mode != S4_GRAPH) {
+        for (int step = 0; step < nsteps; ++step)
+            if ((r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s, &sy)))
+                return r;
+        return S4_OK;
+    }
+    const std::string key = "level|" + std::to_string(L->serial) + "|" +
+                            graph_key(b, nbox, u, rho, c2, dt, workspace, ci, batched);
+    return graph_run(
+        ctx, key,
+        [&](hipStream_t cs) { return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, cs, &sy); },
+        nsteps, s);
+}
+
+// Stage-pair RK4 (variant 3) over any set of boxes, on their own (periodic
+// addressing) or as a level (ghost addressing with exchanges).  A step of
+// parity 0 reads y from (u, rho) and writes the workspace copy (Up, Rp); a
+// step of parity 1 goes back, so an even number of steps ends in the
+// caller's buffers.  Tables: [parity][pair][box].  On a level, pair 0 needs
+// the ghosts of its input u and rho, pair 1 those of u_3 and rho_3 (its u_n
+// ghosts are still those exchanged before pair 0).
+static void pair_tables(const s4_box *b, int nbox, double *const *u, double *const *rho, const double *const *c2,
+                        const std::vector<char *> &wsb, const Cand &c, std::vector<DevBox> &tab,
+                        std::vector<PairFields> &pf)
+{
+    tab.assign(4 * (size_t)nbox, DevBox{});
+    pf.resize((size_t)nbox);
+    int item0 = 0;
+    for (int i = 0; i < nbox; ++i) {
+        const PairFields W = pair_fields(b[i], wsb[(size_t)i]);
+        pf[(size_t)i] = W;
+        DevBox D = devbox(b[i], c);
+        D.item0 = item0;
+        item0 += (int)dev_items(D);
+        for (int p = 0; p < 2; ++p) {
+            const double *ui = p ? W.Up : u[i], *ri = p ? W.Rp : rho[i];
+            double *uo = p ? u[i] : W.Up, *ro = p ? rho[i] : W.Rp;
+            DevBox A = D;
+            A.in = ui;
+            A.p[0] = ri;
+            A.p[5] = c2 ? c2[i] : nullptr;
+            A.q[0] = W.U3;
+            A.q[1] = W.R3;
+            A.q[2] = W.AU;
+            A.q[3] = W.AR;
+            DevBox Bx = D;
+            Bx.in = W.U3;
+            Bx.p[0] = W.R3;
+            Bx.p[1] = ui;
+            Bx.p[2] = ri;
+            Bx.p[3] = W.AU;
+            Bx.p[4] = W.AR;
+            Bx.p[5] = c2 ? c2[i] : nullptr;
+            Bx.q[0] = uo;
+            Bx.q[1] = ro;
+            tab[(size_t)(2 * p) * nbox + i] = A;
+            tab[(size_t)(2 * p + 1) * nbox + i] = Bx;
+        }
+    }
+}
+
+static int pair_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, int nbox, bool batched,
+                     DevBox *dtab, int *counters, int64_t nitems, double dt, int parity, hipStream_t s,
+                     const SyncArgs *sy)
+{
+    const bool gh = sy != nullptr;
+    for (int k = 0; k < 2; ++k) {
+        const StageCoef K1 = rk4_coef(2 * k, dt), K2 = rk4_coef(2 * k + 1, dt);
+        const int t = 2 * parity + k;
+        if (sy) {
+            hipError_t e = launch_sync(sy->P, sy->W, sy->F + (size_t)t * 2 * nbox, 2, nbox, sy->nblocks, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "ghost exchange launch");
+        }
+        if (batched) {
+            int per = max_blocks_pair2(k, c.tx, c.nw, gh);
+            if (per <= 0)
+                per = 2;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
+            hipError_t e = launch_pair2_batched(k, c.tx, c.nw, dtab + (size_t)t * nbox, nbox, (int)nitems,
+                                                counters + 2 * t, grid, K1, K2, s, gh);
+            if (e != hipSuccess)
+                return hip_fail(e, "batched stage-pair launch");
+        } else {
+            for (int i = 0; i < nbox; ++i) {
+                const DevBox &D = tab[(size_t)t * nbox + i];
+                hipError_t e = launch_pair2(k, c.tx, c.nw, D, K1, K2, (int)dev_items(D), ctx->nxcd, s, gh);
+                if (e != hipSuccess)
+                    return hip_fail(e, "stage-pair launch");
+            }
+        }
+    }
+    return S4_OK;
+}
+
+// nsteps (even) stage-pair steps; L != NULL: the boxes form that level
+static int pair_run(s4_ctx *ctx, int ci, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                    const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s,
+                    const s4_level *L)
+{
+    if (nsteps <= 0)
+        return S4_OK;
+    const Cand &c = cands()[ci];
+    char *ws = (char *)workspace;
+    std::vector<DevBox> tab;
+    std::vector<PairFields> pf;
+    std::vector<char *> wsb((size_t)nbox);
+    size_t off = 0;
+    for (int i = 0; i < nbox; ++i) {
+        wsb[(size_t)i] = ws + off;
+        off += RK4_FIELDS * field_bytes(b[i]);
+    }
+    pair_tables(b, nbox, u, rho, c2, wsb, c, tab, pf);
+    int64_t nitems = 0;
+    for (int i = 0; i < nbox; ++i)
+        nitems += dev_items(tab[i]);
+    if (nitems > 0x3fffffff)
+        return fail(S4_EINVAL, "too many work items");
+    const bool batched = nbox > 1 && mode != S4_PERBOX;
+    char *dbase = ws + rk4_fields_bytes(b, nbox);
+    const size_t tb = rk4_table_bytes(nbox);
+    const size_t pb = L ? sync_pieces_bytes(L) : 0, fb = L ? ptr_table_bytes(nbox, 8) : 0;
+    int r;
+    if (batched || L) {
+        std::vector<char> bytes(tb + pb + fb, 0);
+        memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
+        if (L) {
+            sync_table(L, bytes.data() + tb);
+            double **F = (double **)(bytes.data() + tb + pb);
+            for (int i = 0; i < nbox; ++i) {
+                const PairFields &W = pf[(size_t)i];
+                double *fl[4][2] = {{u[i], rho[i]}, {W.U3, W.R3}, {W.Up, W.Rp}, {W.U3, W.R3}};
+                for (int t = 0; t < 4; ++t)
+                    for (int f = 0; f < 2; ++f)
+                        F[(size_t)(2 * t + f) * nbox + i] = fl[t][f];
+            }
+        }
+        if ((r = upload_table(dbase, bytes, s)))
+            return r;
+    }
+    DevBox *dtab = (DevBox *)dbase;
+    int *counters = (int *)(dbase + round256(4 * (size_t)nbox * sizeof(DevBox)));
+    SyncArgs sy{nullptr, nullptr, 0, nullptr};
+    if (L)
+        sy = SyncArgs{(const SyncPiece *)(dbase + tb), sync_block_table(L, dbase + tb), (int)sync_blocks(L),
+                      (double *const *)(dbase + tb + pb)};
+    const SyncArgs *syp = L ? &sy : nullptr;
+    auto two = [&](hipStream_t cs) -> int {
+        int rr = pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, 0, cs, syp);
+        return rr ? rr : pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, 1, cs, syp);
+    };
+    if (mode != S4_GRAPH) {
+        for (int k = 0; k < nsteps / 2; ++k)
+            if ((r = two(s)))
+                return r;
+        return S4_OK;
+    }
+    const std::string key = "pair2|" + (L ? std::to_string(L->serial) : std::string("-")) + "|" +
+                            graph_key(b, nbox, u, rho, c2, dt, workspace, ci, batched);
+    return graph_run(ctx, key, two, nsteps / 2, s);
 }
 
 int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,
@@ -1704,50 +1944,16 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     if ((r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, ws_bytes, need)) || nsteps == 0)
         return r;
     hipStream_t s = (hipStream_t)stream;
-    // the per-stage kernel set only (the fused pairs wrap around one box)
     int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
-    if (cands()[ci].variant == 1 || cands()[ci].variant == 3)
+    if (cands()[ci].variant == 1) // the widened-tile pairs wrap around one box
         ci = heuristic(ctx, b, nbox);
-    const Cand &c = cands()[ci];
-    char *ws = (char *)workspace;
-    std::vector<DevBox> tab;
-    rk4_tables(b, nbox, u, rho, c2, ws, c, tab);
-    int64_t nitems = 0;
-    for (int i = 0; i < nbox; ++i)
-        nitems += dev_items(tab[i]);
-    if (nitems > 0x3fffffff)
-        return fail(S4_EINVAL, "too many work items");
-    const int64_t nblocks = sync_blocks(L);
-
-    // [stage tables | item counters | exchange schedule | stage-input pointers], uploaded at once
-    const size_t tb = rk4_table_bytes(nbox), pb = sync_pieces_bytes(L), fb = ptr_table_bytes(nbox, 4);
-    char *dbase = ws + rk4_fields_bytes(b, nbox);
-    std::vector<char> bytes(tb + pb + fb, 0);
-    memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
-    sync_table(L, bytes.data() + tb);
-    double **F = (double **)(bytes.data() + tb + pb);
-    for (int st = 0; st < 4; ++st)
-        for (int i = 0; i < nbox; ++i)
-            F[(size_t)st * nbox + i] = const_cast<double *>(tab[(size_t)st * nbox + i].in);
-    if ((r = upload_table(dbase, bytes, s)))
+    if (cands()[ci].variant != 3)
+        return level_stage_run(ctx, L, ci, u, rho, c2, dt, nsteps, mode, workspace, s);
+    if ((r = pair_run(ctx, ci, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, L)) || nsteps % 2 == 0)
         return r;
-    DevBox *dtab = (DevBox *)dbase;
-    int *counters = (int *)(dbase + round256(4 * (size_t)nbox * sizeof(DevBox)));
-    const SyncArgs sy{(const SyncPiece *)(dbase + tb), sync_block_table(L, dbase + tb), (int)nblocks,
-                      (double *const *)(dbase + tb + pb)};
-    const bool batched = nbox > 1 && mode != S4_PERBOX;
-    if (mode != S4_GRAPH) {
-        for (int step = 0; step < nsteps; ++step)
-            if ((r = rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s, &sy)))
-                return r;
-        return S4_OK;
-    }
-    const std::string key = "level|" + std::to_string(L->serial) + "|" +
-                            graph_key(b, nbox, u, rho, c2, dt, workspace, ci, batched);
-    return graph_run(
-        ctx, key,
-        [&](hipStream_t cs) { return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, cs, &sy); },
-        nsteps, s);
+    // an odd last step with the per-stage kernels (same arithmetic)
+    return level_stage_run(ctx, L, heuristic(ctx, b, nbox), u, rho, c2, dt, 1, mode == S4_GRAPH ? S4_BATCHED : mode,
+                           workspace, s);
 }
 
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)
@@ -1827,16 +2033,23 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             std::vector<char *> wsb(nbox);
             for (int i = 0; i < nbox; ++i)
                 wsb[i] = (char *)F[i][2] - field_shift(b[i]);
-            tab.assign(4 * (size_t)nbox, DevBox{});
-            for (int i = 0; i < nbox; ++i) {
-                std::vector<DevBox> one;
-                double *ui[1] = {us[i]}, *ri[1] = {rs[i]};
-                rk4_tables(&b[i], 1, ui, ri, nullptr, wsb[i], c, one);
-                for (int st = 0; st < 4; ++st) {
-                    one[st].item0 = (int)nitems;
-                    tab[(size_t)st * nbox + i] = one[st];
+            if (c.variant == 3) {
+                std::vector<PairFields> pfs;
+                pair_tables(b, nbox, us.data(), rs.data(), nullptr, wsb, c, tab, pfs);
+                for (int i = 0; i < nbox; ++i)
+                    nitems += dev_items(tab[(size_t)i]);
+            } else {
+                tab.assign(4 * (size_t)nbox, DevBox{});
+                for (int i = 0; i < nbox; ++i) {
+                    std::vector<DevBox> one;
+                    double *ui[1] = {us[i]}, *ri[1] = {rs[i]};
+                    rk4_tables(&b[i], 1, ui, ri, nullptr, wsb[i], c, one);
+                    for (int st = 0; st < 4; ++st) {
+                        one[st].item0 = (int)nitems;
+                        tab[(size_t)st * nbox + i] = one[st];
+                    }
+                    nitems += dev_items(one[0]);
                 }
-                nitems += dev_items(one[0]);
             }
             if (batched) {
                 std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
@@ -1851,7 +2064,9 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             const int set = rot++ % TUNE_SETS;
             switch (op) {
             case S4_OP_RK4:
-                if (c.variant == 1 || c.variant == 3) // one fused step: (u, rho) -> ping-pong buffers, alternating
+                if (c.variant == 3) // one stage-pair step, alternating between (u, rho) and the ping-pong copy
+                    return pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, set & 1, s, nullptr);
+                if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
                     return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
                                          set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
                                          s);

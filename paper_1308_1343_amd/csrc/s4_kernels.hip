@@ -681,23 +681,32 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
 //     every tap (from taps of rho_3 and u_n) gives L u_4.
 // Each tap value of u_{s+1} is the fma the stage kernel stores there, so
 // results are bit for bit those of the per-stage kernels.  The traversal is
-// the tile traversal's (radius-2 halo, periodic addressing) over NF stencil
+// the tile traversal's (radius-2 halo; periodic addressing, or ghost
+// addressing on a level whose ghost zones are exchanged) over NF stencil
 // fields: each field's current plane sits in LDS (double buffered) and its
 // column's five z values in registers.  Reads and writes per point: pair 0
 // reads u_n, rho_n and writes u_3, rho_3, acc_u, acc_rho; pair 1 reads u_3,
 // rho_3, u_n, rho_n, acc_u, acc_rho and writes u_{n+1}, rho_{n+1} (to
 // another buffer than u_n, which neighbouring tiles still read).
 
-template <int TX, int NW, int PAIR, bool HASC2>
-__global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
+template <int TX, int NW, int PAIR>
+struct Pair2Lds {
+    static constexpr int NF = PAIR == 0 ? 2 : 3;
+    static constexpr int PLANE = Tile<TX, NW>::LY * Tile<TX, NW>::LX;
+    static constexpr int SIZE = 2 * NF * PLANE; // doubles
+};
+
+// one work item of a stage pair; c^2 (B.p[5]) is optional per box: without
+// it the stencil is multiplied by 1.0, which is exact
+template <int TX, int NW, int PAIR, bool WRAP>
+__device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, const StageCoef &K1, const StageCoef &K2,
+                                          double *lds)
 {
     using T = Tile<TX, NW>;
-    constexpr int NF = PAIR == 0 ? 2 : 3;
-    constexpr int PLANE = T::LY * T::LX;
-    __shared__ double lds[2 * NF * PLANE];
-    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
-    const ItemPos P = item_pos(B, item, TX, T::TY);
-    const Walker<TX, NW, true> w(B, P, threadIdx.x);
+    constexpr int NF = Pair2Lds<TX, NW, PAIR>::NF;
+    constexpr int PLANE = Pair2Lds<TX, NW, PAIR>::PLANE;
+    const Walker<TX, NW, WRAP> w(B, P, threadIdx.x);
+    const bool hasc2 = B.p[5] != nullptr;
     const int lc = w.lc;
     // stencil fields: pair 0: u_n, rho_n; pair 1: u_3, rho_3, u_n
     const double *F[3] = {B.in, B.p[0], B.p[1]};
@@ -718,7 +727,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
     double pw[4] = {1.0, 0.0, 0.0, 0.0}, pwn[4] = {1.0, 0.0, 0.0, 0.0};
     auto load_pw = [&](int k, double *v) {
         const int64_t c = w.point(B, k);
-        if (HASC2)
+        if (hasc2)
             v[0] = ldp(B.p[5] + c);
         if constexpr (PAIR == 1) {
             v[1] = ldp(B.p[2] + c);
@@ -764,7 +773,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
                 const double un = q[0][2], rn = q[1][2];
                 const double lap1 = lap4(B, un, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
                                          L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
-                const double kr1 = HASC2 ? c2 * lap1 : lap1;
+                const double kr1 = c2 * lap1;
                 const double u2 = fma(a1, rn, un);
                 const double r2 = fma(a1, kr1, rn);
                 // stage 2: L u_2 with u_2 = u_n + a1 rho_n at every tap
@@ -772,7 +781,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
                 auto tz = [&](int d) { return fma(a1, q[1][d], q[0][d]); };
                 const double lap2 = lap4(B, u2, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
                                          tz(1), tz(3), tz(4));
-                const double kr2 = HASC2 ? c2 * lap2 : lap2;
+                const double kr2 = c2 * lap2;
                 const int64_t c = w.point(B, k);
                 st(B.q[0] + c, fma(a2, r2, un));
                 st(B.q[1] + c, fma(a2, kr2, rn));
@@ -785,7 +794,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
                 const double rn = pw[1], au = pw[2], ar = pw[3];
                 const double lap3 = lap4(B, u3, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
                                          L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
-                const double kr3 = HASC2 ? c2 * lap3 : lap3;
+                const double kr3 = c2 * lap3;
                 const double u4 = fma(a1, r3, un);
                 const double r4 = fma(a1, kr3, rn);
                 const double au4 = fma(K1.b, r3, au);
@@ -795,7 +804,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
                 auto tz = [&](int d) { return fma(a1, q[1][d], q[2][d]); };
                 const double lap4v = lap4(B, u4, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
                                           tz(1), tz(3), tz(4));
-                const double kr4 = HASC2 ? c2 * lap4v : lap4v;
+                const double kr4 = c2 * lap4v;
                 const int64_t c = w.point(B, k);
                 st(B.q[0] + c, fma(K2.b, r4, au4));
                 st(B.q[1] + c, fma(K2.b, kr4, ar4));
@@ -816,6 +825,53 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
         for (int v = 0; v < 4; ++v)
             pw[v] = pwn[v];
         buf ^= 1;
+    }
+}
+
+
+template <int TX, int NW, int PAIR, bool WRAP>
+__global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
+{
+    __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, TX, Tile<TX, NW>::TY);
+    run_pair2<TX, NW, PAIR, WRAP>(B, P, K1, K2, lds);
+}
+
+// persistent form over a (box, item) queue, as k_tiles_batched
+template <int TX, int NW, int PAIR, bool WRAP>
+__global__ __launch_bounds__(NW * 64) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, int nitems,
+                                                          int *counter, StageCoef K1, StageCoef K2)
+{
+    __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = atomicAdd(&counter[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= nitems)
+            break;
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab[mid].item0 <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevBox B = tab[lo];
+        const ItemPos P = item_pos(B, item - B.item0, TX, Tile<TX, NW>::TY);
+        run_pair2<TX, NW, PAIR, WRAP>(B, P, K1, K2, lds);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&counter[1], 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(&counter[0], 0);
+            atomicExch(&counter[1], 0);
+        }
     }
 }
 
@@ -932,7 +988,7 @@ __global__ __launch_bounds__(256) void k_fill_periodic(DevBox B)
 // launch never read what another writes.
 
 __global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, const int *__restrict__ W,
-                                              double *const *__restrict__ F)
+                                              double *const *__restrict__ F, int nf, int nbox)
 {
     const SyncPiece &q = P[W[blockIdx.x]];
     // piece volumes are below 2^31 (checked on the host): 32-bit index arithmetic
@@ -942,8 +998,12 @@ __global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, c
         return;
     const unsigned r = t / nx, i = t - r * nx;
     const unsigned k = r / ny, j = r - k * ny;
-    const double v = F[q.src][q.soff + i + (int64_t)j * q.ssy + (int64_t)k * q.ssz];
-    F[q.dst][q.doff + i + (int64_t)j * q.dsy + (int64_t)k * q.dsz] = v;
+    const int64_t so = q.soff + i + (int64_t)j * q.ssy + (int64_t)k * q.ssz;
+    const int64_t d = q.doff + i + (int64_t)j * q.dsy + (int64_t)k * q.dsz;
+    for (int f = 0; f < nf; ++f) {
+        double *const *Ff = F + (size_t)f * nbox;
+        Ff[q.dst][d] = Ff[q.src][so];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,28 +1217,69 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 }
 
 
+#define S4_PAIR2_SHAPES(X)                                                                             \
+    X(64, 4) X(64, 8) X(32, 4) X(32, 8)
+
 hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
-                        int nitems, int nxcd, hipStream_t s)
+                        int nitems, int nxcd, hipStream_t s, bool ghosted)
 {
-    const bool c2 = B.p[5] != nullptr;
-#define P2(TX_, NW_)                                                                                   \
+#define X(TX_, NW_)                                                                                    \
     if (tx == TX_ && nw == NW_) {                                                                      \
-        if (pair == 0 && !c2)                                                                          \
-            hipLaunchKernelGGL((k_pair2<TX_, NW_, 0, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
-        else if (pair == 0)                                                                            \
+        if (pair == 0 && !ghosted)                                                                     \
             hipLaunchKernelGGL((k_pair2<TX_, NW_, 0, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
-        else if (!c2)                                                                                  \
-            hipLaunchKernelGGL((k_pair2<TX_, NW_, 1, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
-        else                                                                                           \
+        else if (pair == 0)                                                                            \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 0, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        else if (!ghosted)                                                                             \
             hipLaunchKernelGGL((k_pair2<TX_, NW_, 1, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_pair2<TX_, NW_, 1, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K1, K2, nxcd); \
         return hipGetLastError();                                                                      \
     }
-    P2(64, 4)
-    P2(64, 8)
-    P2(32, 4)
-    P2(32, 8)
-#undef P2
+    S4_PAIR2_SHAPES(X)
+#undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, int nitems, int *counter,
+                                int grid, const StageCoef &K1, const StageCoef &K2, hipStream_t s, bool ghosted)
+{
+#define X(TX_, NW_)                                                                                    \
+    if (tx == TX_ && nw == NW_) {                                                                      \
+        if (pair == 0 && !ghosted)                                                                     \
+            hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 0, true>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
+                               nitems, counter, K1, K2);                                               \
+        else if (pair == 0)                                                                            \
+            hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 0, false>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
+                               nitems, counter, K1, K2);                                               \
+        else if (!ghosted)                                                                             \
+            hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 1, true>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
+                               nitems, counter, K1, K2);                                               \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 1, false>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
+                               nitems, counter, K1, K2);                                               \
+        return hipGetLastError();                                                                      \
+    }
+    S4_PAIR2_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+int max_blocks_pair2(int pair, int tx, int nw, bool ghosted)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X(TX_, NW_)                                                                                    \
+    if (tx == TX_ && nw == NW_) {                                                                      \
+        if (pair == 0)                                                                                 \
+            e = ghosted ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair2_batched<TX_, NW_, 0, false>, NW_ * 64, 0) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair2_batched<TX_, NW_, 0, true>, NW_ * 64, 0); \
+        else                                                                                           \
+            e = ghosted ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair2_batched<TX_, NW_, 1, false>, NW_ * 64, 0) \
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pair2_batched<TX_, NW_, 1, true>, NW_ * 64, 0); \
+    }
+    S4_PAIR2_SHAPES(X)
+#undef X
+    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_fill(const DevBox &B, hipStream_t s)
@@ -1190,11 +1291,12 @@ hipError_t launch_fill(const DevBox &B, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nblocks, hipStream_t s)
+hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nf, int nbox, int nblocks,
+                       hipStream_t s)
 {
-    if (nblocks <= 0)
+    if (nblocks <= 0 || nf <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_sync, dim3((unsigned)nblocks), dim3(256), 0, s, P, W, F);
+    hipLaunchKernelGGL(k_sync, dim3((unsigned)nblocks), dim3(256), 0, s, P, W, F, nf, nbox);
     return hipGetLastError();
 }
 

@@ -40,17 +40,24 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
                            int nitems, int nxcd, hipStream_t s);
 
 // Two RK4 stages per pass on the plain tile (pair 0: stages 1-2, pair 1:
-// stages 3-4), workgroups of tx x (nw*64/tx) lanes, one output point each.
+// stages 3-4), workgroups of tx x (nw*64/tx) lanes, one output point each;
+// periodic addressing, or ghost addressing when ghosted.
 hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
-                        int nitems, int nxcd, hipStream_t s);
+                        int nitems, int nxcd, hipStream_t s, bool ghosted = false);
+// persistent form over a table of boxes (counter as launch_tiles_batched)
+hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, int nitems, int *counter,
+                                int grid, const StageCoef &K1, const StageCoef &K2, hipStream_t s,
+                                bool ghosted = false);
+int max_blocks_pair2(int pair, int tx, int nw, bool ghosted = false);
 
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 
 // Level ghost exchange over nblocks workgroups of 256 threads: W[b] is the
-// piece (in device table P) that workgroup b copies from; F is a device table
-// of one field pointer per box.
-hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nblocks, hipStream_t s);
+// piece (in device table P) that workgroup b copies; F is a device table of
+// nf x nbox field pointers (field-major), every field exchanged alike.
+hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nf, int nbox, int nblocks,
+                       hipStream_t s);
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s);
 

@@ -201,18 +201,23 @@ def test_level_sync_argument_errors(ctx):
     assert e.value.code == S.S4_EALIAS
 
 
-@pytest.mark.parametrize("mode", ["perbox", "batched"])
-def test_level_rk4_row_kernels_bitwise(ctx, mode):
-    """The row-register stage kernels with ghost addressing give the tile kernels' result bit for bit."""
+@pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
+@pytest.mark.parametrize("kind,nsteps", [("rows", 3), ("fused", 3), ("fused", 4)])
+def test_level_rk4_kernel_sets_bitwise(ctx, mode, kind, nsteps):
+    """The row-register stage kernels and the stage pairs, with ghost addressing and the
+    exchanges they need, give the per-stage tile kernels' result bit for bit."""
     from _gpu import cands_by_kind
     d = W.level_tiling(**SMALL)
-    ref_u, ref_r, recs = level_rk4_case(ctx, d, 3, mode)
     L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
-    rows = cands_by_kind(ctx, S.S4_OP_RK4, boxes)["rows"]
-    for cand in (rows[0], rows[len(rows) // 2], rows[-1]):
+    S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, 2)
+    S.s4_level_rk4(ctx, L, u, r, None, d["dt"], nsteps, mode)
+    S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
+    ref_u, ref_r = [host(t) for t in u], [host(t) for t in r]
+    cl = cands_by_kind(ctx, S.S4_OP_RK4, boxes)[kind]
+    for cand in (cl[0], cl[len(cl) // 2], cl[-1]):
         L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
         S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, cand)
-        S.s4_level_rk4(ctx, L, u, r, None, d["dt"], 3, mode)
+        S.s4_level_rk4(ctx, L, u, r, None, d["dt"], nsteps, mode)
         for a, b_ in zip([host(t) for t in u] + [host(t) for t in r], ref_u + ref_r):
             np.testing.assert_array_equal(a[3:-3, 3:-3, 3:-3], b_[3:-3, 3:-3, 3:-3], err_msg=f"candidate {cand}")
         S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)

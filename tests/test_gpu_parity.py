@@ -179,6 +179,41 @@ def test_bboxset_modes_match_oracle(ctx):
         assert rel(res["graph"][0][i], wu, g) <= TOL and rel(res["graph"][1][i], wr, g) <= TOL
 
 
+@pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
+@pytest.mark.parametrize("nsteps", [2, 3])
+def test_bboxset_stage_pairs_bitwise(ctx, mode, nsteps):
+    """Stage-pair candidates on a set of self-periodic boxes, some with c^2 and some without,
+    bit for bit against the per-stage tile kernels (odd counts end with one per-stage step)."""
+    boxes = small_bboxset(13, 7)
+    g, dt = 3, 0.25 / 128
+
+    def run(cand):
+        us, rs, cs, bs = [], [], [], []
+        for i, bx in enumerate(boxes):
+            us.append(dev(rand_box(bx["n"], g, 14, 2 * i), g))
+            rs.append(dev(rand_box(bx["n"], g, 14, 2 * i + 1), g))
+            cs.append(dev(O.embed(1.0 + 0.5 * W.uniform_pm1(14, 100 + i, bx["n"][::-1]), g), g) if i % 2 else None)
+            bs.append(S.box_of(us[-1], g, bx["dx"], bx["level"]))
+        S.s4_set_choice(ctx, S.S4_OP_RK4, bs, cand)
+        S.s4_rk4(ctx, bs, us, rs, cs, dt, nsteps, mode)
+        S.s4_set_choice(ctx, S.S4_OP_RK4, bs, -1)
+        return [host(t) for t in us + rs], bs
+
+    ref, bs = run(2)
+    pairs = cands_by_kind(ctx, S.S4_OP_RK4, bs)["fused"]
+    assert pairs and all(S.s4_get_choice(ctx, S.S4_OP_RK4, bs)["ncandidates"] > c for c in pairs)
+    for cand in (pairs[0], pairs[len(pairs) // 2], pairs[-1]):
+        got, _ = run(cand)
+        for a, b_ in zip(got, ref):
+            np.testing.assert_array_equal(a, b_, err_msg=f"candidate {cand}")
+    # and against the oracle box by box
+    for i, bx in enumerate(boxes):
+        c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(14, 100 + i, bx["n"][::-1]), g) if i % 2 else None
+        wu, wr = O.rk4(rand_box(bx["n"], g, 14, 2 * i), rand_box(bx["n"], g, 14, 2 * i + 1), g, bx["dx"], dt,
+                       nsteps, c2)
+        assert rel(ref[i], wu, g) <= TOL and rel(ref[len(boxes) + i], wr, g) <= TOL
+
+
 def test_graph_replays_match_eager(ctx):
     """One captured step replayed several times, with eager work in between."""
     boxes = small_bboxset(11, 5)

@@ -7,17 +7,22 @@ import numpy as np
 
 import paper_1308_1343_amd as S
 
-# the library's candidate list, in its order: one kernel per stage, then fused stage pairs
-CANDS = [(0, tx, nw, tz) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0, 64, 32, 16, 8)] + \
-        [(1, tx, nw, tz) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
-ORD_TX = {16: 0, 32: 1, 64: 2}
+# the library's candidate list, in its order (variant, tx, nw, tz, ry): one kernel per stage
+# on the tile traversal, on the row-register traversal, stage pairs per tap, widened stage pairs
+CANDS = [(0, tx, nw, tz, 0) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0, 64, 32, 16, 8)] + \
+        [(2, tx, 4, tz, ry) for tx in (256, 128, 64) for ry in (4, 2) for tz in (64, 32, 16)] + \
+        [(3, tx, nw, tz, 0) for tx, nw in ((64, 4), (64, 8), (32, 8), (32, 4)) for tz in (64, 32, 16)] + \
+        [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
+ORD_TX = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}
 ORD_NW = {4: 0, 8: 1, 16: 2}
 ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 0: 4}
+ORD_RY = {0: 0, 2: 0, 4: 1}
 BOX = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
 
 
 def dist(a, b):
-    return abs(ORD_TX[a[1]] - ORD_TX[b[1]]) + abs(ORD_NW[a[2]] - ORD_NW[b[2]]) + abs(ORD_TZ[a[3]] - ORD_TZ[b[3]])
+    return (abs(ORD_TX[a[1]] - ORD_TX[b[1]]) + abs(ORD_NW[a[2]] - ORD_NW[b[2]]) + abs(ORD_TZ[a[3]] - ORD_TZ[b[3]]) +
+            abs(ORD_RY[a[4]] - ORD_RY[b[4]]))
 
 
 def bowl(center, slope=0.05, other_variant=2.0):
@@ -28,13 +33,16 @@ def bowl(center, slope=0.05, other_variant=2.0):
 def test_candidate_table_matches_library():
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), ncalls=3)
     assert all(0 <= t < len(CANDS) for t in tr)
-    for op, n in ((S.S4_OP_WAVE_RHS, 30), (S.S4_OP_RK4, 42)):
+    for op, n in ((S.S4_OP_WAVE_RHS, 48), (S.S4_OP_ADJOINT_STEP, 30)):
         tr = S.s4_online_simulate(op, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400, restart_prob=0.2)
-        assert max(tr) < n  # fused stage pairs only for single-box RK4
+        assert max(tr) < n  # stage pairs only for RK4, row kernels only for the RHS and RK4
+    tr = S.s4_online_simulate(S.S4_OP_RK4, [BOX, BOX], list(np.linspace(1, 2, len(CANDS))), ncalls=400,
+                              restart_prob=0.2)
+    assert max(tr) < 60  # widened stage pairs only on one box
 
 
 def test_converges_on_a_smooth_landscape():
-    target = CANDS.index((0, 16, 4, 32))
+    target = CANDS.index((0, 16, 4, 32, 0))
     cost = bowl(target)
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=120)
     assert tr[0] != target
@@ -45,7 +53,7 @@ def test_converges_on_a_smooth_landscape():
 
 def test_restarts_escape_a_local_optimum():
     start = S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), ncalls=1)[0]
-    glob = CANDS.index((1, 32, 16, 16))
+    glob = CANDS.index((1, 32, 16, 16, 0))
     cost = [1.5] * len(CANDS)
     cost[start] = 1.0  # an isolated local optimum at the starting setting
     for i, d in enumerate(CANDS):  # a good basin around the global optimum
@@ -59,7 +67,7 @@ def test_restarts_escape_a_local_optimum():
 
 
 def test_excursions_are_cheap():
-    target = CANDS.index((1, 64, 16, 64))
+    target = CANDS.index((1, 64, 16, 64, 0))
     cost = bowl(target, slope=0.3, other_variant=3.0)
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.02, seed=5, ncalls=4000)
     steady = np.mean([cost[t] for t in tr[-2000:]])
@@ -67,7 +75,7 @@ def test_excursions_are_cheap():
 
 
 def test_noise_tolerance_and_determinism():
-    target = CANDS.index((0, 32, 8, 16))
+    target = CANDS.index((0, 32, 8, 16, 0))
     cost = bowl(target, slope=0.1)
     a = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, noise=0.03, restart_prob=0.01, seed=7, ncalls=600)
     b = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, noise=0.03, restart_prob=0.01, seed=7, ncalls=600)
@@ -86,8 +94,20 @@ def test_simulation_rejects_bad_arguments():
 
 def test_moves_between_kernel_sets():
     """A per-stage basin whose best z chunk (8) has no fused-pair counterpart
-    must still lead to a better fused-pair setting without random restarts."""
-    stage_best, pair_best = (0, 32, 8, 8), (1, 32, 16, 16)
-    cost = [(1.0 + 0.05 * dist(d, stage_best)) if d[0] == 0 else (0.85 + 0.05 * dist(d, pair_best)) for d in CANDS]
+    must still lead to a better fused-pair setting without random restarts,
+    past two kernel sets that are worse everywhere."""
+    stage_best, pair_best = (0, 32, 8, 8, 0), (1, 32, 16, 16, 0)
+    cost = [(1.0 + 0.05 * dist(d, stage_best)) if d[0] == 0 else (0.85 + 0.05 * dist(d, pair_best)) if d[0] == 1
+            else 2.0 for d in CANDS]
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=200)
     assert all(CANDS[t] == pair_best for t in tr[-30:])
+
+
+def test_reaches_every_kernel_set():
+    """From the per-stage start the neighbourhood reaches the best setting of
+    whichever kernel set holds it, without random restarts."""
+    for best in ((3, 64, 4, 32, 0), (2, 256, 4, 32, 4), (1, 64, 16, 64, 0)):
+        cost = [0.6 + 0.05 * dist(d, best) if d[0] == best[0] else 1.0 + 0.01 * dist(d, (0, 64, 8, 32, 0))
+                for d in CANDS]
+        tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=300)
+        assert all(CANDS[t] == best for t in tr[-30:]), best
