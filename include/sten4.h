@@ -174,6 +174,15 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
            const double *const *c2, double dt, int nsteps, int mode, void *workspace,
            size_t ws_bytes, void *stream);
 
+/* One RK4 step of s4_rk4 on one periodic box, out of place: reads
+ * (u_in, rho_in), writes (u_out, rho_out) at interior points; the inputs are
+ * not modified and must not overlap the outputs (S4_EALIAS).  Gives the same
+ * values as s4_rk4 on a copy of the inputs.  For recomputing the states of a
+ * checkpointed segment during backpropagation.  c2 and the workspace as for
+ * s4_rk4 (S4_OP_RK4 on this machine). */
+int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                   double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream);
+
 /* Adjoint (transpose) of the wave RHS as a linear map of interior values,
  * for periodic boxes:
  *   F^T(lu, lrho) = (L_p(c^2 lrho), lu),
@@ -193,9 +202,11 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
  *   kb1 = dt/6 ybar + dt/2 yb2;   yb1 = F^T kb1
  *   ybar_n = ybar + yb1 + yb2 + yb3 + yb4
  *   c2_bar += sum_s (kb_s)_rho * (L_p u_s)
- * u_n, rho_n: the forward state at the start of the step (the stage states
- * u_2..u_4 are recomputed from it with periodic addressing; ghosts of u_n
- * are not read and u_n, rho_n are not modified).  lam_u, lam_rho: on entry
+ * u_n, rho_n: the forward state at the start of the step (with c2_bar, the
+ * stage states u_3, rho_3 are recomputed from it and u_2, u_4 are formed at
+ * each stencil tap, with periodic addressing; ghosts of u_n are not read and
+ * u_n, rho_n are not modified).  The step runs as two passes: adjoint stages
+ * 4 and 3, then 2 and 1, each stencilling c^2 kb_rho formed at every tap.  lam_u, lam_rho: on entry
  * ybar = dJ/dy_{n+1}, on return dJ/dy_n (interior).  c2_bar, if not NULL,
  * is accumulated into at interior points; c2 == NULL means c = 1.
  * Workspace as for s4_rk4 with S4_OP_ADJOINT_STEP. */

@@ -37,7 +37,7 @@ MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 # the entry points include/sten4.h declares
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
            "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
-           "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
+           "s4_rk4_step_to", "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
            "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
            "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
            "s4_bset_derivative", "s4_bset_info", "s4_bset_keys", "s4_bset_boxes", "s4_bset_contains",
@@ -87,6 +87,7 @@ def lib():
     L.s4_rk4.argtypes = [vp, BP, i, PP, PP, PP, d, i, i, vp, sz, vp]
     L.s4_wave_adjoint_rhs.argtypes = [vp, BP, i, PP, PP, PP, PP, PP, vp]
     L.s4_rk4_adjoint_step.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
+    L.s4_rk4_step_to.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, sz, vp]
     L.s4_tune.argtypes = [vp, i, BP, i, i, vp, sz, vp]
     L.s4_get_choice.argtypes = [vp, i, BP, i, ctypes.POINTER(i)]
     L.s4_set_choice.argtypes = [vp, i, BP, i, i]
@@ -291,6 +292,15 @@ def s4_rk4(ctx, boxes, u, rho, c2, dt, nsteps, mode=S4_GRAPH, ws=None, stream=No
         ws = workspace(s4_workspace_size(boxes, S4_OP_RK4, mode), u[0].device)
     _check(lib().s4_rk4(ctx.handle, arr, n, _ptrs(u), _ptrs(rho), None if c2 is None else _ptrs(c2),
                         float(dt), int(nsteps), int(mode), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def s4_rk4_step_to(ctx, box, u_in, rho_in, c2, dt, u_out, rho_out, ws=None, stream=None):
+    arr, _ = _boxes(box)
+    if ws is None:
+        ws = workspace(s4_workspace_size(box, S4_OP_RK4, S4_PERBOX), u_in.device)
+    _check(lib().s4_rk4_step_to(ctx.handle, arr, _ptr(u_in), _ptr(rho_in), _ptr(c2), float(dt), _ptr(u_out),
+                                _ptr(rho_out), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
 
 

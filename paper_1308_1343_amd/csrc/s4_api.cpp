@@ -149,7 +149,7 @@ static int kernel_op(int op)
     case S4_OP_WAVE_RHS: return OP_RHS;
     case S4_OP_RK4: return OP_STAGE;
     case S4_OP_ADJOINT_RHS: return OP_ADJRHS;
-    case S4_OP_ADJOINT_STEP: return OP_ADJSTAGE;
+    case S4_OP_ADJOINT_STEP: return OP_ADJSTEP;
     case S4_OP_DERIV_MIXED: return OP_COUNT; // its own kernel, k_mixed
     default: return -1;
     }
@@ -692,7 +692,7 @@ static int upload_table(void *dst, const std::vector<char> &bytes, hipStream_t s
 // workspace layouts
 
 static const int RK4_FIELDS = 6;   // Ua Ub Ra Rb AccU AccR
-static const int ADJ_FIELDS = 13;  // Ua Ub Ra Rb LU1..4 KBU KBa KBb AccU AccR
+static const int ADJ_FIELDS = 6;   // U3 R3 KR2 KR1 AccU AccR
 static const int TUNE_SETS = 7;    // independent buffer sets the tuner rotates through
 
 static size_t rk4_fields_bytes(const s4_box *b, int nbox)
@@ -1071,9 +1071,21 @@ int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const
 }
 
 // RK4 stage tables for all boxes: stage s reads u_s (stencil) and writes the
-// next stage input; the accumulators hold y_n + sum_{r<=s} b_r k_r.
+// next stage input; the accumulators hold y_n + sum_{r<=s} b_r k_r.  The
+// step reads y_n from (uin, rin) and its last stage writes (uout, rout).
+static void rk4_tables_io(const s4_box *b, int nbox, const double *const *uin, const double *const *rin,
+                          double *const *uout, double *const *rout, const double *const *c2, char *ws,
+                          const Cand &c, std::vector<DevBox> &tab);
+
 static void rk4_tables(const s4_box *b, int nbox, double *const *u, double *const *rho,
                        const double *const *c2, char *ws, const Cand &c, std::vector<DevBox> &tab)
+{
+    rk4_tables_io(b, nbox, u, rho, u, rho, c2, ws, c, tab);
+}
+
+static void rk4_tables_io(const s4_box *b, int nbox, const double *const *uin, const double *const *rin,
+                          double *const *uout, double *const *rout, const double *const *c2, char *ws,
+                          const Cand &c, std::vector<DevBox> &tab)
 {
     tab.assign(4 * (size_t)nbox, DevBox{});
     size_t off = 0;
@@ -1085,10 +1097,10 @@ static void rk4_tables(const s4_box *b, int nbox, double *const *u, double *cons
             F[k] = ws_field(ws + off + k * fb, b[i]);
         off += RK4_FIELDS * fb;
         double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3], *AU = F[4], *AR = F[5];
-        const double *in_[4] = {u[i], Ua, Ub, Ua};
-        const double *rs_[4] = {rho[i], Ra, Rb, Ra};
-        double *uo_[4] = {Ua, Ub, Ua, u[i]};
-        double *ro_[4] = {Ra, Rb, Ra, rho[i]};
+        const double *in_[4] = {uin[i], Ua, Ub, Ua};
+        const double *rs_[4] = {rin[i], Ra, Rb, Ra};
+        double *uo_[4] = {Ua, Ub, Ua, uout[i]};
+        double *ro_[4] = {Ra, Rb, Ra, rout[i]};
         DevBox D = devbox(b[i], c);
         D.item0 = item0;
         item0 += (int)dev_items(D);
@@ -1096,8 +1108,8 @@ static void rk4_tables(const s4_box *b, int nbox, double *const *u, double *cons
             DevBox E = D;
             E.in = in_[s];
             E.p[0] = rs_[s];
-            E.p[1] = u[i];
-            E.p[2] = rho[i];
+            E.p[1] = uin[i];
+            E.p[2] = rin[i];
             E.p[3] = AU;
             E.p[4] = AR;
             E.p[5] = c2 ? c2[i] : nullptr;
@@ -1355,6 +1367,56 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
     return S4_OK;
 }
 
+int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                   double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !u_in || !rho_in || !u_out || !rho_out)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = check_boxes(b, 1, S4_OP_RK4);
+    if (r)
+        return r;
+    if (!(std::isfinite(dt) && dt > 0.0))
+        return fail(S4_EINVAL, "dt must be finite and > 0");
+    if ((r = check_ptr(u_in, "u_in", 0)) || (r = check_ptr(rho_in, "rho_in", 0)) ||
+        (r = check_ptr(u_out, "u_out", 0)) || (r = check_ptr(rho_out, "rho_out", 0)) ||
+        (r = check_ptr(c2, "c2", 0, true)))
+        return r;
+    const size_t need = rk4_fields_bytes(b, 1) + rk4_table_bytes(1);
+    if (!workspace)
+        return fail(S4_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255)
+        return fail(S4_ELAYOUT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    const size_t n = (size_t)box_elems(b[0]) * 8;
+    const std::vector<Range> wr = {{u_out, n, "u_out", 0}, {rho_out, n, "rho_out", 0}, {workspace, need, "workspace", 0}};
+    std::vector<Range> all = wr;
+    all.push_back({u_in, n, "u_in", 0});
+    all.push_back({rho_in, n, "rho_in", 0});
+    if (c2)
+        all.push_back({c2, n, "c2", 0});
+    if ((r = check_disjoint(wr, all)))
+        return r;
+    hipStream_t s = (hipStream_t)stream;
+    const Choice ch = choose(ctx, S4_OP_RK4, b, 1);
+    OnlineTimer tm(ctx, ch, s);
+    const Cand &c = cands()[ch.cand];
+    if (c.variant == 1 || c.variant == 3) {
+        r = rk4_pair_step(ctx, c, b[0], u_in, rho_in, u_out, rho_out, c2, pair_fields(b[0], (char *)workspace), dt,
+                          s);
+    } else {
+        std::vector<DevBox> tab;
+        double *uo[1] = {u_out}, *ro[1] = {rho_out};
+        const double *ui[1] = {u_in}, *ri[1] = {rho_in}, *c2v[1] = {c2};
+        rk4_tables_io(b, 1, ui, ri, uo, ro, c2 ? c2v : nullptr, (char *)workspace, c, tab);
+        r = rk4_step(ctx, c, tab, 1, false, nullptr, nullptr, dev_items(tab[0]), dt, s);
+    }
+    if (r)
+        return r;
+    tm.stop(1.0);
+    return S4_OK;
+}
+
 // the launches of s4_rk4 for choice ch (arguments already validated)
 static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, double *const *u, double *const *rho,
                    const double *const *c2, double dt, int nsteps, int mode, void *workspace, hipStream_t s)
@@ -1477,73 +1539,69 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
 
 // The eight launches of one backward RK4 step: forward recompute of the
 // stage states storing L u_s, then the adjoint stages 4, 3, 2, 1.
+// One backward RK4 step: with c2_bar, the forward stage-pair kernel gives
+// u_3 and rho_3; then the two adjoint passes (stages 4-3, then 2-1).
+// Workspace fields: U3 R3 KR2 KR1 ACU ACR.
 static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *u_n, const double *rho_n,
                                const double *c2, double dt, double *lam_u, double *lam_rho, double *c2_bar,
                                char *ws, hipStream_t s)
 {
-    int r;
     const size_t fb = field_bytes(b);
     double *F[ADJ_FIELDS];
     for (int k = 0; k < ADJ_FIELDS; ++k)
         F[k] = ws_field(ws + k * fb, b);
-    double *Ua = F[0], *Ub = F[1], *Ra = F[2], *Rb = F[3];
-    double *LU[4] = {F[4], F[5], F[6], F[7]};
-    double *KBU = F[8], *KBa = F[9], *KBb = F[10], *ACU = F[11], *ACR = F[12];
-    const DevBox D0 = devbox(b, c);
-
-    // forward recompute of the stage states, storing L u_s
-    static const double Afw[4] = {0.5, 0.5, 1.0, 0.0};
-    const double *in_[4] = {u_n, Ua, Ub, Ua};
-    const double *rs_[4] = {rho_n, Ra, Rb, Ra};
-    double *uo_[4] = {Ua, Ub, Ua, nullptr};
-    double *ro_[4] = {Ra, Rb, Ra, nullptr};
-    for (int st = 0; st < 4; ++st) {
-        DevBox E = D0;
-        E.in = in_[st];
-        E.p[0] = rs_[st];
-        E.p[1] = u_n;
-        E.p[2] = rho_n;
-        E.p[5] = c2;
-        E.q[0] = uo_[st];
-        E.q[1] = ro_[st];
-        E.q[2] = LU[st];
-        StageCoef K{};
-        K.stage = st + 1;
-        K.a = Afw[st] * dt;
-        K.scale = 1.0;
-        if ((r = launch_one(ctx, OP_FWDREC, c, E, K, s)))
-            return r;
+    double *U3 = F[0], *R3 = F[1], *KR2 = F[2], *KR1 = F[3], *ACU = F[4], *ACR = F[5];
+    const bool cb = c2_bar != nullptr;
+    hipError_t e;
+    if (cb) {
+        const Cand &pc = cands()[cand_index(64, 4, 32, 3)];
+        DevBox A = devbox(b, pc);
+        A.in = u_n;
+        A.p[0] = rho_n;
+        A.p[5] = c2;
+        A.q[0] = U3;
+        A.q[1] = R3;
+        e = launch_pair2(0, pc.tx, pc.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), (int)dev_items(A), ctx->nxcd, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "forward stage-pair launch");
     }
-    // reverse sweep over the stages: 4, 3, 2, 1
-    static const double Cw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    const double *kin[4] = {KBa, KBb, KBa, lam_rho}; // stencil input of adjoint stage s (index s-1)
-    double *kout[4] = {lam_rho, KBa, KBb, KBa};      // kb_rho written by stage s
-    for (int st = 3; st >= 0; --st) {
-        DevBox E = D0;
-        E.in = kin[st];
-        E.inmul = c2;
-        E.p[0] = KBU;
-        E.p[1] = lam_u;
-        E.p[2] = lam_rho;
-        E.p[3] = ACU;
-        E.p[4] = ACR;
-        E.p[5] = LU[st];
-        E.p[6] = c2_bar;
-        E.q[0] = st == 0 ? lam_u : KBU;
-        E.q[1] = kout[st];
-        E.q[2] = ACU;
-        E.q[3] = ACR;
-        E.q[4] = c2_bar;
-        StageCoef K{};
-        K.stage = st + 1;
-        K.scale = st == 3 ? Cw[3] * dt : 1.0;
-        if (st > 0) {
-            K.b_next = Cw[st - 1] * dt;
-            K.a_next = Afw[st - 1] * dt;
-        }
-        if ((r = launch_one(ctx, OP_ADJSTAGE, c, E, K, s)))
-            return r;
-    }
+    StageCoef K{};
+    K.a = dt;
+    K.b = dt / 6.0;
+    K.a_next = dt / 3.0;
+    K.b_next = dt / 2.0;
+    K.scale = 1.0;
+    const DevBox D = devbox(b, c);
+    const int items = (int)dev_items(D);
+    DevBox E = D;
+    E.in = lam_u;
+    E.p[0] = lam_rho;
+    E.p[1] = U3;
+    E.p[2] = u_n;
+    E.p[3] = R3;
+    E.p[5] = c2;
+    E.p[6] = c2_bar;
+    E.q[0] = KR2;
+    E.q[1] = KR1;
+    E.q[2] = ACU;
+    E.q[3] = ACR;
+    E.q[4] = c2_bar;
+    if ((e = launch_adj2(0, c.tx, c.nw, cb, E, K, items, ctx->nxcd, s)) != hipSuccess)
+        return hip_fail(e, "adjoint pass launch");
+    E = D;
+    E.in = KR2;
+    E.p[0] = KR1;
+    E.p[1] = u_n;
+    E.p[2] = rho_n;
+    E.p[3] = ACU;
+    E.p[4] = ACR;
+    E.p[5] = c2;
+    E.p[6] = c2_bar;
+    E.q[0] = lam_u;
+    E.q[1] = lam_rho;
+    E.q[4] = c2_bar;
+    if ((e = launch_adj2(1, c.tx, c.nw, cb, E, K, items, ctx->nxcd, s)) != hipSuccess)
+        return hip_fail(e, "adjoint pass launch");
     return S4_OK;
 }
 

@@ -25,12 +25,11 @@ namespace s4 {
 
 // kinds of per-point work that ride on the tile traversal
 enum Op : int {
-    OP_RHS = 0,      // rho_t = c2 * L(u)                      (ghosts read)
-    OP_STAGE = 1,    // one fused RK4 stage                     (periodic addressing)
-    OP_ADJRHS = 2,   // (L(c2*lrho), lu)                        (periodic addressing)
-    OP_FWDREC = 3,   // forward stage recompute storing L(u_s)  (periodic addressing)
-    OP_ADJSTAGE = 4, // one fused adjoint RK4 stage             (periodic addressing)
-    OP_COUNT = 5
+    OP_RHS = 0,     // rho_t = c2 * L(u)                      (ghosts read)
+    OP_STAGE = 1,   // one fused RK4 stage                     (periodic addressing)
+    OP_ADJRHS = 2,  // (L(c2*lrho), lu)                        (periodic addressing)
+    OP_ADJSTEP = 3, // backward RK4 step (two passes of k_adj2, not a tile-traversal op)
+    OP_COUNT = 4
 };
 
 // One box as the kernels see it: geometry, stencil coefficients, the tile
@@ -66,14 +65,15 @@ struct MixArgs {
     int32_t items;
 };
 
-// Scalars of one stage launch.
+// Scalars of one stage launch.  The backward step's passes (k_adj2) use
+// a = dt, b = dt/6, a_next = dt/3, b_next = dt/2.
 struct StageCoef {
     int stage;      // 1..4
     double a;       // dt * (1/2, 1/2, 1, -)  weight of k_s in the next stage input
     double b;       // dt * (1/6, 1/3, 1/3, 1/6)  weight of k_s in y_{n+1}
-    double scale;   // multiplier of the stencil input (adjoint stage 4: dt/6)
-    double b_next;  // adjoint: dt * c_{s-1}
-    double a_next;  // adjoint: dt * a_{s-1}
+    double scale;   // unused by the kernels (set to 1)
+    double b_next;
+    double a_next;
 };
 
 template <int TX, int NW>

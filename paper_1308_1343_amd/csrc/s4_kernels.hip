@@ -51,7 +51,7 @@ __device__ __forceinline__ double ldp(const double *p)
 // before plane k is computed.  pw_load reads the streams an op needs at the
 // point c; pw_apply combines them with the stencil result and stores.
 // center: the stencil input at the point (after the input transform);
-// raw: scale * in[c]; lap: L of the transformed input.
+// lap: L of the transformed input.
 
 struct PW {
     double v[6];
@@ -75,30 +75,12 @@ __device__ __forceinline__ void pw_load(const DevBox &B, const StageCoef &K, int
         }
     } else if constexpr (OPK == OP_ADJRHS) {
         w.v[0] = ldp(B.p[0] + c); // lu
-    } else if constexpr (OPK == OP_FWDREC) {
-        if (K.stage < 4) {
-            w.v[0] = B.p[5] ? ldp(B.p[5] + c) : 1.0; // c^2
-            w.v[1] = ldp(B.p[0] + c);                // rho_s
-            if (K.stage > 1) {
-                w.v[2] = ldp(B.p[1] + c); // u_n
-                w.v[3] = ldp(B.p[2] + c); // rho_n
-            }
-        }
-    } else if constexpr (OPK == OP_ADJSTAGE) {
-        w.v[0] = ldp(B.p[1] + c); // lam_u (ybar)
-        w.v[1] = ldp(B.p[2] + c); // lam_rho
-        if (K.stage < 4) {
-            w.v[2] = ldp(B.p[0] + c); // kb_u
-            w.v[3] = ldp(B.p[3] + c); // acc_u
-            w.v[4] = ldp(B.p[4] + c); // acc_rho
-        }
-        w.v[5] = B.q[4] ? ldp(B.p[5] + c) : 0.0; // L u_s
     }
 }
 
 template <int OPK>
-__device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, int64_t c, double center,
-                                         double raw, double lap, const PW &w)
+__device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, int64_t c, double center, double lap,
+                                         const PW &w)
 {
     if constexpr (OPK == OP_RHS) {
         // rho_t = c^2 L u   (c2 optional)
@@ -132,41 +114,6 @@ __device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, in
         // F^T(lu, lrho) = (L(c^2 lrho), lu)
         st(B.q[0] + c, lap);
         st(B.q[1] + c, w.v[0]);
-    } else if constexpr (OPK == OP_FWDREC) {
-        // forward stage recompute: store L u_s; next stage input (u, rho)
-        st(B.q[2] + c, lap);
-        if (K.stage < 4) {
-            const double kr = B.p[5] ? w.v[0] * lap : lap;
-            const double ku = w.v[1];
-            const double un = K.stage == 1 ? center : w.v[2];
-            const double rn = K.stage == 1 ? ku : w.v[3];
-            st(B.q[0] + c, fma(K.a, ku, un));
-            st(B.q[1] + c, fma(K.a, kr, rn));
-        }
-    } else if constexpr (OPK == OP_ADJSTAGE) {
-        // adjoint stage s: yb_s = F^T(kb_s) = (L(c^2 kb_rho), kb_u);
-        // c2bar += kb_rho * L u_s; acc += yb_s;
-        // kb_{s-1} = dt c_{s-1} ybar + dt a_{s-1} yb_s   (s > 1)
-        // ybar_n = ybar + acc                              (s == 1)
-        const double lu = w.v[0], lr = w.v[1];
-        const double kbu = K.stage == 4 ? K.scale * lu : w.v[2];
-        const double ybu = lap, ybr = kbu;
-        if (B.q[4])
-            st(B.q[4] + c, fma(raw, w.v[5], ldp(B.p[6] + c)));
-        double accu = ybu, accr = ybr;
-        if (K.stage < 4) {
-            accu = w.v[3] + ybu;
-            accr = w.v[4] + ybr;
-        }
-        if (K.stage > 1) {
-            st(B.q[0] + c, fma(K.a_next, ybu, K.b_next * lu));
-            st(B.q[1] + c, fma(K.a_next, ybr, K.b_next * lr));
-            st(B.q[2] + c, accu);
-            st(B.q[3] + c, accr);
-        } else {
-            st(B.q[0] + c, lu + accu);
-            st(B.q[1] + c, lr + accr);
-        }
     }
 }
 
@@ -186,32 +133,22 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
     const int lc = w.lc;
     const double *in = B.in;
     const double *mul = B.inmul;
-    const double scale = K.scale;
 
-    // input transform: w = mul * (scale * in); raw = scale * in
-    auto ldw = [&](int64_t e, double &raw) -> double {
-        double v = in[e];
-        if (OPK == OP_ADJSTAGE)
-            v = scale * v;
-        raw = v;
-        if (mul)
-            v = mul[e] * v;
-        return v;
-    };
+    // input transform: mul * in (mul optional)
+    auto ldw = [&](int64_t e) -> double { return mul ? mul[e] * in[e] : in[e]; };
 
-    double r2, r3, r4, rd;
-    double q0 = ldw(w.col + w.zoff(P.z0 - 2), rd);
-    double q1 = ldw(w.col + w.zoff(P.z0 - 1), rd);
-    double q2 = ldw(w.col + w.zoff(P.z0), r2);
-    double q3 = ldw(w.col + w.zoff(P.z0 + 1), r3);
-    double q4 = ldw(w.col + w.zoff(P.z0 + 2), r4);
+    double q0 = ldw(w.col + w.zoff(P.z0 - 2));
+    double q1 = ldw(w.col + w.zoff(P.z0 - 1));
+    double q2 = ldw(w.col + w.zoff(P.z0));
+    double q3 = ldw(w.col + w.zoff(P.z0 + 1));
+    double q4 = ldw(w.col + w.zoff(P.z0 + 2));
     double hv[T::HS];
     {
         const int64_t zo = w.zoff(P.z0);
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
-                hv[s] = ldw(w.hcol[s] + zo, rd);
+                hv[s] = ldw(w.hcol[s] + zo);
     }
     PW pw;
     if (w.active)
@@ -225,15 +162,15 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
             if (w.hl[s] >= 0)
                 L[w.hl[s]] = hv[s];
         __syncthreads();
-        double q4n = 0.0, r4n = 0.0, hvn[T::HS];
+        double q4n = 0.0, hvn[T::HS];
         PW pwn;
         if (k + 1 < P.z1) {
-            q4n = ldw(w.col + w.zoff(k + 3), r4n);
+            q4n = ldw(w.col + w.zoff(k + 3));
             const int64_t zo = w.zoff(k + 1);
 #pragma unroll
             for (int s = 0; s < T::HS; ++s)
                 if (w.hl[s] >= 0)
-                    hvn[s] = ldw(w.hcol[s] + zo, rd);
+                    hvn[s] = ldw(w.hcol[s] + zo);
             if (w.active)
                 pw_load<OPK>(B, K, w.point(B, k + 1), pwn);
         }
@@ -241,16 +178,13 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
             const double lap = lap4(B, q2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2],
                                     L[lc - 2 * T::LX], L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX],
                                     q0, q1, q3, q4);
-            pw_apply<OPK>(B, K, w.point(B, k), q2, r2, lap, pw);
+            pw_apply<OPK>(B, K, w.point(B, k), q2, lap, pw);
         }
         q0 = q1;
         q1 = q2;
         q2 = q3;
         q3 = q4;
         q4 = q4n;
-        r2 = r3;
-        r3 = r4;
-        r4 = r4n;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             hv[s] = hvn[s];
@@ -345,7 +279,6 @@ __device__ __forceinline__ double lane_value(double v, int l)
 template <int RY, int OPK>
 struct RowPlane {
     double c[RY];    // rows j0 .. j0+RY-1 at plane p+2 (transformed)
-    double craw[RY]; // their raw values (adjoint stage only)
     double ym[2];    // rows j0-2, j0-1 at plane p
     double yp[2];    // rows j0+RY, j0+RY+1 at plane p
     double h[RY];    // x halo of each row at plane p (lanes 0..3)
@@ -360,46 +293,32 @@ __device__ __forceinline__ void run_rows(const DevBox &B, const ItemPos &P, cons
         return;
     const double *in = B.in;
     const double *mul = B.inmul;
-    const double scale = K.scale;
-    auto ldw = [&](int64_t e, double &raw) -> double {
-        double v = in[e];
-        if (OPK == OP_ADJSTAGE)
-            v = scale * v;
-        raw = v;
-        if (mul)
-            v = mul[e] * v;
-        return v;
-    };
+    auto ldw = [&](int64_t e) -> double { return mul ? mul[e] * in[e] : in[e]; };
     auto load = [&](int p, RowPlane<RY, OPK> &L) {
         const int64_t z2 = w.zoff(p + 2), z0 = w.zoff(p);
-        double rd;
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            L.c[r] = ldw(w.xc + w.roff[r + 2] + z2, L.craw[r]);
-        L.ym[0] = ldw(w.xc + w.roff[0] + z0, rd);
-        L.ym[1] = ldw(w.xc + w.roff[1] + z0, rd);
-        L.yp[0] = ldw(w.xc + w.roff[RY + 2] + z0, rd);
-        L.yp[1] = ldw(w.xc + w.roff[RY + 3] + z0, rd);
+            L.c[r] = ldw(w.xc + w.roff[r + 2] + z2);
+        L.ym[0] = ldw(w.xc + w.roff[0] + z0);
+        L.ym[1] = ldw(w.xc + w.roff[1] + z0);
+        L.yp[0] = ldw(w.xc + w.roff[RY + 2] + z0);
+        L.yp[1] = ldw(w.xc + w.roff[RY + 3] + z0);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
-            L.h[r] = lane < 4 ? ldw(w.hx + w.roff[r + 2] + z0, rd) : 0.0;
+            L.h[r] = lane < 4 ? ldw(w.hx + w.roff[r + 2] + z0) : 0.0;
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             if (w.active_x && w.row_in(r))
                 pw_load<OPK>(B, K, w.point(B, r, p), L.pw[r]);
     };
-    // per-row z queues of the transformed input (planes k-2 .. k+2) and, for
-    // the adjoint stage, of the raw input (planes k .. k+2)
-    double q[RY][5], rq[RY][3];
-    {
-        double rd;
+    // per-row z queues of the transformed input (planes k-2 .. k+2)
+    double q[RY][5];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            q[r][1] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 2), rd);
-            q[r][2] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 1), rd);
-            q[r][3] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0), rq[r][1]);
-            q[r][4] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 + 1), rq[r][2]);
-        }
+    for (int r = 0; r < RY; ++r) {
+        q[r][1] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 2));
+        q[r][2] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 - 1));
+        q[r][3] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0));
+        q[r][4] = ldw(w.xc + w.roff[r + 2] + w.zoff(P.z0 + 1));
     }
     auto compute = [&](int k, const RowPlane<RY, OPK> &L) {
 #pragma unroll
@@ -408,9 +327,6 @@ __device__ __forceinline__ void run_rows(const DevBox &B, const ItemPos &P, cons
             for (int d = 0; d < 4; ++d)
                 q[r][d] = q[r][d + 1];
             q[r][4] = L.c[r];
-            rq[r][0] = rq[r][1];
-            rq[r][1] = rq[r][2];
-            rq[r][2] = L.craw[r];
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -425,7 +341,7 @@ __device__ __forceinline__ void run_rows(const DevBox &B, const ItemPos &P, cons
             const double yp2 = r + 2 < RY ? q[r + 2 < RY ? r + 2 : 0][2] : L.yp[r + 2 - RY >= 0 ? r + 2 - RY : 0];
             const double lap = lap4(B, c0, xm2, xm1, xp1, xp2, ym2, ym1, yp1, yp2, q[r][0], q[r][1], q[r][3], q[r][4]);
             if (w.active_x && w.row_in(r))
-                pw_apply<OPK>(B, K, w.point(B, r, k), c0, rq[r][0], lap, L.pw[r]);
+                pw_apply<OPK>(B, K, w.point(B, r, k), c0, lap, L.pw[r]);
         }
     };
     const int z0 = P.z0, z1 = P.z1;
@@ -785,8 +701,10 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
                 const int64_t c = w.point(B, k);
                 st(B.q[0] + c, fma(a2, r2, un));
                 st(B.q[1] + c, fma(a2, kr2, rn));
-                st(B.q[2] + c, fma(K2.b, r2, fma(1.0 / 3.0, u2 - un, un)));
-                st(B.q[3] + c, fma(K2.b, kr2, fma(1.0 / 3.0, r2 - rn, rn)));
+                if (B.q[2]) { // the running sums (not needed when only u_3, rho_3 are wanted)
+                    st(B.q[2] + c, fma(K2.b, r2, fma(1.0 / 3.0, u2 - un, un)));
+                    st(B.q[3] + c, fma(K2.b, kr2, fma(1.0 / 3.0, r2 - rn, rn)));
+                }
             } else {
                 const double *L2 = L + 2 * PLANE;
                 // stage 3: L u_3
@@ -872,6 +790,211 @@ __global__ __launch_bounds__(NW * 64) void k_pair2_batched(const DevBox *__restr
             atomicExch(&counter[0], 0);
             atomicExch(&counter[1], 0);
         }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// One backward RK4 step in two passes.  The adjoint of F(u, rho) =
+// (rho, c^2 L u) is F^T(a, b) = (L(c^2 b), a) (L symmetric under periodic
+// addressing).  With kb_s = (ku_s, kr_s) and lambda = (lu, lr) = dJ/dy_{n+1}:
+//   ku4 = dt/6 lu, kr4 = dt/6 lr, kr3 = dt/3 lr + dt ku4          (pointwise)
+//   ku3 = dt/3 lu + dt L(c^2 kr4),   ku2 = dt/3 lu + dt/2 L(c^2 kr3)
+//   kr2 = dt/3 lr + dt/2 ku3,        kr1 = dt/6 lr + dt/2 ku2
+//   ku1 = dt/6 lu + dt/2 L(c^2 kr2)
+//   dJ/dy_n = (lu + sum_s L(c^2 kr_s), lr + sum_s ku_s)
+//   c2bar  += sum_s kr_s L u_s
+// Pass A stencils c^2 kr4 and c^2 kr3, formed at every tap from taps of lu,
+// lr and c^2, and stores kr2, kr1 and the partial sums; pass B stencils
+// c^2 kr2 and c^2 kr1 and writes dJ/dy_n over lambda (pass B reads lambda
+// only at the point).  With c2bar, pass A also applies L to u_3 and to
+// u_4 = u_n + dt rho_3 (formed per tap; u_3, rho_3 from the forward
+// stage-pair kernel) and pass B to u_1 = u_n and u_2 = u_n + dt/2 rho_n.
+// The LDS and the z queues hold the transformed values t (NL fields); the
+// raw values two planes ahead are loaded into registers first.
+//   pass A:  in lu, p0 lr, p1 u_3, p2 u_n, p3 rho_3, p5 c^2, p6 c2bar;
+//            out q0 kr2, q1 kr1, q2 acc_u, q3 acc_rho, q4 c2bar
+//   pass B:  in kr2, p0 kr1, p1 u_n, p2 rho_n, p3 acc_u, p4 acc_rho, p5 c^2,
+//            p6 c2bar; out q0 lambda_u (read first), q1 lambda_rho, q4 c2bar
+// K: a = dt, b = dt/6, a_next = dt/3, b_next = dt/2.
+
+template <int PASS, bool C2BAR>
+struct AdjPass {
+    static constexpr int NL = C2BAR ? 4 : 2; // transformed stencil fields
+    static constexpr int NR = C2BAR ? 6 : 3; // raw fields read per tap
+};
+
+template <int PASS, bool C2BAR>
+__device__ __forceinline__ void adj_raw(const DevBox &B, int64_t e, double *r)
+{
+    r[0] = B.in[e];
+    r[1] = B.p[0][e];
+    r[2] = B.p[5] ? B.p[5][e] : 1.0;
+    if constexpr (C2BAR) {
+        if constexpr (PASS == 0) {
+            r[3] = B.p[1][e]; // u_3
+            r[4] = B.p[2][e]; // u_n
+            r[5] = B.p[3][e]; // rho_3
+        } else {
+            r[3] = B.p[1][e]; // u_n
+            r[4] = B.p[2][e]; // rho_n
+        }
+    }
+}
+
+// transformed values from the raw ones
+template <int PASS, bool C2BAR>
+__device__ __forceinline__ void adj_tf(const StageCoef &K, const double *r, double *t)
+{
+    if constexpr (PASS == 0) {
+        const double ku4 = K.b * r[0], kr4 = K.b * r[1];
+        const double kr3 = fma(K.a, ku4, K.a_next * r[1]);
+        t[0] = r[2] * kr4;
+        t[1] = r[2] * kr3;
+        if constexpr (C2BAR) {
+            t[2] = r[3];
+            t[3] = fma(K.a, r[5], r[4]);
+        }
+    } else {
+        t[0] = r[2] * r[0];
+        t[1] = r[2] * r[1];
+        if constexpr (C2BAR) {
+            t[2] = r[3];
+            t[3] = fma(K.b_next, r[4], r[3]);
+        }
+    }
+}
+
+template <int TX, int NW, int PASS, bool C2BAR>
+__global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxcd)
+{
+    using T = Tile<TX, NW>;
+    using A = AdjPass<PASS, C2BAR>;
+    constexpr int NL = A::NL, NR = A::NR;
+    constexpr int PLANE = T::LY * T::LX;
+    __shared__ double lds[2 * NL * PLANE];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, TX, T::TY);
+    const Walker<TX, NW, true> w(B, P, threadIdx.x);
+    const int lc = w.lc;
+
+    // z queues of the transformed fields (planes k-2 .. k+2) and of the two
+    // raw values needed at the point (planes k .. k+2)
+    double q[NL][5], rq[2][3];
+    double nr[NR], nh[T::HS][NR]; // raw loads of the next plane: own column (plane k+3), halo (plane k+1)
+    double hv[NL][T::HS];
+    {
+        double r[NR], t[NL];
+        for (int d = 0; d < 5; ++d) {
+            adj_raw<PASS, C2BAR>(B, w.col + w.zoff(P.z0 - 2 + d), r);
+            adj_tf<PASS, C2BAR>(K, r, t);
+#pragma unroll
+            for (int f = 0; f < NL; ++f)
+                q[f][d] = t[f];
+            if (d >= 2) {
+                rq[0][d - 2] = r[0];
+                rq[1][d - 2] = r[1];
+            }
+        }
+        const int64_t zo = w.zoff(P.z0);
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0) {
+                adj_raw<PASS, C2BAR>(B, w.hcol[s] + zo, r);
+                adj_tf<PASS, C2BAR>(K, r, t);
+#pragma unroll
+                for (int f = 0; f < NL; ++f)
+                    hv[f][s] = t[f];
+            }
+    }
+    int buf = 0;
+    for (int k = P.z0; k < P.z1; ++k) {
+        double *L = lds + buf * NL * PLANE;
+#pragma unroll
+        for (int f = 0; f < NL; ++f) {
+            L[f * PLANE + lc] = q[f][2];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    L[f * PLANE + w.hl[s]] = hv[f][s];
+        }
+        __syncthreads();
+        const bool more = k + 1 < P.z1;
+        if (more) {
+            adj_raw<PASS, C2BAR>(B, w.col + w.zoff(k + 3), nr);
+            const int64_t z1 = w.zoff(k + 1);
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    adj_raw<PASS, C2BAR>(B, w.hcol[s] + z1, nh[s]);
+        }
+        if (w.active) {
+            const int64_t c = w.point(B, k);
+            auto lapf = [&](int f) {
+                const double *Lf = L + f * PLANE;
+                return lap4(B, q[f][2], Lf[lc - 2], Lf[lc - 1], Lf[lc + 1], Lf[lc + 2], Lf[lc - 2 * T::LX],
+                            Lf[lc - T::LX], Lf[lc + T::LX], Lf[lc + 2 * T::LX], q[f][0], q[f][1], q[f][3], q[f][4]);
+            };
+            const double dt = K.a, d6 = K.b, d3 = K.a_next, d2 = K.b_next;
+            if constexpr (PASS == 0) {
+                const double lu = rq[0][0], lr = rq[1][0];
+                const double Y4 = lapf(0), Y3 = lapf(1);
+                const double ku4 = d6 * lu, kr4 = d6 * lr;
+                const double kr3 = fma(dt, ku4, d3 * lr);
+                const double ku3 = fma(dt, Y4, d3 * lu);
+                const double ku2 = fma(d2, Y3, d3 * lu);
+                const double kr2 = fma(d2, ku3, d3 * lr);
+                const double kr1 = fma(d2, ku2, d6 * lr);
+                st(B.q[0] + c, kr2);
+                st(B.q[1] + c, kr1);
+                st(B.q[2] + c, lu + Y4 + Y3);
+                st(B.q[3] + c, lr + ku4 + ku3 + ku2);
+                if constexpr (C2BAR) {
+                    const double Lu3 = lapf(2), Lu4 = lapf(3);
+                    st(B.q[4] + c, fma(kr4, Lu4, fma(kr3, Lu3, ldp(B.p[6] + c))));
+                }
+            } else {
+                const double kr2 = rq[0][0], kr1 = rq[1][0];
+                const double Y2 = lapf(0), Y1 = lapf(1);
+                const double lu = ldp(B.q[0] + c);
+                const double ku1 = fma(d2, Y2, d6 * lu);
+                st(B.q[0] + c, ldp(B.p[3] + c) + Y2 + Y1);
+                st(B.q[1] + c, ldp(B.p[4] + c) + ku1);
+                if constexpr (C2BAR) {
+                    const double Lu1 = lapf(2), Lu2 = lapf(3);
+                    st(B.q[4] + c, fma(kr2, Lu2, fma(kr1, Lu1, ldp(B.p[6] + c))));
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NL; ++f) {
+            q[f][0] = q[f][1];
+            q[f][1] = q[f][2];
+            q[f][2] = q[f][3];
+            q[f][3] = q[f][4];
+        }
+        rq[0][0] = rq[0][1];
+        rq[0][1] = rq[0][2];
+        rq[1][0] = rq[1][1];
+        rq[1][1] = rq[1][2];
+        if (more) {
+            double t[NL];
+            adj_tf<PASS, C2BAR>(K, nr, t);
+#pragma unroll
+            for (int f = 0; f < NL; ++f)
+                q[f][4] = t[f];
+            rq[0][2] = nr[0];
+            rq[1][2] = nr[1];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0) {
+                    adj_tf<PASS, C2BAR>(K, nh[s], t);
+#pragma unroll
+                    for (int f = 0; f < NL; ++f)
+                        hv[f][s] = t[f];
+                }
+        }
+        buf ^= 1;
     }
 }
 
@@ -1045,9 +1168,7 @@ static hipError_t launch_batched_t(const DevBox *tab, int nbox, int nitems, int 
     X(TX, NW, false, OP_RHS)                                                                           \
     X(TX, NW, true, OP_STAGE)                                                                          \
     X(TX, NW, false, OP_STAGE)                                                                         \
-    X(TX, NW, true, OP_ADJRHS)                                                                         \
-    X(TX, NW, true, OP_FWDREC)                                                                         \
-    X(TX, NW, true, OP_ADJSTAGE)
+    X(TX, NW, true, OP_ADJRHS)
 
 #define S4_FOR_SHAPES(X)                                                                               \
     S4_FOR_OPS(X, 64, 4)                                                                               \
@@ -1280,6 +1401,27 @@ int max_blocks_pair2(int pair, int tx, int nw, bool ghosted)
     S4_PAIR2_SHAPES(X)
 #undef X
     return e == hipSuccess ? nb : 0;
+}
+
+
+hipError_t launch_adj2(int pass, int tx, int nw, bool c2bar, const DevBox &B, const StageCoef &K, int nitems,
+                       int nxcd, hipStream_t s)
+{
+#define X(TX_, NW_)                                                                                    \
+    if (tx == TX_ && nw == NW_) {                                                                      \
+        if (pass == 0 && !c2bar)                                                                       \
+            hipLaunchKernelGGL((k_adj2<TX_, NW_, 0, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K, nxcd); \
+        else if (pass == 0)                                                                            \
+            hipLaunchKernelGGL((k_adj2<TX_, NW_, 0, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K, nxcd); \
+        else if (!c2bar)                                                                               \
+            hipLaunchKernelGGL((k_adj2<TX_, NW_, 1, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K, nxcd); \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_adj2<TX_, NW_, 1, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B, K, nxcd); \
+        return hipGetLastError();                                                                      \
+    }
+    X(64, 8) X(64, 4) X(32, 8) X(32, 4) X(16, 8) X(16, 4)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fill(const DevBox &B, hipStream_t s)

@@ -50,6 +50,11 @@ hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int
                                 bool ghosted = false);
 int max_blocks_pair2(int pair, int tx, int nw, bool ghosted = false);
 
+// One pass (0: adjoint stages 4-3, 1: stages 2-1) of the two-pass backward
+// RK4 step on one periodic box; c2bar: accumulate dJ/dc^2.
+hipError_t launch_adj2(int pass, int tx, int nw, bool c2bar, const DevBox &B, const StageCoef &K, int nitems,
+                       int nxcd, hipStream_t s);
+
 // Periodic ghost fill of the field q[0] of box B (one thread per ghost point).
 hipError_t launch_fill(const DevBox &B, hipStream_t s);
 

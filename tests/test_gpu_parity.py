@@ -214,6 +214,32 @@ def test_bboxset_stage_pairs_bitwise(ctx, mode, nsteps):
         assert rel(ref[i], wu, g) <= TOL and rel(ref[len(boxes) + i], wr, g) <= TOL
 
 
+def test_rk4_step_to_matches_in_place(ctx):
+    """The out-of-place step equals s4_rk4 on a copy, bit for bit, in every kernel set."""
+    n, g = (37, 19, 23), 2
+    dx = (1 / 37, 1 / 19, 1 / 23)
+    dt = 0.2 / 37
+    u0, r0 = rand_box(n, g, 15, 1), rand_box(n, g, 15, 2)
+    c2 = dev(O.embed(1.0 + 0.5 * W.uniform_pm1(15, 3, n[::-1]), g), g)
+    ui, ri = dev(u0, g), dev(r0, g)
+    b = S.box_of(ui, g, dx)
+    kinds = cands_by_kind(ctx, S.S4_OP_RK4, b)
+    for cand in (kinds["tiles"][3], kinds["rows"][0], kinds["fused"][0], kinds["fused"][-1]):
+        S.s4_set_choice(ctx, S.S4_OP_RK4, b, cand)
+        u, r = dev(u0, g), dev(r0, g)
+        S.s4_rk4(ctx, b, [u], [r], [c2], dt, 1, "perbox")
+        uo, ro = S.alloc_field(n, g, fill=NAN), S.alloc_field(n, g, fill=NAN)
+        S.s4_rk4_step_to(ctx, b, ui, ri, c2, dt, uo, ro)
+        np.testing.assert_array_equal(inner(host(uo), g), inner(host(u), g), err_msg=f"candidate {cand}")
+        np.testing.assert_array_equal(inner(host(ro), g), inner(host(r), g), err_msg=f"candidate {cand}")
+        assert ghosts_untouched(host(uo), g)
+        np.testing.assert_array_equal(inner(host(ui), g), inner(u0, g))  # input untouched
+    S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    with pytest.raises(S.Sten4Error) as e:
+        S.s4_rk4_step_to(ctx, b, ui, ri, None, dt, ui, ro)
+    assert e.value.code == S.S4_EALIAS
+
+
 def test_graph_replays_match_eager(ctx):
     """One captured step replayed several times, with eager work in between."""
     boxes = small_bboxset(11, 5)
