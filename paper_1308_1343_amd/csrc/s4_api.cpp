@@ -111,7 +111,7 @@ static const std::vector<Cand> &cands()
             for (int ry : {4, 2})
                 for (int tz : {64, 32, 16})
                     c.push_back({tx, 4, tz, 2, ry});
-        for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}})
+        for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}, {16, 8}, {16, 4}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 3, 0});
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
@@ -317,10 +317,10 @@ static int64_t items_of(const s4_box &b, const Cand &c)
     return (int64_t)((b.n[0] + tx - 1) / tx) * ((b.n[1] + ty - 1) / ty) * ((b.n[2] + tz - 1) / tz);
 }
 
-// LoopControl-style initial parameters: the widest x tile the boxes fill,
-// 8 wavefronts, and the longest z chunk that still gives every CU about
-// four workgroups.
-static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
+// LoopControl-style initial parameters of the per-operation kernels
+// (variant 0): the widest x tile the boxes fill, 8 wavefronts, and the
+// longest z chunk that still gives every CU about four workgroups.
+static int tile_heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
 {
     int maxnx = 0;
     for (int i = 0; i < nbox; ++i)
@@ -335,6 +335,32 @@ static int heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
             return cand_index(tx, nw, tz);
     }
     return cand_index(tx, nw, 8);
+}
+
+// Starting setting of an op.  RK4 runs two stages per pass with the per-tap
+// stage pairs (variant 3): tile 64 x 4 (whole 512-byte rows) unless idle
+// lanes of ragged boxes would pass a fifth of the lanes, then 32 x 16; the
+// longest z chunk that gives every CU four items (eight over several boxes,
+// whose uneven sizes the work queue balances best in small pieces).
+static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox)
+{
+    if (op != S4_OP_RK4)
+        return tile_heuristic(ctx, b, nbox);
+    double pts = 0, lanes = 0;
+    for (int i = 0; i < nbox; ++i) {
+        pts += (double)b[i].n[0] * b[i].n[1] * b[i].n[2];
+        lanes += (double)((b[i].n[0] + 63) / 64 * 64) * ((b[i].n[1] + 3) / 4 * 4) * b[i].n[2];
+    }
+    const int tx = pts >= 0.8 * lanes ? 64 : 32, nw = tx == 64 ? 4 : 8;
+    const int64_t want = (nbox > 1 ? 8 : 4) * (int64_t)ctx->ncu;
+    for (int tz : {64, 32}) {
+        int64_t items = 0;
+        for (int i = 0; i < nbox; ++i)
+            items += items_of(b[i], {tx, nw, tz, 3, 0});
+        if (items >= want)
+            return cand_index(tx, nw, tz, 3);
+    }
+    return cand_index(tx, nw, 16, 3);
 }
 
 // settings one step away: one parameter moved to its neighbouring value in
@@ -387,7 +413,7 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
     OnlineSetup &st = ctx->online_state[key];
     st.hill.allowed = allowed_cands(op, nbox);
     auto t = ctx->tuned.find(key);
-    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, b, nbox);
+    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, op, b, nbox);
     st.hill.restart_prob = ctx->restart_prob;
     st.hill.rng ^= ctx->seed * 0xD1342543DE82EF95ull + std::hash<std::string>()(key);
     return st;
@@ -411,7 +437,7 @@ static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek =
     auto t = ctx->tuned.find(key);
     if (t != ctx->tuned.end())
         return {t->second, 1, key};
-    return {heuristic(ctx, b, nbox), 0, key};
+    return {heuristic(ctx, op, b, nbox), 0, key};
 }
 
 // Timing of one call for the on-line tuner: events around the call's
@@ -703,9 +729,19 @@ static size_t rk4_fields_bytes(const s4_box *b, int nbox)
     return t;
 }
 
+// counters of the four work queues of one batched RK4 step (one per stage
+// or stage pair, each QUEUE_INTS ints)
+static const size_t QUEUE_BYTES = 4 * QUEUE_INTS * sizeof(int);
+
 static size_t rk4_table_bytes(int nbox)
 {
-    return round256(4 * (size_t)nbox * sizeof(DevBox)) + 256; // 4 stage tables + item counters
+    return round256(4 * (size_t)nbox * sizeof(DevBox)) + QUEUE_BYTES; // 4 stage tables + queue counters
+}
+
+// work queue `slot` (0..3) of a batched step over nitems items, one range per XCD
+static ItemQueue step_queue(const s4_ctx *ctx, int *counters, int slot, int64_t nitems)
+{
+    return ItemQueue{counters + QUEUE_INTS * slot, (int)nitems, std::max(1, std::min(ctx->nxcd, QUEUE_INTS - 1))};
 }
 
 // ---------------------------------------------------------------------------
@@ -852,7 +888,7 @@ int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, in
     s4_ctx sim; // host-only: the heuristic needs the CU count only
     Hill h;
     h.allowed = allowed_cands(op, nbox);
-    h.start = heuristic(&sim, b, nbox);
+    h.start = heuristic(&sim, op, b, nbox);
     h.restart_prob = restart_prob;
     h.rng ^= seed * 0xD1342543DE82EF95ull;
     Hill noise_rng;
@@ -1161,10 +1197,10 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
             const int grid = persistent_grid(ctx, OP_STAGE, c, nitems, gh);
             hipError_t e =
                 c.variant == 2
-                    ? launch_rows_batched(OP_STAGE, c.tx / 64, c.ry, dtab + (size_t)st * nbox, nbox, (int)nitems,
-                                          counters + 2 * st, grid, K, s, gh)
-                    : launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox, (int)nitems,
-                                           counters + 2 * st, grid, K, s, gh);
+                    ? launch_rows_batched(OP_STAGE, c.tx / 64, c.ry, dtab + (size_t)st * nbox, nbox,
+                                          step_queue(ctx, counters, st, nitems), grid, K, s, gh)
+                    : launch_tiles_batched(OP_STAGE, c.tx, c.nw, dtab + (size_t)st * nbox, nbox,
+                                           step_queue(ctx, counters, st, nitems), grid, K, s, gh);
             if (e != hipSuccess)
                 return hip_fail(e, "batched stage launch");
         } else {
@@ -1447,7 +1483,7 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
         if (nsteps % 2 == 0)
             return S4_OK;
         // odd remainder: one step with the per-stage kernels (same arithmetic)
-        const Cand &c0 = cands()[heuristic(ctx, b, nbox)];
+        const Cand &c0 = cands()[tile_heuristic(ctx, b, nbox)];
         std::vector<DevBox> tab0;
         rk4_tables(b, nbox, u, rho, c2, ws, c0, tab0);
         return rk4_step(ctx, c0, tab0, nbox, false, nullptr, nullptr, dev_items(tab0[0]), dt, s);
@@ -1457,7 +1493,7 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
             nsteps % 2 == 0)
             return r;
         // an odd last step with the per-stage kernels (same arithmetic)
-        const Choice c0{heuristic(ctx, b, nbox), 0, ch.key};
+        const Choice c0{tile_heuristic(ctx, b, nbox), 0, ch.key};
         return rk4_run(ctx, c0, b, nbox, u, rho, c2, dt, 1, mode == S4_GRAPH ? S4_BATCHED : mode, workspace, s);
     }
     const Cand &c = cands()[ch.cand];
@@ -1472,8 +1508,8 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
     DevBox *dtab = (DevBox *)(ws + rk4_fields_bytes(b, nbox));
     int *counters = (int *)((char *)dtab + round256(4 * (size_t)nbox * sizeof(DevBox)));
     if (batched) {
-        // table bytes followed by zeroed item counters (8 ints)
-        std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
+        // table bytes followed by zeroed queue counters
+        std::vector<char> bytes(rk4_table_bytes(nbox), 0);
         memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
         if ((r = upload_table(dtab, bytes, s)))
             return r;
@@ -1900,8 +1936,8 @@ static int pair_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab,
             if (per <= 0)
                 per = 2;
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
-            hipError_t e = launch_pair2_batched(k, c.tx, c.nw, dtab + (size_t)t * nbox, nbox, (int)nitems,
-                                                counters + 2 * t, grid, K1, K2, s, gh);
+            hipError_t e = launch_pair2_batched(k, c.tx, c.nw, dtab + (size_t)t * nbox, nbox,
+                                                step_queue(ctx, counters, t, nitems), grid, K1, K2, s, gh);
             if (e != hipSuccess)
                 return hip_fail(e, "batched stage-pair launch");
         } else {
@@ -2004,14 +2040,14 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     hipStream_t s = (hipStream_t)stream;
     int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
     if (cands()[ci].variant == 1) // the widened-tile pairs wrap around one box
-        ci = heuristic(ctx, b, nbox);
+        ci = heuristic(ctx, S4_OP_RK4, b, nbox);
     if (cands()[ci].variant != 3)
         return level_stage_run(ctx, L, ci, u, rho, c2, dt, nsteps, mode, workspace, s);
     if ((r = pair_run(ctx, ci, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, L)) || nsteps % 2 == 0)
         return r;
     // an odd last step with the per-stage kernels (same arithmetic)
-    return level_stage_run(ctx, L, heuristic(ctx, b, nbox), u, rho, c2, dt, 1, mode == S4_GRAPH ? S4_BATCHED : mode,
-                           workspace, s);
+    return level_stage_run(ctx, L, tile_heuristic(ctx, b, nbox), u, rho, c2, dt, 1,
+                           mode == S4_GRAPH ? S4_BATCHED : mode, workspace, s);
 }
 
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)
@@ -2110,7 +2146,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
                 }
             }
             if (batched) {
-                std::vector<char> bytes(round256(4 * (size_t)nbox * sizeof(DevBox)) + 8 * sizeof(int), 0);
+                std::vector<char> bytes(rk4_table_bytes(nbox), 0);
                 memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
                 if ((r = upload_table(dtab, bytes, s)))
                     break;

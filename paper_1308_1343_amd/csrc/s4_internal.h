@@ -89,16 +89,22 @@ struct Tile {
 };
 
 // Position p along an axis of n interior points mapped to an index that may
-// be read: periodic addressing wraps it into [0, n); ghost addressing keeps
-// it (callers never go below -2) but clamps points past n+1, which only
-// lanes outside the box touch, to the last ghost a radius-2 stencil reads.
-S4_HD inline int readable(int p, int n, bool wrap)
+// be read.  Callers never go below -2.  With `clamp`, points past n+1, which
+// only lanes outside the box touch and whose values no radius-2 stencil
+// uses, are clamped to n+1, so idle lanes re-read a line already in flight
+// instead of fetching more rows; traversals whose outer lanes compute values
+// that are used (the widened-tile stage pairs) pass clamp = false.  Periodic
+// addressing then wraps into [0, n); ghost addressing keeps the index
+// (ghosts -2 .. n+1) and always clamps.
+S4_HD inline int readable(int p, int n, bool wrap, bool clamp = true)
 {
+    if (clamp || !wrap)
+        p = p < n + 1 ? p : n + 1;
     if (wrap) {
         int r = p % n;
         return r < 0 ? r + n : r;
     }
-    return p < n + 1 ? p : n + 1;
+    return p;
 }
 
 // element offset of point (i, j, k) from the box's ghost corner
@@ -154,7 +160,7 @@ S4_HD inline void halo_slot(int h, int &lrow, int &lcol, int &dx, int &dy)
 // Per-thread addressing of one work item, shared by the kernels and the
 // host-side geometry test: the thread's own column, its halo slots, the LDS
 // slots it writes, and the element offsets of plane k.
-template <int TX, int NW, bool WRAP>
+template <int TX, int NW, bool WRAP, bool CLAMP = true>
 struct Walker {
     using T = Tile<TX, NW>;
     int i, j;          // interior point of this thread (may lie outside the box)
@@ -176,20 +182,20 @@ struct Walker {
         i = P.x0 + lx;
         j = P.y0 + ly;
         active = i < nx && j < ny;
-        col = (int64_t)(readable(i, nx, WRAP) + g) + (int64_t)(readable(j, ny, WRAP) + g) * B.sy;
+        col = (int64_t)(readable(i, nx, WRAP, CLAMP) + g) + (int64_t)(readable(j, ny, WRAP, CLAMP) + g) * B.sy;
         for (int s = 0; s < T::HS; ++s) {
             const int h = t + s * T::NT;
             int lrow = 0, lcol = 0, dx = 0, dy = 0;
             if (h < T::NH)
                 halo_slot<TX, NW>(h, lrow, lcol, dx, dy);
             hl[s] = h < T::NH ? lrow * T::LX + lcol : -1;
-            hcol[s] = (int64_t)(readable(P.x0 + dx, nx, WRAP) + g) +
-                      (int64_t)(readable(P.y0 + dy, ny, WRAP) + g) * B.sy;
+            hcol[s] = (int64_t)(readable(P.x0 + dx, nx, WRAP, CLAMP) + g) +
+                      (int64_t)(readable(P.y0 + dy, ny, WRAP, CLAMP) + g) * B.sy;
         }
         lc = (ly + 2) * T::LX + (lx + 2);
     }
     // z part of the offset of plane k (k may be a stencil neighbour outside [0, nz))
-    S4_HD int64_t zoff(int k) const { return (int64_t)(readable(k, nz, WRAP) + g) * sz; }
+    S4_HD int64_t zoff(int k) const { return (int64_t)(readable(k, nz, WRAP, CLAMP) + g) * sz; }
     // element offset of the thread's interior point in plane k (active threads only)
     S4_HD int64_t point(const DevBox &B, int k) const
     {
@@ -407,6 +413,51 @@ struct SyncPiece {
     int64_t doff, soff;
     int64_t dsy, dsz, ssy, ssz;
 };
+
+// Work queue of a persistent launch over a table of boxes.  The nitems items
+// (box after box; inside a box x tiles, then y tiles, then z chunks, so that
+// consecutive items are neighbours) are cut into nq contiguous ranges.
+// Workgroup b starts on range b % nq: the hardware places workgroups on the
+// XCDs round-robin, so with nq equal to the XCD count each range is worked
+// under one L2 and neighbouring tiles share their halo lines there.  A
+// workgroup whose range is used up takes items from the following ranges in
+// turn, and stops after finding all nq ranges used up.  counter[0] counts
+// finished workgroups and counter[1 + q] hands out range q; the last
+// workgroup to finish clears them all, so each launch starts from zero
+// without a memset.
+constexpr int QUEUE_INTS = 16; // ints reserved per launch; nq <= QUEUE_INTS - 1
+
+struct ItemQueue {
+    int *counter; // 1 + nq ints, zero before the launch
+    int nitems;
+    int nq;
+};
+
+// first item of range q
+S4_HD inline int queue_lo(int q, int nitems, int nq)
+{
+    return (int)((int64_t)nitems * q / nq);
+}
+
+// Next item of a workgroup, or Q.nitems once every range is used up.  q is
+// the range being worked (start: workgroup index % Q.nq), left the ranges
+// not yet found used up (start: Q.nq).  fetch_add(p) adds one to *p and
+// returns the old value (an atomic on the GPU).
+template <class FetchAdd>
+S4_HD inline int queue_next(const ItemQueue &Q, int &q, int &left, FetchAdd fetch_add)
+{
+    while (left > 0) {
+        const int lo = queue_lo(q, Q.nitems, Q.nq), hi = queue_lo(q + 1, Q.nitems, Q.nq);
+        if (lo < hi) {
+            const int i = fetch_add(&Q.counter[1 + q]);
+            if (i < hi - lo)
+                return lo + i;
+        }
+        q = q + 1 == Q.nq ? 0 : q + 1;
+        --left;
+    }
+    return Q.nitems;
+}
 
 // split a launch of `nblocks` workgroups so that the hardware's round-robin
 // placement (block b runs on XCD b % nxcd) gives each XCD a contiguous range

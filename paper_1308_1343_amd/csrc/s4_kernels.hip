@@ -203,46 +203,59 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_single(DevBox B, StageCoef K,
     run_item<TX, NW, WRAP, OPK>(B, P, K, lds);
 }
 
-// Persistent form: a fixed grid pulls items of all boxes from one counter.
-// counter[0] hands out items, counter[1] counts workgroups that ran out of
-// work; the last one resets both, so every launch starts from zero without
-// a memset.
+// next item of the calling workgroup (thread 0 only), see queue_next
+__device__ inline int queue_take(const ItemQueue &Q, int &q, int &left)
+{
+    return queue_next(Q, q, left, [](int *p) { return atomicAdd(p, 1); });
+}
+
+// thread 0, after its workgroup's last item: the last workgroup clears the counters
+__device__ inline void queue_finish(const ItemQueue &Q)
+{
+    __threadfence();
+    if (atomicAdd(&Q.counter[0], 1) == (int)gridDim.x - 1)
+        for (int q = 0; q <= Q.nq; ++q)
+            atomicExch(&Q.counter[q], 0);
+}
+
+// box of global item `item`: last box with item0 <= item
+__device__ inline int box_of(const DevBox *__restrict__ tab, int nbox, int item)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].item0 <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent form: a fixed grid pulls the items of all boxes from the
+// per-XCD work queue Q.
 template <int TX, int NW, bool WRAP, int OPK>
-__global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restrict__ tab, int nbox,
-                                                          int nitems, int *counter, StageCoef K)
+__global__ __launch_bounds__(NW * 64) void k_tiles_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
+                                                          StageCoef K)
 {
     using T = Tile<TX, NW>;
     __shared__ double lds[2 * T::LY * T::LX];
     __shared__ int s_item;
+    int q = blockIdx.x % Q.nq, left = Q.nq;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
-            s_item = atomicAdd(&counter[0], 1);
+            s_item = queue_take(Q, q, left);
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= nitems)
+        if (item >= Q.nitems)
             break;
-        // box of this item: last box with item0 <= item
-        int lo = 0, hi = nbox - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].item0 <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const DevBox B = tab[lo];
+        const DevBox B = tab[box_of(tab, nbox, item)];
         const ItemPos P = item_pos(B, item - B.item0, TX, T::TY);
         run_item<TX, NW, WRAP, OPK>(B, P, K, lds);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(&counter[1], 1);
-        if (done == (int)gridDim.x - 1) {
-            atomicExch(&counter[0], 0);
-            atomicExch(&counter[1], 0);
-        }
-    }
+    if (threadIdx.x == 0)
+        queue_finish(Q);
 }
 
 
@@ -375,41 +388,28 @@ __global__ __launch_bounds__(WX *WY * 64) void k_rows_single(DevBox B, StageCoef
     run_rows<WX, WY, RY, WRAP, OPK>(B, P, K, wave, threadIdx.x % 64);
 }
 
-// persistent form over a (box, item) queue, as k_tiles_batched
+// persistent form over the per-XCD work queue, as k_tiles_batched
 template <int WX, int WY, int RY, bool WRAP, int OPK>
-__global__ __launch_bounds__(WX *WY * 64) void k_rows_batched(const DevBox *__restrict__ tab, int nbox, int nitems,
-                                                             int *counter, StageCoef K)
+__global__ __launch_bounds__(WX *WY * 64) void k_rows_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
+                                                             StageCoef K)
 {
     __shared__ int s_item;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    int q = blockIdx.x % Q.nq, left = Q.nq;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
-            s_item = atomicAdd(&counter[0], 1);
+            s_item = queue_take(Q, q, left);
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= nitems)
+        if (item >= Q.nitems)
             break;
-        int lo = 0, hi = nbox - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].item0 <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const DevBox B = tab[lo];
+        const DevBox B = tab[box_of(tab, nbox, item)];
         const ItemPos P = item_pos(B, item - B.item0, 64 * WX, RY * WY);
         run_rows<WX, WY, RY, WRAP, OPK>(B, P, K, wave, threadIdx.x % 64);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(&counter[1], 1);
-        if (done == (int)gridDim.x - 1) {
-            atomicExch(&counter[0], 0);
-            atomicExch(&counter[1], 0);
-        }
-    }
+    if (threadIdx.x == 0)
+        queue_finish(Q);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
     ItemPos Pe = P;
     Pe.x0 -= 2;
     Pe.y0 -= 2;
-    const Walker<TXE, NW, true> w(B, Pe, threadIdx.x);
+    const Walker<TXE, NW, true, false> w(B, Pe, threadIdx.x);
     const int lx = threadIdx.x % TXE, ly = threadIdx.x / TXE;
     const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < B.n[0] && w.j < B.n[1];
     const int l2 = ly * TXE + lx;
@@ -756,41 +756,28 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
     run_pair2<TX, NW, PAIR, WRAP>(B, P, K1, K2, lds);
 }
 
-// persistent form over a (box, item) queue, as k_tiles_batched
+// persistent form over the per-XCD work queue, as k_tiles_batched
 template <int TX, int NW, int PAIR, bool WRAP>
-__global__ __launch_bounds__(NW * 64) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, int nitems,
-                                                          int *counter, StageCoef K1, StageCoef K2)
+__global__ __launch_bounds__(NW * 64) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
+                                                          StageCoef K1, StageCoef K2)
 {
     __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
     __shared__ int s_item;
+    int q = blockIdx.x % Q.nq, left = Q.nq;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0)
-            s_item = atomicAdd(&counter[0], 1);
+            s_item = queue_take(Q, q, left);
         __syncthreads();
         const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= nitems)
+        if (item >= Q.nitems)
             break;
-        int lo = 0, hi = nbox - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab[mid].item0 <= item)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const DevBox B = tab[lo];
+        const DevBox B = tab[box_of(tab, nbox, item)];
         const ItemPos P = item_pos(B, item - B.item0, TX, Tile<TX, NW>::TY);
         run_pair2<TX, NW, PAIR, WRAP>(B, P, K1, K2, lds);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(&counter[1], 1);
-        if (done == (int)gridDim.x - 1) {
-            atomicExch(&counter[0], 0);
-            atomicExch(&counter[1], 0);
-        }
-    }
+    if (threadIdx.x == 0)
+        queue_finish(Q);
 }
 
 
@@ -1156,11 +1143,10 @@ static hipError_t launch_single_t(const DevBox &B, const StageCoef &K, int nitem
 }
 
 template <int TX, int NW, bool WRAP, int OPK>
-static hipError_t launch_batched_t(const DevBox *tab, int nbox, int nitems, int *counter, int grid,
+static hipError_t launch_batched_t(const DevBox *tab, int nbox, const ItemQueue &Q, int grid,
                                    const StageCoef &K, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tiles_batched<TX, NW, WRAP, OPK>), dim3(grid), dim3(NW * 64), 0, s, tab, nbox,
-                       nitems, counter, K);
+    hipLaunchKernelGGL((k_tiles_batched<TX, NW, WRAP, OPK>), dim3(grid), dim3(NW * 64), 0, s, tab, nbox, Q, K);
     return hipGetLastError();
 }
 
@@ -1197,13 +1183,13 @@ hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const St
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
-                                int *counter, int grid, const StageCoef &K, hipStream_t s, bool ghosted)
+hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, const ItemQueue &Q,
+                                int grid, const StageCoef &K, hipStream_t s, bool ghosted)
 {
     const bool wrap = wrap_of(op, ghosted);
 #define X(TX_, NW_, W_, O_)                                                                            \
     if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
-        return launch_batched_t<TX_, NW_, W_, O_>(tab, nbox, nitems, counter, grid, K, s);
+        return launch_batched_t<TX_, NW_, W_, O_>(tab, nbox, Q, grid, K, s);
     S4_FOR_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1236,12 +1222,12 @@ static hipError_t launch_rows_single_t(const DevBox &B, const StageCoef &K, int 
 }
 
 template <int WX, int RY, bool WRAP, int OPK>
-static hipError_t launch_rows_batched_t(const DevBox *tab, int nbox, int nitems, int *counter, int grid,
+static hipError_t launch_rows_batched_t(const DevBox *tab, int nbox, const ItemQueue &Q, int grid,
                                         const StageCoef &K, hipStream_t s)
 {
     constexpr int WY = 4 / WX;
     hipLaunchKernelGGL((k_rows_batched<WX, WY, RY, WRAP, OPK>), dim3(grid), dim3(WX * WY * 64), 0, s, tab, nbox,
-                       nitems, counter, K);
+                       Q, K);
     return hipGetLastError();
 }
 
@@ -1270,13 +1256,13 @@ hipError_t launch_rows_single(int op, int wx, int ry, const DevBox &B, const Sta
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, int nitems, int *counter,
+hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, const ItemQueue &Q,
                                int grid, const StageCoef &K, hipStream_t s, bool ghosted)
 {
     const bool wrap = wrap_of(op, ghosted);
 #define X(WX_, RY_, W_, O_)                                                                            \
     if (wx == WX_ && ry == RY_ && wrap == W_ && op == O_)                                              \
-        return launch_rows_batched_t<WX_, RY_, W_, O_>(tab, nbox, nitems, counter, grid, K, s);
+        return launch_rows_batched_t<WX_, RY_, W_, O_>(tab, nbox, Q, grid, K, s);
     S4_ROW_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1339,7 +1325,7 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 
 
 #define S4_PAIR2_SHAPES(X)                                                                             \
-    X(64, 4) X(64, 8) X(32, 4) X(32, 8)
+    X(64, 4) X(64, 8) X(32, 4) X(32, 8) X(16, 4) X(16, 8)
 
 hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
                         int nitems, int nxcd, hipStream_t s, bool ghosted)
@@ -1361,23 +1347,23 @@ hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCo
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, int nitems, int *counter,
+hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, const ItemQueue &Q,
                                 int grid, const StageCoef &K1, const StageCoef &K2, hipStream_t s, bool ghosted)
 {
 #define X(TX_, NW_)                                                                                    \
     if (tx == TX_ && nw == NW_) {                                                                      \
         if (pair == 0 && !ghosted)                                                                     \
             hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 0, true>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
-                               nitems, counter, K1, K2);                                               \
+                               Q, K1, K2);                                               \
         else if (pair == 0)                                                                            \
             hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 0, false>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
-                               nitems, counter, K1, K2);                                               \
+                               Q, K1, K2);                                               \
         else if (!ghosted)                                                                             \
             hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 1, true>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
-                               nitems, counter, K1, K2);                                               \
+                               Q, K1, K2);                                               \
         else                                                                                           \
             hipLaunchKernelGGL((k_pair2_batched<TX_, NW_, 1, false>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, \
-                               nitems, counter, K1, K2);                                               \
+                               Q, K1, K2);                                               \
         return hipGetLastError();                                                                      \
     }
     S4_PAIR2_SHAPES(X)

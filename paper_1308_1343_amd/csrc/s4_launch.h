@@ -14,10 +14,10 @@ hipError_t launch_tiles_single(int op, int tx, int nw, const DevBox &B, const St
                                int nxcd, hipStream_t s, bool ghosted = false);
 
 // All boxes of a device table in one persistent launch of `grid` workgroups
-// over a shared item counter (counter[0..1] must be zero before the first
-// launch; each launch leaves them zero).
-hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, int nitems,
-                                int *counter, int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
+// over the per-XCD work queue Q (its 1 + Q.nq counters must be zero before
+// the first launch; each launch leaves them zero).
+hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int nbox, const ItemQueue &Q,
+                                int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
 
 // Resident workgroups per CU of the batched kernel for this shape (0 if unknown).
 int max_blocks_per_cu(int op, int tx, int nw, bool ghosted = false);
@@ -26,7 +26,7 @@ int max_blocks_per_cu(int op, int tx, int nw, bool ghosted = false);
 // each) for OP_RHS and OP_STAGE, single box and persistent batched forms.
 hipError_t launch_rows_single(int op, int wx, int ry, const DevBox &B, const StageCoef &K, int nitems, int nxcd,
                               hipStream_t s, bool ghosted = false);
-hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, int nitems, int *counter,
+hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nbox, const ItemQueue &Q,
                                int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
 int max_blocks_rows(int op, int wx, int ry, bool ghosted = false);
 
@@ -44,8 +44,8 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 // periodic addressing, or ghost addressing when ghosted.
 hipError_t launch_pair2(int pair, int tx, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
                         int nitems, int nxcd, hipStream_t s, bool ghosted = false);
-// persistent form over a table of boxes (counter as launch_tiles_batched)
-hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, int nitems, int *counter,
+// persistent form over a table of boxes (queue as launch_tiles_batched)
+hipError_t launch_pair2_batched(int pair, int tx, int nw, const DevBox *tab, int nbox, const ItemQueue &Q,
                                 int grid, const StageCoef &K1, const StageCoef &K2, hipStream_t s,
                                 bool ghosted = false);
 int max_blocks_pair2(int pair, int tx, int nw, bool ghosted = false);

@@ -283,7 +283,7 @@ static void run_pair(int nx, int ny, int nz, int g, int padx, int tz_req)
         ItemPos Pe = P;
         Pe.x0 -= 2;
         Pe.y0 -= 2;
-        std::vector<Walker<TXE, NW, true>> W;
+        std::vector<Walker<TXE, NW, true, false>> W;
         for (int t = 0; t < T::NT; ++t)
             W.emplace_back(B, Pe, t);
         std::vector<int64_t> qa(T::NT * 5, -1), qb(T::NT * 5, -1);
@@ -567,8 +567,57 @@ static void shapes()
     }
 }
 
+// The per-XCD work queue of the batched kernels, with the workgroups'
+// calls interleaved at random: every item is handed out exactly once, every
+// workgroup stops within nitems + nq calls, and a workgroup's first item
+// comes from its own range while that range lasts.
+static void queue_check(int nitems, int nq, int grid, unsigned seed)
+{
+    std::vector<int> cnt(1 + nq, 0), got(nitems, 0);
+    const ItemQueue Q{cnt.data(), nitems, nq};
+    std::vector<int> q(grid), left(grid, nq), calls(grid, 0), first(grid, -1);
+    std::vector<char> done(grid, 0);
+    for (int b = 0; b < grid; ++b)
+        q[b] = b % nq;
+    int running = grid;
+    unsigned x = seed;
+    auto add = [](int *p) { return (*p)++; };
+    while (running > 0) {
+        x = x * 1103515245u + 12345u;
+        int b = (int)((x >> 8) % (unsigned)grid);
+        while (done[b])
+            b = (b + 1) % grid;
+        const int start_q = q[b];
+        const int lo = queue_lo(start_q, nitems, nq), hi = queue_lo(start_q + 1, nitems, nq);
+        const bool own_left = cnt[1 + start_q] < hi - lo;
+        const int it = queue_next(Q, q[b], left[b], add);
+        ++calls[b];
+        CHECK(calls[b] <= nitems + nq + 1, "queue: workgroup %d does not stop", b);
+        if (it >= nitems) {
+            done[b] = 1;
+            --running;
+            continue;
+        }
+        CHECK(it >= 0, "queue: negative item");
+        if (it >= 0) {
+            got[it]++;
+            if (first[b] < 0) {
+                first[b] = it;
+                if (own_left)
+                    CHECK(it >= lo && it < hi, "queue: first item %d of workgroup %d not in its range", it, b);
+            }
+        }
+    }
+    for (int i = 0; i < nitems; ++i)
+        CHECK(got[i] == 1, "queue: item %d handed out %d times", i, got[i]);
+}
+
 int main()
 {
+    const int QS[][3] = {{1000, 8, 64}, {7, 8, 3}, {0, 8, 4}, {1, 8, 16}, {5000, 8, 1}, {123, 1, 9}, {97, 15, 40}};
+    for (auto &s : QS)
+        for (unsigned seed = 1; seed <= 3; ++seed)
+            queue_check(s[0], s[1], s[2], seed);
     const int G[][4] = {{32, 32, 32, 2}, {5, 7, 6, 3}, {70, 9, 5, 3}, {2, 2, 2, 2}, {3, 17, 4, 3}, {1, 1, 1, 2}};
     for (auto &s : G)
         ghost_shell(s[0], s[1], s[2], s[3]);
