@@ -64,7 +64,8 @@ def kernel_source_hash():
 def kernel_set(ch):
     """Name of the kernel set behind a tile choice (s4_get_choice's kernel op)."""
     k = ch["kernel_op"]
-    return "stage pairs" if k == 100 else "stage pairs per tap" if k == 101 else "rows" if k >= 200 else "tiles"
+    return ("stage pairs" if k == 100 else "stage pairs per tap" if k == 101 else "whole steps" if k == 102
+            else "rows" if k >= 200 else "tiles")
 
 
 def traffic_from_profile(kernel_key, tile):
@@ -152,20 +153,24 @@ def main():
     value = npts * K / wall / 1e9
     # dominant kernel: the only kernel in the timed region.  Per-stage kernel set:
     # 4 launches per step moving 4, 8, 10, 6 accesses per point; fused stage
-    # pairs: 2 launches per step moving 6 (stages 1-2) and 8 (stages 3-4).
-    fused = choice["kernel_op"] in (100, 101)
-    launch_bytes = [6, 8] if fused else [4, 8, 10, 6]  # 8-byte accesses per point and launch
+    # pairs: 2 launches per step moving 6 (stages 1-2) and 8 (stages 3-4);
+    # whole steps: 1 launch reading u_n, rho_n and writing u_{n+1}, rho_{n+1}.
+    kop = choice["kernel_op"]
+    launch_bytes = [4] if kop == 102 else [6, 8] if kop in (100, 101) else [4, 8, 10, 6]  # 8-byte accesses
     nlaunch = len(launch_bytes)
     bytes_per_launch = npts * 8 * sum(launch_bytes) / nlaunch
     launch_s = ev_ms / 1e3 / (nlaunch * K)
     achieved = bytes_per_launch / launch_s / 1e9
-    if choice["kernel_op"] == 100:
+    if kop == 102:
+        kname = f"k_rk4_step4<{choice['tile_x']},{choice['threads'] // 64}>"
+        tkey = "step4_wave256"
+    elif kop == 100:
         kname = f"k_rk4_pair<{choice['tile_x']},{choice['threads'] // 64},pair 0|1>"
         tkey = "pair_wave256"
-    elif choice["kernel_op"] == 101:
+    elif kop == 101:
         kname = f"k_pair2<{choice['tile_x']},{choice['threads'] // 64},pair 0|1>"
         tkey = "pair2_wave256"
-    elif choice["kernel_op"] >= 200:
+    elif kop >= 200:
         wx = choice["tile_x"] // 64
         kname = f"k_rows_single<{wx},{4 // wx},{choice['tile_y'] // (4 // wx)},periodic,stage 1..4>"
         tkey = "rows_stage_wave256"

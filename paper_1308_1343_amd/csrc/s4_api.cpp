@@ -90,8 +90,10 @@ static int hip_fail(hipError_t e, const char *where)
 // stages -- variant 1 recomputes the first stage on a widened workgroup tile
 // tx x (nw*64/tx) with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms
 // the second stage's stencil input at each tap on the plain tile
-// tx x (nw*64/tx) (any number of boxes, levels included).  tz
-// is the z chunk (0 = whole box).  The list is ordered so that the
+// tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (one
+// box) runs a whole RK4 step per pass on the widened tile of variant 1,
+// stages 1-2 on all lanes and 3-4 on the output tile.  tz is the z chunk
+// (0 = whole box; for variant 4, equal shares of the tile-plane sequence).  The list is ordered so that the
 // candidates any op may use form a prefix of it.
 struct Cand {
     int tx, nw, tz;
@@ -117,6 +119,9 @@ static const std::vector<Cand> &cands()
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 1, 0});
+        for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}, {64, 8}})
+            for (int tz : {0, 128, 64, 32})
+                c.push_back({tn.first, tn.second, tz, 4, 0});
         return c;
     }();
     return v;
@@ -140,7 +145,7 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
         return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
     if (c.variant == 3)
         return op == S4_OP_RK4;
-    return op == S4_OP_RK4 && nbox == 1; // variant 1
+    return op == S4_OP_RK4 && nbox == 1; // variants 1 and 4
 }
 
 static int kernel_op(int op)
@@ -174,7 +179,7 @@ struct GraphEntry {
 static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : tx == 64 ? 2 : tx == 128 ? 3 : 4; }
 static int ord_ry(int ry) { return ry == 4 ? 1 : 0; }
 static int ord_nw(int nw) { return nw == 4 ? 0 : nw == 8 ? 1 : 2; }
-static int ord_tz(int tz) { return tz == 8 ? 0 : tz == 16 ? 1 : tz == 32 ? 2 : tz == 64 ? 3 : 4; }
+static int ord_tz(int tz) { return tz == 8 ? 0 : tz == 16 ? 1 : tz == 32 ? 2 : tz == 64 ? 3 : tz == 128 ? 4 : 5; }
 
 struct Hill {
     std::vector<int> allowed;     // candidates this setup may use
@@ -302,12 +307,12 @@ static int tile_ty(const Cand &c)
 // output tile extents in x and y
 static int out_tx(const Cand &c)
 {
-    return c.variant == 1 ? c.tx - 4 : c.tx;
+    return c.variant == 1 || c.variant == 4 ? c.tx - 4 : c.tx;
 }
 
 static int out_ty(const Cand &c)
 {
-    return c.variant == 1 ? tile_ty(c) - 4 : tile_ty(c);
+    return c.variant == 1 || c.variant == 4 ? tile_ty(c) - 4 : tile_ty(c);
 }
 
 static int64_t items_of(const s4_box &b, const Cand &c)
@@ -373,7 +378,7 @@ std::vector<int> Hill::neighbours(int c) const
                std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry));
     };
     std::vector<int> out;
-    int nearest[4] = {1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
+    int nearest[5] = {1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
     for (int d : allowed)
         if (cands()[d].variant != a.variant)
             nearest[cands()[d].variant] = std::min(nearest[cands()[d].variant], dist(cands()[d]));
@@ -938,8 +943,13 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
         return r;
     const Choice ch = choose(ctx, op, b, nbox, true);
     const Cand &c = cands()[ch.cand];
-    // 100, 101: RK4 stage pairs (widened tile, per-tap); 200 + op: the op's kernels on the row-register traversal
-    out[0] = c.variant == 1 ? 100 : c.variant == 3 ? 101 : c.variant == 2 ? 200 + kernel_op(op) : kernel_op(op);
+    // 100, 101: RK4 stage pairs (widened tile, per-tap); 102: whole RK4 steps;
+    // 200 + op: the op's kernels on the row-register traversal
+    out[0] = c.variant == 1   ? 100
+             : c.variant == 3 ? 101
+             : c.variant == 4 ? 102
+             : c.variant == 2 ? 200 + kernel_op(op)
+                              : kernel_op(op);
     out[1] = c.tx;
     out[2] = tile_ty(c);
     out[3] = c.tz;
@@ -1214,11 +1224,12 @@ static int rk4_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab, 
     return S4_OK;
 }
 
-// Fused stage-pair RK4 on one box.  One step is two launches: pair 0 reads
-// y_n = (ui, ri) and writes y_3 (U3, R3) and the running sum (AU, AR); pair 1
-// reads them and writes y_{n+1} to (uo, ro).  Steps alternate between the
-// caller's state and a ping-pong copy in the workspace, so an even number
-// of steps ends in the caller's buffers.
+// Fused RK4 on one box.  With stage pairs one step is two launches: pair 0
+// reads y_n = (ui, ri) and writes y_3 (U3, R3) and the running sum (AU, AR);
+// pair 1 reads them and writes y_{n+1} to (uo, ro).  A whole-step kernel
+// (variant 4) reads y_n and writes y_{n+1} in one launch.  Steps alternate
+// between the caller's state and a ping-pong copy in the workspace, so an
+// even number of steps ends in the caller's buffers.
 struct PairFields {
     double *U3, *R3, *Up, *Rp, *AU, *AR;
 };
@@ -1228,6 +1239,23 @@ static PairFields pair_fields(const s4_box &b, char *ws)
     const size_t fb = field_bytes(b);
     auto F = [&](int k) { return ws_field(ws + k * fb, b); };
     return {F(0), F(2), F(1), F(3), F(4), F(5)};
+}
+
+// Planes per workgroup of the whole-step kernel.  tz > 0: 0, one workgroup
+// per (tile, z chunk) item.  tz = 0 (balanced): the box's tile-plane
+// sequence shared equally by one round of resident workgroups, but no fewer
+// than 16 planes per run (each run pays a 4-plane start-up at either end of
+// its z range).
+static int step4_run(const s4_ctx *ctx, const Cand &c, const DevBox &D)
+{
+    if (c.tz > 0)
+        return 0;
+    const int64_t total = (int64_t)D.tiles[0] * D.tiles[1] * D.n[2];
+    int per = max_blocks_step4(c.tx, c.nw);
+    if (per <= 0)
+        per = 1;
+    const int64_t wgs = (int64_t)per * ctx->ncu;
+    return (int)std::max<int64_t>(16, (total + wgs - 1) / wgs);
 }
 
 static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *ui, const double *ri,
@@ -1243,6 +1271,13 @@ static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const doub
     A.q[1] = W.R3;
     A.q[2] = W.AU;
     A.q[3] = W.AR;
+    if (c.variant == 4) {
+        A.q[0] = uo;
+        A.q[1] = ro;
+        const StageCoef K[4] = {rk4_coef(0, dt), rk4_coef(1, dt), rk4_coef(2, dt), rk4_coef(3, dt)};
+        hipError_t e = launch_rk4_step4(c.tx, c.nw, A, K, step4_run(ctx, c, A), ctx->nxcd, s);
+        return e == hipSuccess ? S4_OK : hip_fail(e, "whole-step launch");
+    }
     hipError_t e = c.variant == 3
                        ? launch_pair2(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s)
                        : launch_rk4_pair(0, c.tx, c.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), items, ctx->nxcd, s);
@@ -1437,7 +1472,7 @@ int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const doubl
     const Choice ch = choose(ctx, S4_OP_RK4, b, 1);
     OnlineTimer tm(ctx, ch, s);
     const Cand &c = cands()[ch.cand];
-    if (c.variant == 1 || c.variant == 3) {
+    if (c.variant == 1 || c.variant == 3 || c.variant == 4) {
         r = rk4_pair_step(ctx, c, b[0], u_in, rho_in, u_out, rho_out, c2, pair_fields(b[0], (char *)workspace), dt,
                           s);
     } else {
@@ -1459,8 +1494,8 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
 {
     int r;
     char *ws = (char *)workspace;
-    if (cands()[ch.cand].variant == 1 && nbox == 1) {
-        // fused stage pairs: pairs of steps, an odd last step with the stage kernels
+    if ((cands()[ch.cand].variant == 1 || cands()[ch.cand].variant == 4) && nbox == 1) {
+        // widened-tile stage pairs or whole steps: pairs of steps, an odd last step with the stage kernels
         const Cand &cp = cands()[ch.cand];
         const PairFields W = pair_fields(b[0], ws);
         const double *c2b = c2 ? c2[0] : nullptr;
@@ -2039,7 +2074,7 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
         return r;
     hipStream_t s = (hipStream_t)stream;
     int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
-    if (cands()[ci].variant == 1) // the widened-tile pairs wrap around one box
+    if (cands()[ci].variant == 1 || cands()[ci].variant == 4) // widened tiles wrap around one box
         ci = heuristic(ctx, S4_OP_RK4, b, nbox);
     if (cands()[ci].variant != 3)
         return level_stage_run(ctx, L, ci, u, rho, c2, dt, nsteps, mode, workspace, s);
@@ -2160,7 +2195,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             case S4_OP_RK4:
                 if (c.variant == 3) // one stage-pair step, alternating between (u, rho) and the ping-pong copy
                     return pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, set & 1, s, nullptr);
-                if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
+                if (c.variant == 1 || c.variant == 4) // one step: (u, rho) -> ping-pong buffers, alternating
                     return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
                                          set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
                                          s);

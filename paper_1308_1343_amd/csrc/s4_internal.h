@@ -132,6 +132,26 @@ S4_HD inline ItemPos item_pos(const DevBox &B, int local, int tx_extent, int ty_
     return P;
 }
 
+// Balanced work of the whole-step kernel: the box's xy tiles times its nz
+// planes form one sequence (tile after tile, planes inside a tile), cut into
+// runs of `run` planes, one run per workgroup, so every workgroup of a
+// single-round launch gets the same work.  A run may end in one tile and go
+// on in the next: run_piece gives the pieces of the run [s, e) one at a time
+// (advancing s), each one tile and a z range; false once the run is done.
+S4_HD inline bool run_piece(const DevBox &B, int txo, int tyo, int64_t &s, int64_t e, ItemPos &P)
+{
+    if (s >= e)
+        return false;
+    const int nz = B.n[2];
+    const int t = (int)(s / nz);
+    P.x0 = (t % B.tiles[0]) * txo;
+    P.y0 = (t / B.tiles[0]) * tyo;
+    P.z0 = (int)(s % nz);
+    P.z1 = (int)(e - s < (int64_t)(nz - P.z0) ? P.z0 + (e - s) : nz);
+    s += P.z1 - P.z0;
+    return true;
+}
+
 // halo slot h of a tile: LDS (row, col) and the tile-relative point (dx, dy)
 template <int TX, int NW>
 S4_HD inline void halo_slot(int h, int &lrow, int &lcol, int &dx, int &dy)

@@ -587,6 +587,181 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
 
 
 // ---------------------------------------------------------------------------
+// One whole RK4 step in one pass: the stage pairs carried one level further.
+// Stage 3's stencil input u_3 = u_n + dt/2 rho_2 depends on k_1 = c^2 L u_n
+// at the point, and stage 4's u_4 = u_n + dt rho_3 on k_2 = c^2 L u_2, so a
+// step reaches radius 4 on u_n and rho_n.  A workgroup of TXE x TYE lanes
+// covers an output tile widened by 2 on each side (the traversal of
+// k_rk4_pair):
+//   phase A, every lane, plane p1: L u_n and L u_2 (u_2 = u_n + dt/2 rho_n
+//     formed at every tap), then the pointwise rho_2, u_3, rho_3, u_4 and
+//     the running sums acc_u (through stage 3) and acc_rho (through stage
+//     2); u_3 and u_4 go to the LDS ring and the column's register queues;
+//   phase B, the inner (TXE-4) x (TYE-4) lanes, plane p1 - 2: L u_3 and
+//     L u_4, rho_4 = rho_n + dt k_3, acc_rho += dt/3 k_3, and
+//     y_{n+1} = acc + dt/6 k_4.
+// Every intermediate is the fma the per-stage kernels store, so results are
+// bit for bit theirs.  Per output point the pass reads u_n, rho_n and c^2
+// and writes u_{n+1}, rho_{n+1}, to other buffers than u_n and rho_n, which
+// neighbouring tiles still read.
+
+template <int TXE, int NW>
+struct Step4Lds {
+    static constexpr int P1 = Tile<TXE, NW>::LY * Tile<TXE, NW>::LX; // u_n and u_2 with halo
+    static constexpr int P2 = TXE * Tile<TXE, NW>::TY;                // u_3 and u_4
+    static constexpr int SIZE = 4 * 2 * P1 + 3 * 2 * P2;              // doubles
+};
+
+// stage coefficients of a whole step: a_1, a_2, b_2, a_3, b_3, b_4 of StageCoef
+struct Step4Coef {
+    double a1, a2, b2, a3, b3, b4;
+};
+
+// one tile and z range of a whole step
+template <int TXE, int NW, bool HASC2>
+__device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, const Step4Coef &K, double *lds)
+{
+    using T = Tile<TXE, NW>;
+    using S = Step4Lds<TXE, NW>;
+    constexpr int TYE = T::TY;
+    constexpr int P1 = S::P1, P2 = S::P2;
+    double *const ring1 = lds;              // 4 slots of [u_n | u_2]
+    double *const ring2 = lds + 4 * 2 * P1; // 3 slots of [u_3 | u_4]
+    ItemPos Pe = P;
+    Pe.x0 -= 2;
+    Pe.y0 -= 2;
+    const Walker<TXE, NW, true, false> w(B, Pe, threadIdx.x);
+    const int lx = threadIdx.x % TXE, ly = threadIdx.x / TXE;
+    const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < B.n[0] && w.j < B.n[1];
+    const int l2 = ly * TXE + lx;
+    const double *__restrict__ uf = B.in;
+    const double *__restrict__ rf = B.p[0];
+    const double *c2 = HASC2 ? B.p[5] : nullptr;
+    const double a1 = K.a1, a2 = K.a2, b2 = K.b2, a3 = K.a3, b3 = K.b3, b4 = K.b4;
+
+    // column queues: planes f-4 .. f of u_n, u_2, rho_n, c^2; planes
+    // f-6 .. f-2 of u_3, u_4; phase A's running sums delayed to phase B
+    double qa0 = 0, qa1 = 0, qa2 = 0, qa3 = 0, qa4 = 0;
+    double qv0 = 0, qv1 = 0, qv2 = 0, qv3 = 0, qv4 = 0;
+    double qr0 = 0, qr1 = 0, qr2 = 0, qr3 = 0, qr4 = 0;
+    double qc0 = 1, qc1 = 1, qc2 = 1, qc3 = 1, qc4 = 1;
+    double qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, qb4 = 0;
+    double qd0 = 0, qd1 = 0, qd2 = 0, qd3 = 0, qd4 = 0;
+    double du0 = 0, du1 = 0, du2 = 0; // acc_u after stage 3
+    double dr0 = 0, dr1 = 0, dr2 = 0; // acc_rho after stage 2
+
+    // plane f of the column (u_n, rho_n, c^2) and of the halo (u_n, rho_n), one plane ahead
+    double nu, nr, nc = 1.0, hu[T::HS], hr[T::HS];
+    auto fetch = [&](int f) {
+        const int64_t zo = w.zoff(f);
+        nu = uf[w.col + zo];
+        nr = rf[w.col + zo];
+        if (HASC2)
+            nc = ldp(c2 + w.col + zo);
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0) {
+                hu[s] = uf[w.hcol[s] + zo];
+                hr[s] = rf[w.hcol[s] + zo];
+            }
+    };
+    fetch(P.z0 - 4);
+    for (int f = P.z0 - 4; f <= P.z1 + 3; ++f) {
+        qa0 = qa1; qa1 = qa2; qa2 = qa3; qa3 = qa4; qa4 = nu;
+        qr0 = qr1; qr1 = qr2; qr2 = qr3; qr3 = qr4; qr4 = nr;
+        qv0 = qv1; qv1 = qv2; qv2 = qv3; qv3 = qv4; qv4 = fma(a1, nr, nu);
+        if (HASC2) {
+            qc0 = qc1; qc1 = qc2; qc2 = qc3; qc3 = qc4; qc4 = nc;
+        }
+        double *R1 = ring1 + (f & 3) * 2 * P1;
+        R1[w.lc] = qa4;
+        R1[P1 + w.lc] = qv4;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0) {
+                R1[w.hl[s]] = hu[s];
+                R1[P1 + w.hl[s]] = fma(a1, hr[s], hu[s]);
+            }
+        __syncthreads();
+        if (f + 1 <= P.z1 + 3)
+            fetch(f + 1);
+        const int p1 = f - 2;
+        if (p1 >= P.z0 - 2) {
+            // phase A (stages 1 and 2) at plane p1, every lane
+            const double *L = ring1 + (p1 & 3) * 2 * P1;
+            const double *V = L + P1;
+            const int lc = w.lc;
+            const double la = lap4(B, qa2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
+                                   L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa0, qa1, qa3, qa4);
+            const double lv = lap4(B, qv2, V[lc - 2], V[lc - 1], V[lc + 1], V[lc + 2], V[lc - 2 * T::LX],
+                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], qv0, qv1, qv3, qv4);
+            const double kr1 = HASC2 ? qc2 * la : la;
+            const double kr2 = HASC2 ? qc2 * lv : lv;
+            const double un = qa2, rn = qr2, u2 = qv2;
+            const double r2 = fma(a1, kr1, rn);
+            const double u3 = fma(a2, r2, un);
+            const double r3 = fma(a2, kr2, rn);
+            const double u4 = fma(a3, r3, un);
+            du0 = fma(b3, r3, fma(b2, r2, fma(1.0 / 3.0, u2 - un, un)));
+            dr0 = fma(b2, kr2, fma(1.0 / 3.0, r2 - rn, rn));
+            double *R2 = ring2 + mod3(p1) * 2 * P2;
+            R2[l2] = u3;
+            R2[P2 + l2] = u4;
+            qb0 = qb1; qb1 = qb2; qb2 = qb3; qb3 = qb4; qb4 = u3;
+            qd0 = qd1; qd1 = qd2; qd2 = qd3; qd3 = qd4; qd4 = u4;
+        }
+        const int p2 = f - 4;
+        if (out && p2 >= P.z0 && p2 < P.z1) {
+            // phase B (stages 3 and 4) at plane p2, the output tile
+            const double *L = ring2 + mod3(p2) * 2 * P2;
+            const double *V = L + P2;
+            const double l3 = lap4(B, qb2, L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
+                                   L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb0, qb1, qb3, qb4);
+            const double l4 = lap4(B, qd2, V[l2 - 2], V[l2 - 1], V[l2 + 1], V[l2 + 2], V[l2 - 2 * TXE],
+                                   V[l2 - TXE], V[l2 + TXE], V[l2 + 2 * TXE], qd0, qd1, qd3, qd4);
+            const double kr3 = HASC2 ? qc0 * l3 : l3;
+            const double kr4 = HASC2 ? qc0 * l4 : l4;
+            const double r4 = fma(a3, kr3, qr0);
+            const int64_t c = w.point(B, p2);
+            st(B.q[0] + c, fma(b4, r4, du2));
+            st(B.q[1] + c, fma(b4, kr4, fma(b3, kr3, dr2)));
+        }
+        if (p1 >= P.z0 - 2) {
+            du2 = du1;
+            du1 = du0;
+            dr2 = dr1;
+            dr1 = dr0;
+        }
+    }
+}
+
+// Workgroup g (placed so that each XCD holds a contiguous range of g) runs
+// work item g -- tiles in order within z chunks of B.tz planes, so that the
+// workgroups of one XCD march a compact patch of tiles through the same
+// planes and share their halo lines in its L2 -- or, with run > 0, planes
+// [g * run, (g + 1) * run) of the box's tile-plane sequence.
+template <int TXE, int NW, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
+{
+    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    constexpr int TYE = Tile<TXE, NW>::TY;
+    const int g = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    if (run == 0) {
+        run_step4<TXE, NW, HASC2>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
+        return;
+    }
+    const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
+    int64_t s = (int64_t)g * run;
+    const int64_t e = s + run < total ? s + run : total;
+    ItemPos P;
+    while (run_piece(B, TXE - 4, TYE - 4, s, e, P)) {
+        run_step4<TXE, NW, HASC2>(B, P, K, lds);
+        __syncthreads(); // the next piece rewrites the LDS rings
+    }
+}
+
+
+// ---------------------------------------------------------------------------
 // Two RK4 stages in one pass without a widened tile.  In the first-order
 // wave equation the next stage's u is pointwise in the current state
 // (u_{s+1} = u_n + a_s rho_s), so the second stage's stencil input at each
@@ -1321,6 +1496,42 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 #undef X
 #undef Y
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
+                            hipStream_t s)
+{
+    const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
+    if (run < 0 || total <= 0)
+        return hipErrorInvalidValue;
+    const int64_t grid = run == 0 ? (int64_t)B.tiles[0] * B.tiles[1] * B.tiles[2] : (total + run - 1) / run;
+    const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};
+#define Y(TXE_, NW_, C_)                                                                               \
+    hipLaunchKernelGGL((k_rk4_step4<TXE_, NW_, C_>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, B, C, run, nxcd)
+#define X(TXE_, NW_)                                                                                   \
+    if (txe == TXE_ && nw == NW_) {                                                                    \
+        if (B.p[5] != nullptr)                                                                         \
+            Y(TXE_, NW_, true);                                                                        \
+        else                                                                                           \
+            Y(TXE_, NW_, false);                                                                       \
+        return hipGetLastError();                                                                      \
+    }
+    X(32, 8) X(64, 8) X(64, 16) X(32, 16)
+#undef X
+#undef Y
+    return hipErrorInvalidValue;
+}
+
+int max_blocks_step4(int txe, int nw)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define X(TXE_, NW_)                                                                                   \
+    if (txe == TXE_ && nw == NW_)                                                                      \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_step4<TXE_, NW_, true>, NW_ * 64, 0);
+    X(32, 8) X(64, 8) X(64, 16) X(32, 16)
+#undef X
+    return e == hipSuccess ? nb : 0;
 }
 
 

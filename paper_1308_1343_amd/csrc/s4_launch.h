@@ -39,6 +39,18 @@ hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, 
 hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const StageCoef &K1, const StageCoef &K2,
                            int nitems, int nxcd, hipStream_t s);
 
+// One whole RK4 step on box B in one pass (periodic addressing): workgroups
+// of txe x (nw*64/txe) lanes, output tiles of (txe-4) x (tye-4) (B.tiles[0..1]
+// counts them).  run = 0: one workgroup per work item (tile, z chunk of
+// B.tz planes); run > 0: each workgroup runs `run` planes of the box's
+// tile-plane sequence (run_piece).  B.in, p[0], p[5]: u_n, rho_n, c^2 (optional); q[0],
+// q[1]: u_{n+1}, rho_{n+1}, which must not alias the inputs.  K: the
+// coefficients of stages 1..4.
+hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
+                            hipStream_t s);
+// resident workgroups per CU of the whole-step kernel (0 if unknown)
+int max_blocks_step4(int txe, int nw);
+
 // Two RK4 stages per pass on the plain tile (pair 0: stages 1-2, pair 1:
 // stages 3-4), workgroups of tx x (nw*64/tx) lanes, one output point each;
 // periodic addressing, or ghost addressing when ghosted.

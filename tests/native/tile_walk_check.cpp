@@ -612,8 +612,47 @@ static void queue_check(int nitems, int nq, int grid, unsigned seed)
         CHECK(got[i] == 1, "queue: item %d handed out %d times", i, got[i]);
 }
 
+// The whole-step kernel's balanced runs: over every workgroup the pieces
+// cover each (tile, plane) of the box exactly once, each piece lies in one
+// tile and is a non-empty z range inside the box.
+static void runs_check(int nx, int ny, int nz, int txo, int tyo, int run)
+{
+    DevBox B{};
+    B.n[0] = nx;
+    B.n[1] = ny;
+    B.n[2] = nz;
+    B.tiles[0] = (nx + txo - 1) / txo;
+    B.tiles[1] = (ny + tyo - 1) / tyo;
+    const int ntile = B.tiles[0] * B.tiles[1];
+    const int64_t total = (int64_t)ntile * nz;
+    const int64_t grid = (total + run - 1) / run;
+    std::vector<int> seen(total, 0);
+    for (int64_t g = 0; g < grid; ++g) {
+        int64_t s = g * run;
+        const int64_t e = s + run < total ? s + run : total;
+        ItemPos P;
+        int pieces = 0;
+        while (run_piece(B, txo, tyo, s, e, P)) {
+            ++pieces;
+            CHECK(P.z0 >= 0 && P.z0 < P.z1 && P.z1 <= nz, "run piece z range [%d,%d)", P.z0, P.z1);
+            CHECK(P.x0 % txo == 0 && P.x0 < nx && P.y0 % tyo == 0 && P.y0 < ny, "run piece tile origin");
+            const int t = P.x0 / txo + (P.y0 / tyo) * B.tiles[0];
+            for (int k = P.z0; k < P.z1; ++k)
+                if (t >= 0 && t < ntile && k >= 0 && k < nz)
+                    seen[(int64_t)t * nz + k]++;
+            CHECK(pieces <= run / nz + 2, "run split into too many pieces");
+        }
+    }
+    for (int64_t i = 0; i < total; ++i)
+        CHECK(seen[i] == 1, "tile-plane %lld covered %d times", (long long)i, seen[i]);
+}
+
 int main()
 {
+    const int RS[][6] = {{256, 256, 256, 60, 12, 110}, {256, 256, 256, 28, 12, 64}, {5, 7, 3, 60, 12, 2},
+                         {70, 9, 5, 28, 28, 1},         {1, 1, 1, 60, 4, 16},       {97, 33, 41, 60, 4, 1000}};
+    for (auto &r : RS)
+        runs_check(r[0], r[1], r[2], r[3], r[4], r[5]);
     const int QS[][3] = {{1000, 8, 64}, {7, 8, 3}, {0, 8, 4}, {1, 8, 16}, {5000, 8, 1}, {123, 1, 9}, {97, 15, 40}};
     for (auto &s : QS)
         for (unsigned seed = 1; seed <= 3; ++seed)

@@ -8,15 +8,17 @@ import numpy as np
 import paper_1308_1343_amd as S
 
 # the library's candidate list, in its order (variant, tx, nw, tz, ry): one kernel per stage
-# on the tile traversal, on the row-register traversal, stage pairs per tap, widened stage pairs
+# on the tile traversal, on the row-register traversal, stage pairs per tap, widened stage pairs,
+# whole steps
 CANDS = [(0, tx, nw, tz, 0) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0, 64, 32, 16, 8)] + \
         [(2, tx, 4, tz, ry) for tx in (256, 128, 64) for ry in (4, 2) for tz in (64, 32, 16)] + \
         [(3, tx, nw, tz, 0) for tx, nw in ((64, 4), (64, 8), (32, 8), (32, 4), (16, 8), (16, 4))
          for tz in (64, 32, 16)] + \
-        [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
+        [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)] + \
+        [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8), (64, 8)) for tz in (0, 128, 64, 32)]
 ORD_TX = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}
 ORD_NW = {4: 0, 8: 1, 16: 2}
-ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 0: 4}
+ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 128: 4, 0: 5}
 ORD_RY = {0: 0, 2: 0, 4: 1}
 BOX = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
 
@@ -68,11 +70,18 @@ def test_restarts_escape_a_local_optimum():
 
 
 def test_excursions_are_cheap():
+    # An excursion starts with probability restart_prob per call and is
+    # abandoned at its first trial slower than 1.5x the best, so on average
+    # it costs about two calls at the worst setting's price: the steady
+    # overhead stays below 2 * restart_prob * (worst / best - 1), 8 % here.
     target = CANDS.index((1, 64, 16, 64, 0))
     cost = bowl(target, slope=0.3, other_variant=3.0)
-    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.02, seed=5, ncalls=4000)
-    steady = np.mean([cost[t] for t in tr[-2000:]])
-    assert steady <= 1.05 * cost[target]  # random restarts cost at most a few per cent
+    p = 0.02
+    bound = 1.0 + 2 * p * (max(cost) / cost[target] - 1.0)
+    for seed in (5, 6, 7):
+        tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=p, seed=seed, ncalls=4000)
+        steady = np.mean([cost[t] for t in tr[-2000:]])
+        assert steady <= bound * cost[target], (seed, steady)
 
 
 def test_noise_tolerance_and_determinism():
@@ -107,7 +116,7 @@ def test_moves_between_kernel_sets():
 def test_reaches_every_kernel_set():
     """From the per-stage start the neighbourhood reaches the best setting of
     whichever kernel set holds it, without random restarts."""
-    for best in ((3, 64, 4, 32, 0), (2, 256, 4, 32, 4), (1, 64, 16, 64, 0)):
+    for best in ((3, 64, 4, 32, 0), (2, 256, 4, 32, 4), (1, 64, 16, 64, 0), (4, 64, 16, 32, 0)):
         cost = [0.6 + 0.05 * dist(d, best) if d[0] == best[0] else 1.0 + 0.01 * dist(d, (0, 64, 8, 32, 0))
                 for d in CANDS]
         tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=300)
