@@ -34,6 +34,31 @@ __device__ __forceinline__ double lap4(const DevBox &B, double c, double xm2, do
     return r;
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also drains the
+// wave's global loads and stores before the barrier; a kernel whose
+// threads never read global memory written in the same launch needs only
+// its LDS writes visible, and its loads and stores in flight keep flying.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Non-temporal store of v at byte offset off of the nbytes at base (a
+// wave-uniform address), dropped by the hardware's buffer range check when
+// off >= nbytes.  Lanes with nothing to store pass such an offset: the
+// instruction still issues, so the number of memory operations that a later
+// wait counts does not depend on which lanes store.
+typedef unsigned int s4_u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned NO_STORE = 0x80000000u;
+
+__device__ __forceinline__ void st_or_drop(double *base, unsigned nbytes, unsigned off, double v)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)nbytes, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(s4_u32x2, v), r, off, 0, 2 /* nt */);
+}
+
 __device__ __forceinline__ void st(double *p, double v)
 {
     __builtin_nontemporal_store(v, p);
@@ -609,7 +634,7 @@ template <int TXE, int NW>
 struct Step4Lds {
     static constexpr int P1 = Tile<TXE, NW>::LY * Tile<TXE, NW>::LX; // u_n and u_2 with halo
     static constexpr int P2 = TXE * Tile<TXE, NW>::TY;                // u_3 and u_4
-    static constexpr int SIZE = 4 * 2 * P1 + 3 * 2 * P2;              // doubles
+    static constexpr int SIZE = 4 * 2 * P1 + 4 * 2 * P2;              // doubles
 };
 
 // stage coefficients of a whole step: a_1, a_2, b_2, a_3, b_3, b_4 of StageCoef
@@ -626,7 +651,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     constexpr int TYE = T::TY;
     constexpr int P1 = S::P1, P2 = S::P2;
     double *const ring1 = lds;              // 4 slots of [u_n | u_2]
-    double *const ring2 = lds + 4 * 2 * P1; // 3 slots of [u_3 | u_4]
+    double *const ring2 = lds + 4 * 2 * P1; // 4 slots of [u_3 | u_4]
     ItemPos Pe = P;
     Pe.x0 -= 2;
     Pe.y0 -= 2;
@@ -637,12 +662,15 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     const double *__restrict__ uf = B.in;
     const double *__restrict__ rf = B.p[0];
     const double *c2 = HASC2 ? B.p[5] : nullptr;
+    // bytes of one z plane of the outputs, the range of the buffer stores
+    // (below 2^31, checked at launch)
+    const unsigned plane_bytes = (unsigned)(B.sz * 8);
     const double a1 = K.a1, a2 = K.a2, b2 = K.b2, a3 = K.a3, b3 = K.b3, b4 = K.b4;
 
-    // column queues: planes f-4 .. f of u_n, u_2, rho_n, c^2; planes
-    // f-6 .. f-2 of u_3, u_4; phase A's running sums delayed to phase B
+    // column queues: planes f-4 .. f of u_n, rho_n, c^2 (u_2 at a plane is
+    // fma(a1, rho_n, u_n), formed where needed); planes f-6 .. f-2 of u_3,
+    // u_4; phase A's running sums delayed to phase B
     double qa0 = 0, qa1 = 0, qa2 = 0, qa3 = 0, qa4 = 0;
-    double qv0 = 0, qv1 = 0, qv2 = 0, qv3 = 0, qv4 = 0;
     double qr0 = 0, qr1 = 0, qr2 = 0, qr3 = 0, qr4 = 0;
     double qc0 = 1, qc1 = 1, qc2 = 1, qc3 = 1, qc4 = 1;
     double qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, qb4 = 0;
@@ -650,10 +678,18 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     double du0 = 0, du1 = 0, du2 = 0; // acc_u after stage 3
     double dr0 = 0, dr1 = 0, dr2 = 0; // acc_rho after stage 2
 
-    // plane f of the column (u_n, rho_n, c^2) and of the halo (u_n, rho_n), one plane ahead
+    // Plane step t = 0 .. nt-1 takes plane f = z0 - 4 + t into ring 1 (slot
+    // t mod 4), computes phase A at f - 2 from the plane taken at step t - 2
+    // (from t = 4 on) into ring 2 (slot t mod 4), and phase B at f - 4 from
+    // the ring-2 plane written at step t - 2 (for t - 8 in [0, tz)).  The
+    // plane fetched next is tracked as a wrapped index (no division per
+    // plane).
+    const int nt = P.z1 - P.z0 + 8, tz = P.z1 - P.z0;
+    const int nz = B.n[2];
+    int kz = readable(P.z0 - 4, nz, true, false); // wrapped index of the plane fetched next
     double nu, nr, nc = 1.0, hu[T::HS], hr[T::HS];
-    auto fetch = [&](int f) {
-        const int64_t zo = w.zoff(f);
+    auto fetch = [&]() {
+        const int64_t zo = (int64_t)(kz + w.g) * w.sz;
         nu = uf[w.col + zo];
         nr = rf[w.col + zo];
         if (HASC2)
@@ -664,56 +700,60 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
                 hu[s] = uf[w.hcol[s] + zo];
                 hr[s] = rf[w.hcol[s] + zo];
             }
+        kz = kz + 1 == nz ? 0 : kz + 1;
     };
-    fetch(P.z0 - 4);
-    for (int f = P.z0 - 4; f <= P.z1 + 3; ++f) {
+    fetch();
+    for (int t = 0; t < nt; ++t) {
+        const int k = t & 3;
         qa0 = qa1; qa1 = qa2; qa2 = qa3; qa3 = qa4; qa4 = nu;
         qr0 = qr1; qr1 = qr2; qr2 = qr3; qr3 = qr4; qr4 = nr;
-        qv0 = qv1; qv1 = qv2; qv2 = qv3; qv3 = qv4; qv4 = fma(a1, nr, nu);
         if (HASC2) {
             qc0 = qc1; qc1 = qc2; qc2 = qc3; qc3 = qc4; qc4 = nc;
         }
-        double *R1 = ring1 + (f & 3) * 2 * P1;
+        double *R1 = ring1 + (k & 3) * 2 * P1;
         R1[w.lc] = qa4;
-        R1[P1 + w.lc] = qv4;
+        R1[P1 + w.lc] = fma(a1, nr, nu);
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0) {
                 R1[w.hl[s]] = hu[s];
                 R1[P1 + w.hl[s]] = fma(a1, hr[s], hu[s]);
             }
-        __syncthreads();
-        if (f + 1 <= P.z1 + 3)
-            fetch(f + 1);
-        const int p1 = f - 2;
-        if (p1 >= P.z0 - 2) {
-            // phase A (stages 1 and 2) at plane p1, every lane
-            const double *L = ring1 + (p1 & 3) * 2 * P1;
+        // the next plane's loads fly across the barrier (their registers
+        // were consumed just above), as do the stores of the last plane
+        if (t + 1 < nt)
+            fetch();
+        lds_barrier();
+        if (t >= 4) {
+            // phase A (stages 1 and 2) at plane f - 2, every lane
+            const double *L = ring1 + ((k + 2) & 3) * 2 * P1; // taken at step t - 2
             const double *V = L + P1;
             const int lc = w.lc;
             const double la = lap4(B, qa2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
                                    L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa0, qa1, qa3, qa4);
-            const double lv = lap4(B, qv2, V[lc - 2], V[lc - 1], V[lc + 1], V[lc + 2], V[lc - 2 * T::LX],
-                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], qv0, qv1, qv3, qv4);
+            const double un = qa2, rn = qr2, u2 = fma(a1, qr2, qa2);
+            const double lv = lap4(B, u2, V[lc - 2], V[lc - 1], V[lc + 1], V[lc + 2], V[lc - 2 * T::LX],
+                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], fma(a1, qr0, qa0),
+                                   fma(a1, qr1, qa1), fma(a1, qr3, qa3), fma(a1, qr4, qa4));
             const double kr1 = HASC2 ? qc2 * la : la;
             const double kr2 = HASC2 ? qc2 * lv : lv;
-            const double un = qa2, rn = qr2, u2 = qv2;
             const double r2 = fma(a1, kr1, rn);
             const double u3 = fma(a2, r2, un);
             const double r3 = fma(a2, kr2, rn);
             const double u4 = fma(a3, r3, un);
             du0 = fma(b3, r3, fma(b2, r2, fma(1.0 / 3.0, u2 - un, un)));
             dr0 = fma(b2, kr2, fma(1.0 / 3.0, r2 - rn, rn));
-            double *R2 = ring2 + mod3(p1) * 2 * P2;
+            double *R2 = ring2 + (k & 3) * 2 * P2;
             R2[l2] = u3;
             R2[P2 + l2] = u4;
             qb0 = qb1; qb1 = qb2; qb2 = qb3; qb3 = qb4; qb4 = u3;
             qd0 = qd1; qd1 = qd2; qd2 = qd3; qd3 = qd4; qd4 = u4;
         }
-        const int p2 = f - 4;
-        if (out && p2 >= P.z0 && p2 < P.z1) {
-            // phase B (stages 3 and 4) at plane p2, the output tile
-            const double *L = ring2 + mod3(p2) * 2 * P2;
+        const bool wr = out && t >= 8 && t - 8 < tz;
+        double yu = 0.0, yr = 0.0;
+        if (wr) {
+            // phase B (stages 3 and 4) at plane f - 4, the output tile
+            const double *L = ring2 + ((k + 2) & 3) * 2 * P2; // written at step t - 2
             const double *V = L + P2;
             const double l3 = lap4(B, qb2, L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
                                    L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb0, qb1, qb3, qb4);
@@ -722,11 +762,19 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             const double kr3 = HASC2 ? qc0 * l3 : l3;
             const double kr4 = HASC2 ? qc0 * l4 : l4;
             const double r4 = fma(a3, kr3, qr0);
-            const int64_t c = w.point(B, p2);
-            st(B.q[0] + c, fma(b4, r4, du2));
-            st(B.q[1] + c, fma(b4, kr4, fma(b3, kr3, dr2)));
+            yu = fma(b4, r4, du2);
+            yr = fma(b4, kr4, fma(b3, kr3, dr2));
         }
-        if (p1 >= P.z0 - 2) {
+        // Two stores on every step and lane (dropped where there is no
+        // output point), so the count of memory operations after the next
+        // plane's loads is fixed and the wait for those loads does not
+        // drain these stores.
+        const int p2 = P.z0 + t - 8, pc = p2 < 0 ? 0 : p2 < nz ? p2 : nz - 1;
+        const int64_t pz = (int64_t)(pc + w.g) * w.sz;
+        const unsigned off = wr ? (unsigned)(w.i + w.g + (int64_t)(w.j + w.g) * B.sy) * 8u : NO_STORE;
+        st_or_drop(B.q[0] + pz, plane_bytes, off, yu);
+        st_or_drop(B.q[1] + pz, plane_bytes, off, yr);
+        if (t >= 4) {
             du2 = du1;
             du1 = du0;
             dr2 = dr1;
@@ -1502,7 +1550,8 @@ hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[
                             hipStream_t s)
 {
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
-    if (run < 0 || total <= 0)
+    // the output stores address one z plane with 31-bit byte offsets
+    if (run < 0 || total <= 0 || B.sz * 8 >= (int64_t)NO_STORE)
         return hipErrorInvalidValue;
     const int64_t grid = run == 0 ? (int64_t)B.tiles[0] * B.tiles[1] * B.tiles[2] : (total + run - 1) / run;
     const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};

@@ -43,9 +43,10 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 // of txe x (nw*64/txe) lanes, output tiles of (txe-4) x (tye-4) (B.tiles[0..1]
 // counts them).  run = 0: one workgroup per work item (tile, z chunk of
 // B.tz planes); run > 0: each workgroup runs `run` planes of the box's
-// tile-plane sequence (run_piece).  B.in, p[0], p[5]: u_n, rho_n, c^2 (optional); q[0],
-// q[1]: u_{n+1}, rho_{n+1}, which must not alias the inputs.  K: the
-// coefficients of stages 1..4.
+// tile-plane sequence (run_piece).  B.in, p[0], p[5]: u_n, rho_n, c^2
+// (optional); q[0], q[1]: u_{n+1}, rho_{n+1}, which must not alias the
+// inputs.  K: the coefficients of stages 1..4.  hipErrorInvalidValue for
+// z planes of 2 GiB or more.
 hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
                             hipStream_t s);
 // resident workgroups per CU of the whole-step kernel (0 if unknown)
