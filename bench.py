@@ -4,10 +4,11 @@
 Headline: classical RK4 of the 3-D scalar wave equation (first-order form)
 on one 256^3 periodic box with 2 ghost zones, h = 1/256, dt = h/4, inputs
 u = U + Gaussian pulse (sigma 0.1), rho = U with U uniform in [-1, 1)
-(seeded splitmix64).  A step is one RK4 step: four stage kernels
-(Laplacian + stage update + running sum, periodic addressing), captured
-once in a hipGraph and replayed, or the two fused stage-pair kernels when the
-tuner picks them.  value = interior points x RK4 steps / s.
+(seeded splitmix64).  A step is one RK4 step, captured once in a hipGraph
+and replayed, with the kernel set the tuner picks: one whole-step kernel,
+two fused stage-pair kernels, or four stage kernels (Laplacian + stage
+update + running sum, periodic addressing).  value = interior points x RK4
+steps / s.
 
 The same JSON line also reports, each on its own workload:
   tuning   the RK4 tile choice from the heuristic, from the library's on-line
@@ -85,8 +86,8 @@ def traffic_from_profile(kernel_key, tile):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--sections", default="rk4,tuning,rhs,copy,mixed,batched,level,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
@@ -510,7 +511,7 @@ def main():
            "warmup": WU, "ms_per_step": round(wall * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "wave256_rk4: 256^3 interior + 2 ghosts, periodic, FP64, h=1/256, dt=h/4, "
-                                  "u=U+Gaussian(0.1), rho=U, RK4 steps (hipGraph of 4 fused stage kernels)",
+                                  "u=U+Gaussian(0.1), rho=U, RK4 steps replayed as a hipGraph",
                       "points": npts, "seed": d["seed"], "tile": [choice["tile_x"], choice["tile_y"],
                                                                    choice["z_chunk"], choice["threads"]],
                       "tile_from_tuner": bool(choice["tuned"])},
