@@ -426,7 +426,7 @@ def main():
         torch.cuda.synchronize()
         one_ms = (time.perf_counter() - t0) * 1e3 / kl
         del one_u, one_r, wso
-        ch = S.s4_get_choice(ctx, S.S4_OP_RK4, lboxes)
+        ch = S.s4_level_choice(ctx, lev)
         out["level"] = {"workload": "level60: 60 boxes, sides U[16,96], g=3, tiling a 280x224x168 periodic domain, "
                                     "face exchange of width 2 before every RK4 stage",
                         "interior_points": lpts, "steps": kl, "modes": res,

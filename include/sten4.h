@@ -221,7 +221,9 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
  * LoopControl tunes per loop setup, Sec. III-B).  Scratch buffers are
  * taken from `scratch` (device memory of at least s4_tune_scratch_size
  * bytes); the caller's data are not touched.  flags: 0 = quick sweep,
- * 1 = full sweep.  Persists to S4_TUNE_CACHE when set. */
+ * 1 = full sweep.  Persists to S4_TUNE_CACHE when set.  For RK4 on several
+ * boxes it also keeps the fastest candidate that can run on a level
+ * (s4_level_choice), for the same boxes coupled as a level. */
 int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scratch,
             size_t scratch_bytes, void *stream);
 
@@ -236,7 +238,9 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
  * out[7] number of candidates this op may use on
  * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 or 101 when the
  * choice is one of RK4's two fused stage-pair kernel sets (widened tile,
- * per-tap second stage) and 200 + the kernel op when it is
+ * per-tap second stage), 102 when it is the whole-step kernel set (one
+ * launch per RK4 step on a tile widened by 4 points in total along x and y)
+ * and 200 + the kernel op when it is
  * the row-register kernel set (out[1] is then the item's x extent, 64 per
  * wavefront along x, and out[2] its y extent). */
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
@@ -393,6 +397,15 @@ int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *worksp
  * the schedule). */
 int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,
                  double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream);
+
+/* The tile choice s4_level_rk4 uses on this level, laid out as
+ * s4_get_choice's out[] (out[7]: the candidates RK4 may use on these
+ * boxes).  A level runs only kernel sets whose stencils read radius-2 ghost
+ * zones: a forced or tuned choice for the boxes that needs more (the
+ * widened-tile sets, out[0] 100 or 102) is replaced by the fastest
+ * level-capable candidate s4_tune found, else by the heuristic start.
+ * Sec. III-B (a loop setup's execution parameters). */
+int s4_level_choice(s4_ctx *ctx, const s4_level *L, int out[8]);
 
 /* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned):
  * the streaming-copy probe that calibrates achievable HBM bandwidth and the

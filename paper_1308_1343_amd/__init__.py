@@ -42,7 +42,7 @@ EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_wor
            "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
            "s4_bset_derivative", "s4_bset_info", "s4_bset_keys", "s4_bset_boxes", "s4_bset_contains",
            "s4_bset_equal", "s4_level_create", "s4_level_destroy", "s4_level_info", "s4_level_pieces",
-           "s4_level_workspace_size", "s4_level_sync", "s4_level_rk4")
+           "s4_level_workspace_size", "s4_level_sync", "s4_level_rk4", "s4_level_choice")
 
 
 class S4Box(ctypes.Structure):
@@ -116,6 +116,7 @@ def lib():
     L.s4_level_workspace_size.argtypes = [vp, i, ctypes.POINTER(sz)]
     L.s4_level_sync.argtypes = [vp, vp, PP, vp, sz, vp]
     L.s4_level_rk4.argtypes = [vp, vp, PP, PP, PP, d, i, i, vp, sz, vp]
+    L.s4_level_choice.argtypes = [vp, vp, ctypes.POINTER(i)]
     for name in EXPORTS:
         if name not in ("s4_destroy", "s4_last_error", "s4_bset_free", "s4_level_destroy"):
             getattr(L, name).restype = i
@@ -327,12 +328,21 @@ def s4_tune(ctx, op, boxes, flags=0, scratch=None, stream=None):
     _check(lib().s4_tune(ctx.handle, op, arr, n, int(flags), _ptr(scratch), scratch.numel(), _stream(stream)))
 
 
+CHOICE_KEYS = ("kernel_op", "tile_x", "tile_y", "z_chunk", "threads", "tuned", "candidate", "ncandidates")
+
+
 def s4_get_choice(ctx, op, boxes) -> dict:
     arr, n = _boxes(boxes)
     out = (ctypes.c_int * 8)()
     _check(lib().s4_get_choice(ctx.handle, op, arr, n, out))
-    keys = ("kernel_op", "tile_x", "tile_y", "z_chunk", "threads", "tuned", "candidate", "ncandidates")
-    return dict(zip(keys, list(out)))
+    return dict(zip(CHOICE_KEYS, list(out)))
+
+
+def s4_level_choice(ctx, level) -> dict:
+    """The tile choice s4_level_rk4 uses on this level (keys as s4_get_choice)."""
+    out = (ctypes.c_int * 8)()
+    _check(lib().s4_level_choice(ctx.handle, level.handle, out))
+    return dict(zip(CHOICE_KEYS, list(out)))
 
 
 def s4_set_choice(ctx, op, boxes, candidate):

@@ -90,10 +90,11 @@ static int hip_fail(hipError_t e, const char *where)
 // stages -- variant 1 recomputes the first stage on a widened workgroup tile
 // tx x (nw*64/tx) with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms
 // the second stage's stencil input at each tap on the plain tile
-// tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (one
-// box) runs a whole RK4 step per pass on the widened tile of variant 1,
-// stages 1-2 on all lanes and 3-4 on the output tile.  tz is the z chunk
-// (0 = whole box; for variant 4, equal shares of the tile-plane sequence).  The list is ordered so that the
+// tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (any
+// number of periodic boxes, no levels) runs a whole RK4 step per pass on the
+// widened tile of variant 1, stages 1-2 on all lanes and 3-4 on the output
+// tile.  tz is the z chunk (0 = whole box; for variant 4 on one box, equal
+// shares of the tile-plane sequence).  The list is ordered so that the
 // candidates any op may use form a prefix of it.
 struct Cand {
     int tx, nw, tz;
@@ -116,12 +117,12 @@ static const std::vector<Cand> &cands()
         for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}, {16, 8}, {16, 4}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 3, 0});
+        for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}}) // 64 x 8 wastes half its lanes
+            for (int tz : {0, 128, 64, 32})
+                c.push_back({tn.first, tn.second, tz, 4, 0});
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 1, 0});
-        for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}, {64, 8}})
-            for (int tz : {0, 128, 64, 32})
-                c.push_back({tn.first, tn.second, tz, 4, 0});
         return c;
     }();
     return v;
@@ -143,9 +144,16 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
         return true;
     if (c.variant == 2)
         return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
-    if (c.variant == 3)
+    if (c.variant == 3 || c.variant == 4)
         return op == S4_OP_RK4;
-    return op == S4_OP_RK4 && nbox == 1; // variants 1 and 4
+    return op == S4_OP_RK4 && nbox == 1; // variant 1
+}
+
+// whether candidate c can run RK4 on a level (ghost-addressed stencils of
+// radius 2; the widened-tile sets need radius 4 or wrap around one box)
+static bool level_capable(const Cand &c)
+{
+    return c.variant != 1 && c.variant != 4;
 }
 
 static int kernel_op(int op)
@@ -342,15 +350,25 @@ static int tile_heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
     return cand_index(tx, nw, 8);
 }
 
-// Starting setting of an op.  RK4 runs two stages per pass with the per-tap
-// stage pairs (variant 3): tile 64 x 4 (whole 512-byte rows) unless idle
-// lanes of ragged boxes would pass a fifth of the lanes, then 32 x 16; the
-// longest z chunk that gives every CU four items (eight over several boxes,
-// whose uneven sizes the work queue balances best in small pieces).
-static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox)
+// Starting setting of an op.  RK4 runs a whole step per pass (variant 4)
+// on 32 x 16 lanes (two workgroups per CU) in 32-plane chunks, the setting
+// the sweep picks on one 256^3 box and on sets of small boxes alike.  On a
+// level (level: radius-2 ghost zones only), and for z planes of 2 GiB or
+// more, RK4 runs two stages per pass with
+// the per-tap stage pairs (variant 3): tile 64 x 4 (whole 512-byte rows)
+// unless idle lanes of ragged boxes would pass a fifth of the lanes, then
+// 32 x 16; the longest z chunk that gives every CU four items (eight over
+// several boxes, whose uneven sizes the work queue balances best in small
+// pieces).
+static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool level = false)
 {
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
+    bool huge = false; // whole steps address one z plane with 31-bit byte offsets
+    for (int i = 0; i < nbox; ++i)
+        huge = huge || b[i].stride[2] * 8 >= (int64_t)0x80000000;
+    if (!level && !huge)
+        return cand_index(32, 8, 32, 4);
     double pts = 0, lanes = 0;
     for (int i = 0; i < nbox; ++i) {
         pts += (double)b[i].n[0] * b[i].n[1] * b[i].n[2];
@@ -392,14 +410,18 @@ std::vector<int> Hill::neighbours(int c) const
     return out;
 }
 
-static std::vector<int> allowed_cands(int op, int nbox)
+static std::vector<int> allowed_cands(int op, int nbox, bool level = false)
 {
     std::vector<int> v;
     for (int i = 0; i < (int)cands().size(); ++i)
-        if (cand_allowed(cands()[i], op, nbox))
+        if (cand_allowed(cands()[i], op, nbox) && (!level || level_capable(cands()[i])))
             v.push_back(i);
     return v;
 }
+
+// setup key of the RK4 steps of a level: the boxes' key, marked, so that a
+// level keeps its own choice among the level-capable candidates
+static const char *const LEVEL_SUFFIX = "|level";
 
 struct Choice {
     int cand;
@@ -410,39 +432,46 @@ struct Choice {
 static void online_harvest(OnlineSetup &st);
 
 // caller holds ctx->mu
-static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox)
+static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox,
+                                 bool level)
 {
     auto it = ctx->online_state.find(key);
     if (it != ctx->online_state.end())
         return it->second;
     OnlineSetup &st = ctx->online_state[key];
-    st.hill.allowed = allowed_cands(op, nbox);
+    st.hill.allowed = allowed_cands(op, nbox, level);
     auto t = ctx->tuned.find(key);
-    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, op, b, nbox);
+    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, op, b, nbox, level);
     st.hill.restart_prob = ctx->restart_prob;
     st.hill.rng ^= ctx->seed * 0xD1342543DE82EF95ull + std::hash<std::string>()(key);
     return st;
 }
 
-// peek: report the choice without advancing the on-line tuner
-static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false)
+// peek: report the choice without advancing the on-line tuner.  level: the
+// RK4 steps of a level (its own setup key; level-capable candidates only,
+// a forced or tuned choice of the boxes is taken if it is one)
+static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false, bool level = false)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const std::string key = setup_key(ctx, op, b, nbox);
-    auto f = ctx->forced.find(key);
-    if (f != ctx->forced.end())
+    const std::string bkey = setup_key(ctx, op, b, nbox);
+    const std::string key = level ? bkey + LEVEL_SUFFIX : bkey;
+    auto ok = [&](int c) { return !level || level_capable(cands()[c]); };
+    auto f = ctx->forced.find(bkey);
+    if (f != ctx->forced.end() && ok(f->second))
         return {f->second, 0, key};
     if (ctx->online) {
-        OnlineSetup &st = online_setup(ctx, key, op, b, nbox);
+        OnlineSetup &st = online_setup(ctx, key, op, b, nbox, level);
         online_harvest(st);
         if (peek)
             return {st.hill.best >= 0 ? st.hill.best : st.hill.start, 2, key};
         return {st.hill.next(), 2, key};
     }
-    auto t = ctx->tuned.find(key);
-    if (t != ctx->tuned.end())
-        return {t->second, 1, key};
-    return {heuristic(ctx, op, b, nbox), 0, key};
+    for (const std::string &k : {key, bkey}) {
+        auto t = ctx->tuned.find(k);
+        if (t != ctx->tuned.end() && ok(t->second))
+            return {t->second, 1, key};
+    }
+    return {heuristic(ctx, op, b, nbox, level), 0, key};
 }
 
 // Timing of one call for the on-line tuner: events around the call's
@@ -934,6 +963,9 @@ void s4_destroy(s4_ctx *ctx)
     delete ctx;
 }
 
+static void fill_choice(int op, int nbox, const Choice &ch, int out[8]);
+static int level_check(const s4_level *L);
+
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
 {
     if (!ctx || !out)
@@ -941,7 +973,24 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
     int r = s4_check_boxes(b, nbox, op);
     if (r)
         return r;
-    const Choice ch = choose(ctx, op, b, nbox, true);
+    fill_choice(op, nbox, choose(ctx, op, b, nbox, true), out);
+    return S4_OK;
+}
+
+int s4_level_choice(s4_ctx *ctx, const s4_level *L, int out[8])
+{
+    if (!ctx || !out)
+        return fail(S4_EINVAL, "NULL argument");
+    int r = level_check(L);
+    if (r)
+        return r;
+    const int nbox = (int)L->boxes.size();
+    fill_choice(S4_OP_RK4, nbox, choose(ctx, S4_OP_RK4, L->boxes.data(), nbox, true, true), out);
+    return S4_OK;
+}
+
+static void fill_choice(int op, int nbox, const Choice &ch, int out[8])
+{
     const Cand &c = cands()[ch.cand];
     // 100, 101: RK4 stage pairs (widened tile, per-tap); 102: whole RK4 steps;
     // 200 + op: the op's kernels on the row-register traversal
@@ -960,7 +1009,6 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
     while (allowed < (int)cands().size() && cand_allowed(cands()[allowed], op, nbox))
         ++allowed;
     out[7] = allowed;
-    return S4_OK;
 }
 
 int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
@@ -1494,8 +1542,8 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
 {
     int r;
     char *ws = (char *)workspace;
-    if ((cands()[ch.cand].variant == 1 || cands()[ch.cand].variant == 4) && nbox == 1) {
-        // widened-tile stage pairs or whole steps: pairs of steps, an odd last step with the stage kernels
+    if (cands()[ch.cand].variant == 1 && nbox == 1) {
+        // widened-tile stage pairs: pairs of steps, an odd last step with the stage kernels
         const Cand &cp = cands()[ch.cand];
         const PairFields W = pair_fields(b[0], ws);
         const double *c2b = c2 ? c2[0] : nullptr;
@@ -1523,7 +1571,7 @@ static int rk4_run(s4_ctx *ctx, const Choice &ch, const s4_box *b, int nbox, dou
         rk4_tables(b, nbox, u, rho, c2, ws, c0, tab0);
         return rk4_step(ctx, c0, tab0, nbox, false, nullptr, nullptr, dev_items(tab0[0]), dt, s);
     }
-    if (cands()[ch.cand].variant == 3) {
+    if (cands()[ch.cand].variant == 3 || cands()[ch.cand].variant == 4) {
         if ((r = pair_run(ctx, ch.cand, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, nullptr)) ||
             nsteps % 2 == 0)
             return r;
@@ -1933,6 +1981,13 @@ static void pair_tables(const s4_box *b, int nbox, double *const *u, double *con
             A.in = ui;
             A.p[0] = ri;
             A.p[5] = c2 ? c2[i] : nullptr;
+            if (c.variant == 4) { // one whole step: y_n -> y_{n+1} (table 2p; 2p+1 unused)
+                A.q[0] = uo;
+                A.q[1] = ro;
+                tab[(size_t)(2 * p) * nbox + i] = A;
+                tab[(size_t)(2 * p + 1) * nbox + i] = A;
+                continue;
+            }
             A.q[0] = W.U3;
             A.q[1] = W.R3;
             A.q[2] = W.AU;
@@ -1958,6 +2013,31 @@ static int pair_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab,
                      const SyncArgs *sy)
 {
     const bool gh = sy != nullptr;
+    if (c.variant == 4) { // one whole-step launch (periodic boxes only)
+        if (gh)
+            return fail(S4_ENOTSUP, "whole RK4 steps do not run on levels");
+        const StageCoef K[4] = {rk4_coef(0, dt), rk4_coef(1, dt), rk4_coef(2, dt), rk4_coef(3, dt)};
+        const DevBox *T = tab.data() + (size_t)(2 * parity) * nbox;
+        bool hasc2 = false;
+        for (int i = 0; i < nbox; ++i) {
+            if (T[i].sz * 8 >= (int64_t)0x80000000)
+                return fail(S4_ENOTSUP, "whole RK4 steps need z planes below 2 GiB (box %d)", i);
+            hasc2 = hasc2 || T[i].p[5] != nullptr;
+        }
+        hipError_t e = hipSuccess;
+        if (batched) {
+            int per = max_blocks_step4(c.tx, c.nw);
+            if (per <= 0)
+                per = 1;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
+            e = launch_rk4_step4_batched(c.tx, c.nw, hasc2, dtab + (size_t)(2 * parity) * nbox, nbox,
+                                         step_queue(ctx, counters, parity, nitems), grid, K, s);
+        } else {
+            for (int i = 0; i < nbox && e == hipSuccess; ++i)
+                e = launch_rk4_step4(c.tx, c.nw, T[i], K, step4_run(ctx, c, T[i]), ctx->nxcd, s);
+        }
+        return e == hipSuccess ? S4_OK : hip_fail(e, "whole-step launch");
+    }
     for (int k = 0; k < 2; ++k) {
         const StageCoef K1 = rk4_coef(2 * k, dt), K2 = rk4_coef(2 * k + 1, dt);
         const int t = 2 * parity + k;
@@ -2073,9 +2153,7 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     if ((r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, ws_bytes, need)) || nsteps == 0)
         return r;
     hipStream_t s = (hipStream_t)stream;
-    int ci = choose(ctx, S4_OP_RK4, b, nbox, true).cand;
-    if (cands()[ci].variant == 1 || cands()[ci].variant == 4) // widened tiles wrap around one box
-        ci = heuristic(ctx, S4_OP_RK4, b, nbox);
+    const int ci = choose(ctx, S4_OP_RK4, b, nbox, true, true).cand;
     if (cands()[ci].variant != 3)
         return level_stage_run(ctx, L, ci, u, rho, c2, dt, nsteps, mode, workspace, s);
     if ((r = pair_run(ctx, ci, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, L)) || nsteps % 2 == 0)
@@ -2140,8 +2218,8 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     hipEvent_t e0, e1;
     S4_HIP(hipEventCreate(&e0));
     S4_HIP(hipEventCreate(&e1));
-    int best = -1;
-    float best_t = 0;
+    int best = -1, best_level = -1;
+    float best_t = 0, best_level_t = 0;
     for (int ci = 0; ci < (int)cands().size() && !r; ++ci) {
         const Cand &c = cands()[ci];
         if (!cand_allowed(c, op, nbox))
@@ -2162,7 +2240,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             std::vector<char *> wsb(nbox);
             for (int i = 0; i < nbox; ++i)
                 wsb[i] = (char *)F[i][2] - field_shift(b[i]);
-            if (c.variant == 3) {
+            if (c.variant == 3 || c.variant == 4) {
                 std::vector<PairFields> pfs;
                 pair_tables(b, nbox, us.data(), rs.data(), nullptr, wsb, c, tab, pfs);
                 for (int i = 0; i < nbox; ++i)
@@ -2193,9 +2271,9 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             const int set = rot++ % TUNE_SETS;
             switch (op) {
             case S4_OP_RK4:
-                if (c.variant == 3) // one stage-pair step, alternating between (u, rho) and the ping-pong copy
+                if (c.variant == 3 || c.variant == 4) // one step, alternating between (u, rho) and the ping-pong copy
                     return pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, set & 1, s, nullptr);
-                if (c.variant == 1 || c.variant == 4) // one step: (u, rho) -> ping-pong buffers, alternating
+                if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
                     return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
                                          set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
                                          s);
@@ -2273,6 +2351,10 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             best = ci;
             best_t = med;
         }
+        if (level_capable(c) && (best_level < 0 || med < best_level_t)) {
+            best_level = ci;
+            best_level_t = med;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -2280,7 +2362,11 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         return r;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        ctx->tuned[setup_key(ctx, op, b, nbox)] = best;
+        const std::string key = setup_key(ctx, op, b, nbox);
+        ctx->tuned[key] = best;
+        // the same boxes as a level run the best level-capable setting
+        if (op == S4_OP_RK4 && nbox > 1 && best_level >= 0)
+            ctx->tuned[key + LEVEL_SUFFIX] = best_level;
     }
     save_cache(ctx);
     return S4_OK;

@@ -692,8 +692,8 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         const int64_t zo = (int64_t)(kz + w.g) * w.sz;
         nu = uf[w.col + zo];
         nr = rf[w.col + zo];
-        if (HASC2)
-            nc = ldp(c2 + w.col + zo);
+        if (HASC2) // per box in a batched launch: no c^2 reads as 1, an exact factor
+            nc = c2 ? ldp(c2 + w.col + zo) : 1.0;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0) {
@@ -781,6 +781,31 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             dr1 = dr0;
         }
     }
+}
+
+// persistent form over the per-XCD work queue of a table of periodic boxes
+// (items: box, tile, z chunk of B.tz planes), as k_tiles_batched
+template <int TXE, int NW, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_rk4_step4_batched(const DevBox *__restrict__ tab, int nbox,
+                                                               ItemQueue Q, Step4Coef K)
+{
+    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    __shared__ int s_item;
+    constexpr int TYE = Tile<TXE, NW>::TY;
+    int q = blockIdx.x % Q.nq, left = Q.nq;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            s_item = queue_take(Q, q, left);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= Q.nitems)
+            break;
+        const DevBox B = tab[box_of(tab, nbox, item)];
+        run_step4<TXE, NW, HASC2>(B, item_pos(B, item - B.item0, TXE - 4, TYE - 4), K, lds);
+    }
+    if (threadIdx.x == 0)
+        queue_finish(Q);
 }
 
 // Workgroup g (placed so that each XCD holds a contiguous range of g) runs
@@ -1565,7 +1590,27 @@ hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[
             Y(TXE_, NW_, false);                                                                       \
         return hipGetLastError();                                                                      \
     }
-    X(32, 8) X(64, 8) X(64, 16) X(32, 16)
+    X(32, 8) X(64, 16) X(32, 16)
+#undef X
+#undef Y
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rk4_step4_batched(int txe, int nw, bool hasc2, const DevBox *tab, int nbox, const ItemQueue &Q,
+                                    int grid, const StageCoef K[4], hipStream_t s)
+{
+    const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};
+#define Y(TXE_, NW_, C_)                                                                               \
+    hipLaunchKernelGGL((k_rk4_step4_batched<TXE_, NW_, C_>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, Q, C)
+#define X(TXE_, NW_)                                                                                   \
+    if (txe == TXE_ && nw == NW_) {                                                                    \
+        if (hasc2)                                                                                     \
+            Y(TXE_, NW_, true);                                                                        \
+        else                                                                                           \
+            Y(TXE_, NW_, false);                                                                       \
+        return hipGetLastError();                                                                      \
+    }
+    X(32, 8) X(64, 16) X(32, 16)
 #undef X
 #undef Y
     return hipErrorInvalidValue;
@@ -1578,7 +1623,7 @@ int max_blocks_step4(int txe, int nw)
 #define X(TXE_, NW_)                                                                                   \
     if (txe == TXE_ && nw == NW_)                                                                      \
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_step4<TXE_, NW_, true>, NW_ * 64, 0);
-    X(32, 8) X(64, 8) X(64, 16) X(32, 16)
+    X(32, 8) X(64, 16) X(32, 16)
 #undef X
     return e == hipSuccess ? nb : 0;
 }

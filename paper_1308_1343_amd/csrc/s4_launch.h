@@ -49,7 +49,12 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 // z planes of 2 GiB or more.
 hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
                             hipStream_t s);
-// resident workgroups per CU of the whole-step kernel (0 if unknown)
+// persistent form over a table of periodic boxes (queue as launch_tiles_batched);
+// hasc2: some box may have c^2 (p[5], null for the others).  The caller
+// checks that no box has a z plane of 2 GiB or more.
+hipError_t launch_rk4_step4_batched(int txe, int nw, bool hasc2, const DevBox *tab, int nbox, const ItemQueue &Q,
+                                    int grid, const StageCoef K[4], hipStream_t s);
+// resident workgroups per CU of the whole-step kernels (0 if unknown)
 int max_blocks_step4(int txe, int nw);
 
 // Two RK4 stages per pass on the plain tile (pair 0: stages 1-2, pair 1:

@@ -201,6 +201,30 @@ def test_level_sync_argument_errors(ctx):
     assert e.value.code == S.S4_EALIAS
 
 
+def test_level_refuses_whole_steps(ctx):
+    """A whole-step choice for the boxes (radius-4 widened tiles) is replaced on a
+    level by a level-capable one, and the level's result is unchanged by it."""
+    from _gpu import cands_by_kind
+    d = W.level_tiling(**SMALL)
+    L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
+    S.s4_level_rk4(ctx, L, u, r, None, d["dt"], 2, "batched")
+    ref = [host(t) for t in u + r]
+    whole = [c for c in cands_by_kind(ctx, S.S4_OP_RK4, boxes)["fused"]
+             if (S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, c) or True)
+             and S.s4_get_choice(ctx, S.S4_OP_RK4, boxes)["kernel_op"] == 102]
+    assert whole
+    for c in (whole[0], whole[-1]):
+        L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, c)
+        assert S.s4_get_choice(ctx, S.S4_OP_RK4, boxes)["kernel_op"] == 102
+        lc = S.s4_level_choice(ctx, L)
+        assert lc["kernel_op"] not in (100, 102) and lc["candidate"] != c
+        S.s4_level_rk4(ctx, L, u, r, None, d["dt"], 2, "batched")
+        for a, b_ in zip([host(t) for t in u + r], ref):
+            np.testing.assert_array_equal(a[3:-3, 3:-3, 3:-3], b_[3:-3, 3:-3, 3:-3])
+    S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
+
+
 @pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
 @pytest.mark.parametrize("kind,nsteps", [("rows", 3), ("fused", 3), ("fused", 4)])
 def test_level_rk4_kernel_sets_bitwise(ctx, mode, kind, nsteps):
@@ -214,9 +238,14 @@ def test_level_rk4_kernel_sets_bitwise(ctx, mode, kind, nsteps):
     S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
     ref_u, ref_r = [host(t) for t in u], [host(t) for t in r]
     cl = cands_by_kind(ctx, S.S4_OP_RK4, boxes)[kind]
+    if kind == "fused":  # the per-tap stage pairs; whole steps cannot run on a level
+        cl = [c for c in cl if (S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, c) or True)
+              and S.s4_get_choice(ctx, S.S4_OP_RK4, boxes)["kernel_op"] == 101]
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
     for cand in (cl[0], cl[len(cl) // 2], cl[-1]):
         L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
         S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, cand)
+        assert S.s4_level_choice(ctx, L)["candidate"] == cand
         S.s4_level_rk4(ctx, L, u, r, None, d["dt"], nsteps, mode)
         for a, b_ in zip([host(t) for t in u] + [host(t) for t in r], ref_u + ref_r):
             np.testing.assert_array_equal(a[3:-3, 3:-3, 3:-3], b_[3:-3, 3:-3, 3:-3], err_msg=f"candidate {cand}")

@@ -182,8 +182,9 @@ def test_bboxset_modes_match_oracle(ctx):
 @pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
 @pytest.mark.parametrize("nsteps", [2, 3])
 def test_bboxset_stage_pairs_bitwise(ctx, mode, nsteps):
-    """Stage-pair candidates on a set of self-periodic boxes, some with c^2 and some without,
-    bit for bit against the per-stage tile kernels (odd counts end with one per-stage step)."""
+    """Stage-pair and whole-step candidates on a set of self-periodic boxes, some with c^2 and
+    some without, bit for bit against the per-stage tile kernels (odd counts end with one
+    per-stage step)."""
     boxes = small_bboxset(13, 7)
     g, dt = 3, 0.25 / 128
 
@@ -202,7 +203,11 @@ def test_bboxset_stage_pairs_bitwise(ctx, mode, nsteps):
     ref, bs = run(2)
     pairs = cands_by_kind(ctx, S.S4_OP_RK4, bs)["fused"]
     assert pairs and all(S.s4_get_choice(ctx, S.S4_OP_RK4, bs)["ncandidates"] > c for c in pairs)
-    for cand in (pairs[0], pairs[len(pairs) // 2], pairs[-1]):
+    whole = [c for c in pairs if (S.s4_set_choice(ctx, S.S4_OP_RK4, bs, c) or True)
+             and S.s4_get_choice(ctx, S.S4_OP_RK4, bs)["kernel_op"] == 102]
+    S.s4_set_choice(ctx, S.S4_OP_RK4, bs, -1)
+    assert whole  # whole RK4 steps run on sets of periodic boxes too
+    for cand in sorted({pairs[0], pairs[len(pairs) // 2], pairs[-1], whole[0], whole[len(whole) // 2]}):
         got, _ = run(cand)
         for a, b_ in zip(got, ref):
             np.testing.assert_array_equal(a, b_, err_msg=f"candidate {cand}")
@@ -340,8 +345,17 @@ def test_fused_candidates_only_for_single_box_rk4(ctx):
         S.s4_set_choice(ctx, S.S4_OP_RK4, [b, b], nc - 1)
     assert e.value.code == S.S4_ENOTSUP
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, nc - 1)
-    assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["kernel_op"] in (100, 101, 102)
+    assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["kernel_op"] == 100  # widened stage pairs: one box only
     S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+    # whole steps and per-tap pairs: RK4 on any number of boxes, no other op
+    kinds = cands_by_kind(ctx, S.S4_OP_RK4, [b, b])
+    assert {S.s4_set_choice(ctx, S.S4_OP_RK4, [b, b], c) or S.s4_get_choice(ctx, S.S4_OP_RK4, [b, b])["kernel_op"]
+            for c in kinds["fused"]} == {101, 102}
+    S.s4_set_choice(ctx, S.S4_OP_RK4, [b, b], -1)
+    for op in (S.S4_OP_WAVE_RHS, S.S4_OP_ADJOINT_STEP):
+        with pytest.raises(S.Sten4Error) as e:
+            S.s4_set_choice(ctx, op, b, kinds["fused"][-1])
+        assert e.value.code == S.S4_ENOTSUP
     # row-register candidates: RHS and RK4 only (any number of boxes)
     rows = cands_by_kind(ctx, S.S4_OP_RK4, b)["rows"]
     assert rows and rows == cands_by_kind(ctx, S.S4_OP_WAVE_RHS, b)["rows"]
