@@ -186,7 +186,7 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
                 L[w.hl[s]] = hv[s];
-        __syncthreads();
+        lds_barrier();
         double q4n = 0.0, hvn[T::HS];
         PW pwn;
         if (k + 1 < P.z1) {
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
 #pragma unroll
         for (int v = 0; v < 6; ++v)
             pw[v] = npw[v];
-        __syncthreads();
+        lds_barrier();
         const int p1 = f - 2;
         if (f + 1 <= P.z1 + 3) {
             const int64_t zo = w.zoff(f + 1);
@@ -912,7 +912,7 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
                 if (w.hl[s] >= 0)
                     L[f * PLANE + w.hl[s]] = hv[f][s];
         }
-        __syncthreads();
+        lds_barrier();
         double q4n[NF], hvn[NF][T::HS];
         if (k + 1 < P.z1) {
             const int64_t z3 = w.zoff(k + 3), z1 = w.zoff(k + 1);
@@ -1153,7 +1153,7 @@ __global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxc
                 if (w.hl[s] >= 0)
                     L[f * PLANE + w.hl[s]] = hv[f][s];
         }
-        __syncthreads();
+        lds_barrier();
         const bool more = k + 1 < P.z1;
         if (more) {
             adj_raw<PASS, C2BAR>(B, w.col + w.zoff(k + 3), nr);
@@ -1282,7 +1282,7 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
         for (int s = 0; s < MT::HS; ++s)
             if (w.hl[s] >= 0)
                 F[w.hl[s]] = hv[s];
-        __syncthreads();
+        lds_barrier();
         const int c = w.lf;
         const double xm2 = F[c - 2], xm1 = F[c - 1], xp1 = F[c + 1], xp2 = F[c + 2];
         const double ym2 = F[c - 2 * LX], ym1 = F[c - LX], yp1 = F[c + LX], yp2 = F[c + 2 * LX];
@@ -1297,7 +1297,7 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
                 const int e = w.dlf[s];
                 D[w.dld[s]] = d1x * fma(8.0, F[e + 1] - F[e - 1], -(F[e + 2] - F[e - 2]));
             }
-        __syncthreads();
+        lds_barrier();
         const int dd = w.ld;
         const double gxy = d1y * fma(8.0, D[dd + TX] - D[dd - TX], -(D[dd + 2 * TX] - D[dd - 2 * TX]));
         const double pin = fma(d2x, fma(-30.0, fv, sx), fma(d2y, fma(-30.0, fv, sy), gxy));
