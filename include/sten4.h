@@ -163,7 +163,10 @@ int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const
  * F.  The box is its own periodic neighbour: the stage kernels read stencil
  * neighbours at wrapped indices, which equals a periodic ghost fill before
  * every F without the fill's launches.  u[i], rho[i] are updated in place at
- * interior points; their ghosts are neither read nor written.
+ * interior points; their ghosts are neither read nor written.  The kernel
+ * set (one kernel per stage, two stages per pass, or a whole step per pass
+ * on a tile widened by 2 points each side) is the context's choice for the
+ * loop setup (s4_get_choice); all give the same values bit for bit.
  * c2 as in s4_wave_rhs.  `workspace` is device memory of at least
  * s4_workspace_size(b, nbox, S4_OP_RK4, mode) bytes, 256-byte aligned, owned
  * by the caller and not used by anything else while the call's work runs.
