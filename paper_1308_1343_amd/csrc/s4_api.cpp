@@ -1656,8 +1656,6 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
     return S4_OK;
 }
 
-// The eight launches of one backward RK4 step: forward recompute of the
-// stage states storing L u_s, then the adjoint stages 4, 3, 2, 1.
 // One backward RK4 step: with c2_bar, the forward stage-pair kernel gives
 // u_3 and rho_3; then the two adjoint passes (stages 4-3, then 2-1).
 // Workspace fields: U3 R3 KR2 KR1 ACU ACR.
@@ -1673,7 +1671,9 @@ static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, cons
     const bool cb = c2_bar != nullptr;
     hipError_t e;
     if (cb) {
-        const Cand &pc = cands()[cand_index(64, 4, 32, 3)];
+        // the per-tap pair-0 kernel with the stage-pair heuristic's tile (z
+        // chunks short enough to give every CU several items)
+        const Cand &pc = cands()[heuristic(ctx, S4_OP_RK4, &b, 1, true)];
         DevBox A = devbox(b, pc);
         A.in = u_n;
         A.p[0] = rho_n;

@@ -201,6 +201,23 @@ def test_level_sync_argument_errors(ctx):
     assert e.value.code == S.S4_EALIAS
 
 
+def test_level_choice_after_tuning(ctx):
+    """s4_tune on a level's boxes keeps, besides the fastest setting, the fastest
+    level-capable one, which the level then runs (reported by s4_level_choice)."""
+    d = W.level_tiling(**SMALL)
+    L, boxes, (u, r), _ = level_of(d, fields=(d["u"], d["rho"]))
+    tctx = S.Context(0)
+    S.s4_tune(tctx, S.S4_OP_RK4, boxes, flags=0)
+    bc, lc = S.s4_get_choice(tctx, S.S4_OP_RK4, boxes), S.s4_level_choice(tctx, L)
+    assert bc["tuned"] == 1 and lc["tuned"] == 1
+    assert lc["kernel_op"] not in (100, 102)
+    if bc["kernel_op"] not in (100, 102):
+        assert lc["candidate"] == bc["candidate"]
+    S.s4_level_rk4(tctx, L, u, r, None, d["dt"], 2, "graph")
+    # interiors only: ghost points the face exchange does not fill keep their NaN canaries
+    assert all(bool(torch.isfinite(t[3:-3, 3:-3, 3:-3]).all()) for t in u + r)
+
+
 def test_level_refuses_whole_steps(ctx):
     """A whole-step choice for the boxes (radius-4 widened tiles) is replaced on a
     level by a level-capable one, and the level's result is unchanged by it."""

@@ -366,6 +366,20 @@ def test_fused_candidates_only_for_single_box_rk4(ctx):
         assert e.value.code == S.S4_ENOTSUP
 
 
+def test_heuristic_kernel_sets(ctx):
+    """Untuned RK4 starts on whole steps (one box or a set), and on the per-tap
+    stage pairs where a z plane reaches 2 GiB (the whole-step stores address a
+    plane with 31-bit byte offsets).  Descriptors only: nothing is allocated."""
+    fresh = S.Context(0)
+    b = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
+    assert S.s4_get_choice(fresh, S.S4_OP_RK4, b)["kernel_op"] == 102
+    assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, b])["kernel_op"] == 102
+    big = S.make_box((16384, 16384, 4), 2, (1, 16400, 16400 * 16388), 1.0)
+    assert S.s4_get_choice(fresh, S.S4_OP_RK4, big)["kernel_op"] == 101
+    assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, big])["kernel_op"] == 101
+    assert S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, b)["kernel_op"] == 0
+
+
 def test_errors_on_device_calls(ctx):
     n, g = (8, 8, 8), 2
     u = S.alloc_field(n, g, fill=0.0)
