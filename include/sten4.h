@@ -250,7 +250,9 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
 
 /* Force a candidate (index into the op's candidate list) for this loop
  * setup, or -1 to drop the forced choice.  For tests that compare
- * candidates bit for bit, and for benchmark sweeps. */
+ * candidates bit for bit, and for benchmark sweeps.  S4_ENOTSUP for a
+ * candidate the op cannot use on these boxes (out[7] of s4_get_choice
+ * bounds them; the whole-step kernels also need z planes below 2 GiB). */
 int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate);
 
 /* On-line tuning: the paper's run-time random-restart hill climbing

@@ -149,6 +149,18 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
     return op == S4_OP_RK4 && nbox == 1; // variant 1
 }
 
+// whether candidate c can run on these boxes: the whole-step kernels address
+// one z plane with 31-bit byte offsets
+static bool cand_fits(const Cand &c, const s4_box *b, int nbox)
+{
+    if (c.variant != 4)
+        return true;
+    for (int i = 0; i < nbox; ++i)
+        if (b[i].stride[2] * 8 >= (int64_t)0x80000000)
+            return false;
+    return true;
+}
+
 // whether candidate c can run RK4 on a level (ghost-addressed stencils of
 // radius 2; the widened-tile sets need radius 4 or wrap around one box)
 static bool level_capable(const Cand &c)
@@ -364,11 +376,9 @@ static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool 
 {
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
-    bool huge = false; // whole steps address one z plane with 31-bit byte offsets
-    for (int i = 0; i < nbox; ++i)
-        huge = huge || b[i].stride[2] * 8 >= (int64_t)0x80000000;
-    if (!level && !huge)
-        return cand_index(32, 8, 32, 4);
+    const int whole = cand_index(32, 8, 32, 4);
+    if (!level && cand_fits(cands()[whole], b, nbox))
+        return whole;
     double pts = 0, lanes = 0;
     for (int i = 0; i < nbox; ++i) {
         pts += (double)b[i].n[0] * b[i].n[1] * b[i].n[2];
@@ -410,11 +420,12 @@ std::vector<int> Hill::neighbours(int c) const
     return out;
 }
 
-static std::vector<int> allowed_cands(int op, int nbox, bool level = false)
+static std::vector<int> allowed_cands(int op, const s4_box *b, int nbox, bool level = false)
 {
     std::vector<int> v;
     for (int i = 0; i < (int)cands().size(); ++i)
-        if (cand_allowed(cands()[i], op, nbox) && (!level || level_capable(cands()[i])))
+        if (cand_allowed(cands()[i], op, nbox) && cand_fits(cands()[i], b, nbox) &&
+            (!level || level_capable(cands()[i])))
             v.push_back(i);
     return v;
 }
@@ -439,7 +450,7 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
     if (it != ctx->online_state.end())
         return it->second;
     OnlineSetup &st = ctx->online_state[key];
-    st.hill.allowed = allowed_cands(op, nbox, level);
+    st.hill.allowed = allowed_cands(op, b, nbox, level);
     auto t = ctx->tuned.find(key);
     st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, op, b, nbox, level);
     st.hill.restart_prob = ctx->restart_prob;
@@ -921,7 +932,7 @@ int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, in
         return fail(S4_EINVAL, "noise in [0, 1) and restart_prob in [0, 1]");
     s4_ctx sim; // host-only: the heuristic needs the CU count only
     Hill h;
-    h.allowed = allowed_cands(op, nbox);
+    h.allowed = allowed_cands(op, b, nbox);
     h.start = heuristic(&sim, op, b, nbox);
     h.restart_prob = restart_prob;
     h.rng ^= seed * 0xD1342543DE82EF95ull;
@@ -1021,7 +1032,10 @@ int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
     if (candidate >= (int)cands().size() || candidate < -1)
         return fail(S4_EINVAL, "candidate %d out of range", candidate);
     if (candidate >= 0 && !cand_allowed(cands()[candidate], op, nbox))
-        return fail(S4_ENOTSUP, "candidate %d (fused RK4 stage pairs) applies to S4_OP_RK4 on one box only", candidate);
+        return fail(S4_ENOTSUP, "candidate %d (kernel set %d) does not apply to op %d on %d boxes", candidate,
+                    cands()[candidate].variant, op, nbox);
+    if (candidate >= 0 && !cand_fits(cands()[candidate], b, nbox))
+        return fail(S4_ENOTSUP, "candidate %d (whole RK4 steps) needs z planes below 2 GiB", candidate);
     std::lock_guard<std::mutex> lk(ctx->mu);
     const std::string key = setup_key(ctx, op, b, nbox);
     if (candidate < 0)
@@ -2222,7 +2236,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     float best_t = 0, best_level_t = 0;
     for (int ci = 0; ci < (int)cands().size() && !r; ++ci) {
         const Cand &c = cands()[ci];
-        if (!cand_allowed(c, op, nbox))
+        if (!cand_allowed(c, op, nbox) || !cand_fits(c, b, nbox))
             continue;
         // per candidate: what one call of the op launches, on scratch buffers
         std::vector<DevBox> tab;

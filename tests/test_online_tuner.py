@@ -121,3 +121,15 @@ def test_reaches_every_kernel_set():
                 for d in CANDS]
         tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.0, ncalls=300)
         assert all(CANDS[t] == best for t in tr[-30:]), best
+
+
+def test_whole_steps_skipped_for_huge_planes():
+    """Boxes whose z planes reach 2 GiB never get a whole-step setting (those
+    kernels address one plane with 31-bit byte offsets), even when it would be
+    the fastest; ordinary boxes reach it."""
+    huge = S.make_box((16384, 16384, 4), 2, (1, 16400, 16400 * 16388), 1.0)
+    cost = [0.5 if d[0] == 4 else 1.0 + 0.01 * i for i, d in enumerate(CANDS)]
+    tr = S.s4_online_simulate(S.S4_OP_RK4, huge, cost, restart_prob=0.3, ncalls=400)
+    assert all(CANDS[t][0] != 4 for t in tr)
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.3, ncalls=400)
+    assert CANDS[tr[-1]][0] == 4
