@@ -497,14 +497,20 @@ def main():
         t0 = time.perf_counter()
         O.rk4(u0, r0, g, d["dx"], d["dt"], 1)
         one = time.perf_counter() - t0
-        m = int(min(100, max(2, math.ceil(12.0 / max(one, 1e-3)))))
+        m = int(min(300, max(2, math.ceil(20.0 / max(one, 1e-3)))))  # about 10-30 s of CPU work
         t0 = time.perf_counter()
         O.rk4(u0, r0, g, d["dx"], d["dt"], m)
         el = time.perf_counter() - t0
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+        except OSError:
+            pass
         cpu = {"value": round(npts * m / el / 1e9, 5), "unit": "Gpoint-updates/s", "cores": O.num_threads(),
                "kind": "oracle",
                "sample": f"{m} RK4 steps of the 256^3 wave workload (after one untimed warm-up step), "
-                         f"plain C FP64 oracle with OpenMP, {el:.1f} s"}
+                         f"plain C FP64 oracle with OpenMP on {model}, {el:.1f} s"}
         log(f"[bench] cpu: {cpu}")
 
     rec = {"metric": METRIC, "value": round(value, 3), "unit": "Gpoint-updates/s", "n_gpus": 1, "steps": K,
