@@ -364,7 +364,8 @@ static int tile_heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
 
 // Starting setting of an op.  RK4 runs a whole step per pass (variant 4)
 // on 32 x 16 lanes (two workgroups per CU) in 32-plane chunks, the setting
-// the sweep picks on one 256^3 box and on sets of small boxes alike.  On a
+// the sweep picks on one 256^3 box and on sets of small boxes alike (equal
+// runs per workgroup on one box too small to fill two rounds).  On a
 // level (level: radius-2 ghost zones only), and for z planes of 2 GiB or
 // more, RK4 runs two stages per pass with
 // the per-tap stage pairs (variant 3): tile 64 x 4 (whole 512-byte rows)
@@ -377,8 +378,14 @@ static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool 
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
     const int whole = cand_index(32, 8, 32, 4);
-    if (!level && cand_fits(cands()[whole], b, nbox))
+    if (!level && cand_fits(cands()[whole], b, nbox)) {
+        // one box with fewer than two rounds of 32-plane items (two 512-lane
+        // workgroups per CU): equal runs of its tile-plane sequence instead,
+        // so every resident workgroup has planes and runs pay one start-up
+        if (nbox == 1 && items_of(b[0], cands()[whole]) < 4 * (int64_t)ctx->ncu)
+            return cand_index(32, 8, 0, 4);
         return whole;
+    }
     double pts = 0, lanes = 0;
     for (int i = 0; i < nbox; ++i) {
         pts += (double)b[i].n[0] * b[i].n[1] * b[i].n[2];
@@ -1306,7 +1313,7 @@ static PairFields pair_fields(const s4_box &b, char *ws)
 // Planes per workgroup of the whole-step kernel.  tz > 0: 0, one workgroup
 // per (tile, z chunk) item.  tz = 0 (balanced): the box's tile-plane
 // sequence shared equally by one round of resident workgroups, but no fewer
-// than 16 planes per run (each run pays a 4-plane start-up at either end of
+// than 8 planes per run (each run pays a 4-plane start-up at either end of
 // its z range).
 static int step4_run(const s4_ctx *ctx, const Cand &c, const DevBox &D)
 {
@@ -1317,7 +1324,7 @@ static int step4_run(const s4_ctx *ctx, const Cand &c, const DevBox &D)
     if (per <= 0)
         per = 1;
     const int64_t wgs = (int64_t)per * ctx->ncu;
-    return (int)std::max<int64_t>(16, (total + wgs - 1) / wgs);
+    return (int)std::max<int64_t>(8, (total + wgs - 1) / wgs);
 }
 
 static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *ui, const double *ri,
