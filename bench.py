@@ -16,6 +16,8 @@ The same JSON line also reports, each on its own workload:
   rhs      one 4th-order Laplacian RHS on the 256^3 box (ghosts read), with
            four rotating buffer sets so no pass finds its data in the
            256 MB last-level cache
+  latency32  microseconds per RHS and per RK4 step on the cache-resident
+           32^3 box
   copy     a streaming copy of 1 GiB (achievable HBM bandwidth)
   batched  one RK4 step over a 60-box, 3-level bboxset (sides 16..96, 3
            ghosts) in per-box launches, one persistent batched launch per
@@ -88,7 +90,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--sections", default="rk4,tuning,rhs,copy,mixed,batched,level,adjoint,cpu")
+    ap.add_argument("--sections", default="rk4,tuning,rhs,latency32,copy,mixed,batched,level,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
     args = ap.parse_args()
@@ -264,6 +266,41 @@ def main():
                                                                       ch["threads"]])}
         log(f"[bench] rhs: {out['rhs']}")
         del us, outs
+
+    # ------------------------------------------------------------------ 32^3 latency
+    if "latency32" in sections:
+        # the cache-resident 32^3 box: microseconds per RHS and per RK4 step
+        # (no HBM fraction: 0.5 MB per field stays in cache)
+        d32 = W.wave32()
+        g32, n32 = d32["ghost"], d32["n"]
+        u32 = S.alloc_field(n32, g32, fill=0.0)
+        r32 = S.alloc_field(n32, g32, fill=0.0)
+        S.interior(u32, g32).copy_(torch.from_numpy(d32["u"]))
+        S.interior(r32, g32).copy_(torch.from_numpy(d32["rho"]))
+        b32 = S.box_of(u32, g32, d32["dx"])
+        S.s4_fill_ghosts_periodic(ctx, b32, [u32])
+        o32 = S.alloc_field(n32, g32, fill=0.0)
+        ws32 = S.workspace(S.s4_workspace_size(b32, S.S4_OP_RK4, S.S4_GRAPH))
+        for _ in range(20):
+            S.s4_wave_rhs(ctx, b32, [u32], None, [o32])
+        S.s4_rk4(ctx, b32, [u32], [r32], None, d32["dt"], 20, "graph", ws=ws32)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(200):
+            S.s4_wave_rhs(ctx, b32, [u32], None, [o32])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rhs_us = e0.elapsed_time(e1) / 200 * 1e3
+        e0.record(stream)
+        S.s4_rk4(ctx, b32, [u32], [r32], None, d32["dt"], 200, "graph", ws=ws32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        step_us = e0.elapsed_time(e1) / 200 * 1e3
+        out["latency32"] = {"workload": "wave32: 32^3 + 2 ghosts, periodic, cache-resident",
+                            "us_per_rhs": round(rhs_us, 2), "us_per_rk4_step": round(step_us, 2),
+                            "rk4_kernel_set": kernel_set(S.s4_get_choice(ctx, S.S4_OP_RK4, b32))}
+        log(f"[bench] latency32: {out['latency32']}")
+        del u32, r32, o32, ws32
 
     # ------------------------------------------------------------------ copy probe
     if "copy" in sections:
