@@ -186,6 +186,21 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
 int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
                    double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream);
 
+/* s4_rk4_step_to that also returns the step's third stage state
+ * y_3 = y_n + dt/2 k_2 of classical RK4 (u3_out, rho3_out: interior points,
+ * in the box's layout, ghosts not written), the forward state the backward
+ * step reads (s4_rk4_adjoint_step_y3).  (u_out, rho_out) are bit for bit
+ * those of s4_rk4_step_to, and y_3 bit for bit the value every RK4 kernel
+ * set forms.  u3_out and rho3_out must not be NULL (S4_EINVAL) and must not
+ * overlap the inputs, the other outputs or the workspace (S4_EALIAS).
+ * Runs the current tile choice for S4_OP_RK4 on this machine when it is a
+ * stage-pair or whole-step set (the per-stage sets give way to the stage
+ * pairs), without a trial or timing of the on-line tuner.  Workspace as for
+ * s4_rk4_step_to. */
+int s4_rk4_step_to_y3(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                      double dt, double *u_out, double *rho_out, double *u3_out, double *rho3_out,
+                      void *workspace, size_t ws_bytes, void *stream);
+
 /* Adjoint (transpose) of the wave RHS as a linear map of interior values,
  * for periodic boxes:
  *   F^T(lu, lrho) = (L_p(c^2 lrho), lu),
@@ -216,6 +231,20 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
 int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
                         const double *c2, double dt, double *lam_u, double *lam_rho,
                         double *c2_bar, void *workspace, size_t ws_bytes, void *stream);
+
+/* s4_rk4_adjoint_step given the step's third stage state (u3, rho3), as
+ * s4_rk4_step_to_y3 returns it, instead of recomputing it: with c2_bar the
+ * step then runs its two adjoint passes only.  Results are bit for bit
+ * those of s4_rk4_adjoint_step when (u3, rho3) came from s4_rk4_step_to_y3
+ * on (u_n, rho_n) with the same c2 and dt.  u3 and rho3 are read (interior
+ * points, with periodic addressing) only when c2_bar is not NULL; they are
+ * required then (S4_EINVAL) and may be NULL otherwise.  They must not
+ * overlap lam_u, lam_rho, c2_bar or the workspace (S4_EALIAS).  Workspace
+ * as for s4_rk4_adjoint_step. */
+int s4_rk4_adjoint_step_y3(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
+                           const double *u3, const double *rho3, const double *c2, double dt,
+                           double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
+                           size_t ws_bytes, void *stream);
 
 /* Time the candidate tile shapes and kernel variants of `op` on these boxes
  * (median of hipEvent timings after warm-up, ties to the lowest candidate

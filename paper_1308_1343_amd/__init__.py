@@ -37,7 +37,7 @@ MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 # the entry points include/sten4.h declares
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
            "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
-           "s4_rk4_step_to", "s4_rk4_adjoint_step", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
+           "s4_rk4_step_to", "s4_rk4_step_to_y3", "s4_rk4_adjoint_step", "s4_rk4_adjoint_step_y3", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
            "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
            "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
            "s4_bset_derivative", "s4_bset_info", "s4_bset_keys", "s4_bset_boxes", "s4_bset_contains",
@@ -88,6 +88,8 @@ def lib():
     L.s4_wave_adjoint_rhs.argtypes = [vp, BP, i, PP, PP, PP, PP, PP, vp]
     L.s4_rk4_adjoint_step.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
     L.s4_rk4_step_to.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, sz, vp]
+    L.s4_rk4_step_to_y3.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, vp, vp, sz, vp]
+    L.s4_rk4_adjoint_step_y3.argtypes = [vp, BP, vp, vp, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
     L.s4_tune.argtypes = [vp, i, BP, i, i, vp, sz, vp]
     L.s4_get_choice.argtypes = [vp, i, BP, i, ctypes.POINTER(i)]
     L.s4_set_choice.argtypes = [vp, i, BP, i, i]
@@ -305,6 +307,16 @@ def s4_rk4_step_to(ctx, box, u_in, rho_in, c2, dt, u_out, rho_out, ws=None, stre
     return ws
 
 
+def s4_rk4_step_to_y3(ctx, box, u_in, rho_in, c2, dt, u_out, rho_out, u3_out, rho3_out, ws=None, stream=None):
+    arr, _ = _boxes(box)
+    if ws is None:
+        ws = workspace(s4_workspace_size(box, S4_OP_RK4, S4_PERBOX), u_in.device)
+    _check(lib().s4_rk4_step_to_y3(ctx.handle, arr, _ptr(u_in), _ptr(rho_in), _ptr(c2), float(dt), _ptr(u_out),
+                                   _ptr(rho_out), _ptr(u3_out), _ptr(rho3_out), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return ws
+
+
 def s4_wave_adjoint_rhs(ctx, boxes, lu, lrho, c2, out_u, out_rho, stream=None):
     arr, n = _boxes(boxes)
     _check(lib().s4_wave_adjoint_rhs(ctx.handle, arr, n, _ptrs(lu), _ptrs(lrho),
@@ -318,6 +330,16 @@ def s4_rk4_adjoint_step(ctx, box, u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, ws
         ws = workspace(s4_workspace_size(box, S4_OP_ADJOINT_STEP), u_n.device)
     _check(lib().s4_rk4_adjoint_step(ctx.handle, arr, _ptr(u_n), _ptr(rho_n), _ptr(c2), float(dt), _ptr(lam_u),
                                      _ptr(lam_rho), _ptr(c2_bar), _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def s4_rk4_adjoint_step_y3(ctx, box, u_n, rho_n, u3, rho3, c2, dt, lam_u, lam_rho, c2_bar, ws=None, stream=None):
+    arr, _ = _boxes(box)
+    if ws is None:
+        ws = workspace(s4_workspace_size(box, S4_OP_ADJOINT_STEP), u_n.device)
+    _check(lib().s4_rk4_adjoint_step_y3(ctx.handle, arr, _ptr(u_n), _ptr(rho_n), _ptr(u3), _ptr(rho3), _ptr(c2),
+                                        float(dt), _ptr(lam_u), _ptr(lam_rho), _ptr(c2_bar), _ptr(ws), ws.numel(),
+                                        _stream(stream)))
     return ws
 
 

@@ -9,7 +9,10 @@ or padded views both work); only interior points carry values, and the
 gradients it returns are zero on ghost points.  Forward keeps the state at
 steps 0, k, 2k, ...; backward walks the segments in reverse, recomputes each
 segment's step states from its checkpoint (one out-of-place step each) and
-applies one adjoint step per forward step, accumulating dJ/dc2.  Every arithmetic step runs in libsten4.
+applies one adjoint step per forward step, accumulating dJ/dc2.  With c2 the
+recomputing steps also keep their third stage state y_3, which the adjoint
+step of dJ/dc2 reads, so that step need not form it again.  Every arithmetic
+step runs in libsten4.
 """
 
 from __future__ import annotations
@@ -17,7 +20,8 @@ from __future__ import annotations
 import torch
 
 from . import (S4_GRAPH, S4_OP_ADJOINT_STEP, S4_OP_RK4, S4_PERBOX, box_of, interior,
-               s4_rk4, s4_rk4_adjoint_step, s4_rk4_step_to, s4_workspace_size, workspace)
+               s4_rk4, s4_rk4_adjoint_step, s4_rk4_adjoint_step_y3, s4_rk4_step_to, s4_rk4_step_to_y3,
+               s4_workspace_size, workspace)
 
 
 def _like(t: torch.Tensor, ghost: int, fill=0.0) -> torch.Tensor:
@@ -76,18 +80,31 @@ class WaveRK4(torch.autograd.Function):
         c2bar = _like(ref, ghost) if has_c2 else None
         ws_f = workspace(s4_workspace_size(box, S4_OP_RK4, S4_PERBOX), ref.device)
         ws_a = workspace(s4_workspace_size(box, S4_OP_ADJOINT_STEP), ref.device)
+        def field():
+            # only interior points are ever read
+            return torch.empty_strided(ref.shape, ref.stride(), dtype=ref.dtype, device=ref.device)
+
         for si in reversed(range(len(ckpts))):
             s0 = si * k
             m = min(k, nsteps - s0)
-            states = [ckpts[si]]
+            states, y3 = [ckpts[si]], []
             for _ in range(m - 1):
-                # the next state, out of place; only interior points are ever read
-                nu = torch.empty_strided(ref.shape, ref.stride(), dtype=ref.dtype, device=ref.device)
-                nr = torch.empty_strided(ref.shape, ref.stride(), dtype=ref.dtype, device=ref.device)
-                s4_rk4_step_to(s4ctx, box, states[-1][0], states[-1][1], c2, dt, nu, nr, ws=ws_f)
+                # the next state, out of place (with c2: and this step's y_3)
+                nu, nr = field(), field()
+                if has_c2:
+                    u3, r3 = field(), field()
+                    s4_rk4_step_to_y3(s4ctx, box, states[-1][0], states[-1][1], c2, dt, nu, nr, u3, r3, ws=ws_f)
+                    y3.append((u3, r3))
+                else:
+                    s4_rk4_step_to(s4ctx, box, states[-1][0], states[-1][1], c2, dt, nu, nr, ws=ws_f)
                 states.append((nu, nr))
             for j in reversed(range(m)):
-                s4_rk4_adjoint_step(s4ctx, box, states[j][0], states[j][1], c2, dt, lam_u, lam_r, c2bar, ws=ws_a)
+                un, rn = states.pop()
+                if j < len(y3):
+                    u3, r3 = y3.pop()
+                    s4_rk4_adjoint_step_y3(s4ctx, box, un, rn, u3, r3, c2, dt, lam_u, lam_r, c2bar, ws=ws_a)
+                else:
+                    s4_rk4_adjoint_step(s4ctx, box, un, rn, c2, dt, lam_u, lam_r, c2bar, ws=ws_a)
         return lam_u, lam_r, c2bar, None, None, None, None, None, None
 
 

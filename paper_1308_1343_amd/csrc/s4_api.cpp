@@ -1327,22 +1327,29 @@ static int step4_run(const s4_ctx *ctx, const Cand &c, const DevBox &D)
     return (int)std::max<int64_t>(8, (total + wgs - 1) / wgs);
 }
 
+// One RK4 step (ui, ri) -> (uo, ro) with a stage-pair or whole-step kernel
+// set.  With u3o and r3o the third stage state y_3 = y_n + dt/2 k_2 is also
+// written there (else it stays in the workspace, or on chip).
 static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *ui, const double *ri,
-                         double *uo, double *ro, const double *c2, const PairFields &W, double dt, hipStream_t s)
+                         double *uo, double *ro, const double *c2, const PairFields &W, double dt, hipStream_t s,
+                         double *u3o = nullptr, double *r3o = nullptr)
 {
     DevBox D = devbox(b, c);
     const int items = (int)dev_items(D);
+    double *const U3 = u3o ? u3o : W.U3, *const R3 = u3o ? r3o : W.R3;
     DevBox A = D;
     A.in = ui;
     A.p[0] = ri;
     A.p[5] = c2;
-    A.q[0] = W.U3;
-    A.q[1] = W.R3;
+    A.q[0] = U3;
+    A.q[1] = R3;
     A.q[2] = W.AU;
     A.q[3] = W.AR;
     if (c.variant == 4) {
         A.q[0] = uo;
         A.q[1] = ro;
+        A.q[2] = u3o;
+        A.q[3] = u3o ? r3o : nullptr;
         const StageCoef K[4] = {rk4_coef(0, dt), rk4_coef(1, dt), rk4_coef(2, dt), rk4_coef(3, dt)};
         hipError_t e = launch_rk4_step4(c.tx, c.nw, A, K, step4_run(ctx, c, A), ctx->nxcd, s);
         return e == hipSuccess ? S4_OK : hip_fail(e, "whole-step launch");
@@ -1353,8 +1360,8 @@ static int rk4_pair_step(s4_ctx *ctx, const Cand &c, const s4_box &b, const doub
     if (e != hipSuccess)
         return hip_fail(e, "stage-pair launch");
     DevBox Bx = D;
-    Bx.in = W.U3;
-    Bx.p[0] = W.R3;
+    Bx.in = U3;
+    Bx.p[0] = R3;
     Bx.p[1] = ui;
     Bx.p[2] = ri;
     Bx.p[3] = W.AU;
@@ -1507,10 +1514,14 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
     return S4_OK;
 }
 
-int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
-                   double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream)
+// s4_rk4_step_to and s4_rk4_step_to_y3: one step out of place, optionally
+// keeping y_3 (u3o, r3o non-NULL)
+static int rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                       double dt, double *u_out, double *rho_out, double *u3o, double *r3o, void *workspace,
+                       size_t ws_bytes, void *stream)
 {
-    if (!ctx || !u_in || !rho_in || !u_out || !rho_out)
+    const bool y3 = u3o || r3o;
+    if (!ctx || !u_in || !rho_in || !u_out || !rho_out || (y3 && !(u3o && r3o)))
         return fail(S4_EINVAL, "NULL argument");
     int r = check_boxes(b, 1, S4_OP_RK4);
     if (r)
@@ -1519,7 +1530,8 @@ int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const doubl
         return fail(S4_EINVAL, "dt must be finite and > 0");
     if ((r = check_ptr(u_in, "u_in", 0)) || (r = check_ptr(rho_in, "rho_in", 0)) ||
         (r = check_ptr(u_out, "u_out", 0)) || (r = check_ptr(rho_out, "rho_out", 0)) ||
-        (r = check_ptr(c2, "c2", 0, true)))
+        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(u3o, "u3_out", 0, true)) ||
+        (r = check_ptr(r3o, "rho3_out", 0, true)))
         return r;
     const size_t need = rk4_fields_bytes(b, 1) + rk4_table_bytes(1);
     if (!workspace)
@@ -1529,7 +1541,11 @@ int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const doubl
     if (ws_bytes < need)
         return fail(S4_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
     const size_t n = (size_t)box_elems(b[0]) * 8;
-    const std::vector<Range> wr = {{u_out, n, "u_out", 0}, {rho_out, n, "rho_out", 0}, {workspace, need, "workspace", 0}};
+    std::vector<Range> wr = {{u_out, n, "u_out", 0}, {rho_out, n, "rho_out", 0}, {workspace, need, "workspace", 0}};
+    if (y3) {
+        wr.push_back({u3o, n, "u3_out", 0});
+        wr.push_back({r3o, n, "rho3_out", 0});
+    }
     std::vector<Range> all = wr;
     all.push_back({u_in, n, "u_in", 0});
     all.push_back({rho_in, n, "rho_in", 0});
@@ -1538,6 +1554,17 @@ int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const doubl
     if ((r = check_disjoint(wr, all)))
         return r;
     hipStream_t s = (hipStream_t)stream;
+    if (y3) {
+        // the current choice without a trial of the on-line tuner (these calls
+        // are not timed); per-stage kernel sets give way to the stage pairs,
+        // whose first pass stores y_3
+        int ci = choose(ctx, S4_OP_RK4, b, 1, true).cand;
+        const int v = cands()[ci].variant;
+        if (v != 1 && v != 3 && v != 4)
+            ci = heuristic(ctx, S4_OP_RK4, b, 1, true);
+        return rk4_pair_step(ctx, cands()[ci], b[0], u_in, rho_in, u_out, rho_out, c2,
+                             pair_fields(b[0], (char *)workspace), dt, s, u3o, r3o);
+    }
     const Choice ch = choose(ctx, S4_OP_RK4, b, 1);
     OnlineTimer tm(ctx, ch, s);
     const Cand &c = cands()[ch.cand];
@@ -1555,6 +1582,22 @@ int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const doubl
         return r;
     tm.stop(1.0);
     return S4_OK;
+}
+
+int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                   double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream)
+{
+    return rk4_step_to(ctx, b, u_in, rho_in, c2, dt, u_out, rho_out, nullptr, nullptr, workspace, ws_bytes, stream);
+}
+
+int s4_rk4_step_to_y3(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
+                      double dt, double *u_out, double *rho_out, double *u3_out, double *rho3_out, void *workspace,
+                      size_t ws_bytes, void *stream)
+{
+    if (!u3_out || !rho3_out)
+        return fail(S4_EINVAL, "NULL argument");
+    return rk4_step_to(ctx, b, u_in, rho_in, c2, dt, u_out, rho_out, u3_out, rho3_out, workspace, ws_bytes,
+                       stream);
 }
 
 // the launches of s4_rk4 for choice ch (arguments already validated)
@@ -1678,20 +1721,22 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
 }
 
 // One backward RK4 step: with c2_bar, the forward stage-pair kernel gives
-// u_3 and rho_3; then the two adjoint passes (stages 4-3, then 2-1).
+// u_3 and rho_3 (unless the caller passes them, y3_u and y3_r); then the
+// two adjoint passes (stages 4-3, then 2-1).
 // Workspace fields: U3 R3 KR2 KR1 ACU ACR.
 static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, const double *u_n, const double *rho_n,
                                const double *c2, double dt, double *lam_u, double *lam_rho, double *c2_bar,
-                               char *ws, hipStream_t s)
+                               char *ws, hipStream_t s, const double *y3_u = nullptr, const double *y3_r = nullptr)
 {
     const size_t fb = field_bytes(b);
     double *F[ADJ_FIELDS];
     for (int k = 0; k < ADJ_FIELDS; ++k)
         F[k] = ws_field(ws + k * fb, b);
-    double *U3 = F[0], *R3 = F[1], *KR2 = F[2], *KR1 = F[3], *ACU = F[4], *ACR = F[5];
+    double *KR2 = F[2], *KR1 = F[3], *ACU = F[4], *ACR = F[5];
+    const double *U3 = y3_u ? y3_u : F[0], *R3 = y3_u ? y3_r : F[1];
     const bool cb = c2_bar != nullptr;
     hipError_t e;
-    if (cb) {
+    if (cb && !y3_u) {
         // the per-tap pair-0 kernel with the stage-pair heuristic's tile (z
         // chunks short enough to give every CU several items)
         const Cand &pc = cands()[heuristic(ctx, S4_OP_RK4, &b, 1, true)];
@@ -1699,8 +1744,8 @@ static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, cons
         A.in = u_n;
         A.p[0] = rho_n;
         A.p[5] = c2;
-        A.q[0] = U3;
-        A.q[1] = R3;
+        A.q[0] = F[0];
+        A.q[1] = F[1];
         e = launch_pair2(0, pc.tx, pc.nw, A, rk4_coef(0, dt), rk4_coef(1, dt), (int)dev_items(A), ctx->nxcd, s);
         if (e != hipSuccess)
             return hip_fail(e, "forward stage-pair launch");
@@ -1745,9 +1790,11 @@ static int adjoint_step_launch(s4_ctx *ctx, const Cand &c, const s4_box &b, cons
     return S4_OK;
 }
 
-int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n, const double *c2,
-                        double dt, double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
-                        size_t ws_bytes, void *stream)
+// s4_rk4_adjoint_step and s4_rk4_adjoint_step_y3 (y3_u, y3_r: the step's
+// third stage state, or NULL to form it here)
+static int rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
+                            const double *y3_u, const double *y3_r, const double *c2, double dt, double *lam_u,
+                            double *lam_rho, double *c2_bar, void *workspace, size_t ws_bytes, void *stream)
 {
     if (!ctx)
         return fail(S4_EINVAL, "ctx is NULL");
@@ -1758,8 +1805,11 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
         return fail(S4_EINVAL, "dt must be finite and > 0");
     if ((r = check_ptr(u_n, "u_n", 0)) || (r = check_ptr(rho_n, "rho_n", 0)) ||
         (r = check_ptr(lam_u, "lam_u", 0)) || (r = check_ptr(lam_rho, "lam_rho", 0)) ||
-        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(c2_bar, "c2_bar", 0, true)))
+        (r = check_ptr(c2, "c2", 0, true)) || (r = check_ptr(c2_bar, "c2_bar", 0, true)) ||
+        (r = check_ptr(y3_u, "u3", 0, true)) || (r = check_ptr(y3_r, "rho3", 0, true)))
         return r;
+    if (!y3_u != !y3_r)
+        return fail(S4_EINVAL, "u3 and rho3 must both be given or both be NULL");
     const size_t fb = field_bytes(b[0]);
     const size_t need = ADJ_FIELDS * fb;
     if (!workspace)
@@ -1775,6 +1825,10 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
     std::vector<Range> all = {{u_n, n, "u_n", 0}, {rho_n, n, "rho_n", 0}};
     if (c2)
         all.push_back({c2, n, "c2", 0});
+    if (y3_u) {
+        all.push_back({y3_u, n, "u3", 0});
+        all.push_back({y3_r, n, "rho3", 0});
+    }
     for (auto &w : wr)
         all.push_back(w);
     if ((r = check_disjoint(wr, all)))
@@ -1784,10 +1838,28 @@ int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const d
     const Cand &c = cands()[ch.cand];
     OnlineTimer tm(ctx, ch, (hipStream_t)stream);
     if ((r = adjoint_step_launch(ctx, c, b[0], u_n, rho_n, c2, dt, lam_u, lam_rho, c2_bar, (char *)workspace,
-                                 (hipStream_t)stream)))
+                                 (hipStream_t)stream, y3_u, y3_r)))
         return r;
     tm.stop(1.0);
     return S4_OK;
+}
+
+int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n, const double *c2,
+                        double dt, double *lam_u, double *lam_rho, double *c2_bar, void *workspace,
+                        size_t ws_bytes, void *stream)
+{
+    return rk4_adjoint_step(ctx, b, u_n, rho_n, nullptr, nullptr, c2, dt, lam_u, lam_rho, c2_bar, workspace,
+                            ws_bytes, stream);
+}
+
+int s4_rk4_adjoint_step_y3(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
+                           const double *u3, const double *rho3, const double *c2, double dt, double *lam_u,
+                           double *lam_rho, double *c2_bar, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (c2_bar && (!u3 || !rho3))
+        return fail(S4_EINVAL, "u3 and rho3 are needed with c2_bar");
+    return rk4_adjoint_step(ctx, b, u_n, rho_n, c2_bar ? u3 : nullptr, c2_bar ? rho3 : nullptr, c2, dt, lam_u,
+                            lam_rho, c2_bar, workspace, ws_bytes, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -628,7 +628,9 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
 // Every intermediate is the fma the per-stage kernels store, so results are
 // bit for bit theirs.  Per output point the pass reads u_n, rho_n and c^2
 // and writes u_{n+1}, rho_{n+1}, to other buffers than u_n and rho_n, which
-// neighbouring tiles still read.
+// neighbouring tiles still read.  With Y3 it also writes the third stage
+// state y_3 = (u_3, rho_3) of phase A's plane on the output tile (B.q[2],
+// B.q[3]), which the backward step reads.
 
 template <int TXE, int NW>
 struct Step4Lds {
@@ -643,7 +645,7 @@ struct Step4Coef {
 };
 
 // one tile and z range of a whole step
-template <int TXE, int NW, bool HASC2>
+template <int TXE, int NW, bool HASC2, bool Y3>
 __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, const Step4Coef &K, double *lds)
 {
     using T = Tile<TXE, NW>;
@@ -659,6 +661,8 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     const int lx = threadIdx.x % TXE, ly = threadIdx.x / TXE;
     const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < B.n[0] && w.j < B.n[1];
     const int l2 = ly * TXE + lx;
+    // byte offset of the lane's output point within a z plane
+    const unsigned xy = (unsigned)(w.i + w.g + (int64_t)(w.j + w.g) * B.sy) * 8u;
     const double *__restrict__ uf = B.in;
     const double *__restrict__ rf = B.p[0];
     const double *c2 = HASC2 ? B.p[5] : nullptr;
@@ -677,6 +681,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     double qd0 = 0, qd1 = 0, qd2 = 0, qd3 = 0, qd4 = 0;
     double du0 = 0, du1 = 0, du2 = 0; // acc_u after stage 3
     double dr0 = 0, dr1 = 0, dr2 = 0; // acc_rho after stage 2
+    double y3u = 0, y3r = 0;          // u_3, rho_3 of phase A's plane (Y3)
 
     // Plane step t = 0 .. nt-1 takes plane f = z0 - 4 + t into ring 1 (slot
     // t mod 4), computes phase A at f - 2 from the plane taken at step t - 2
@@ -741,6 +746,10 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             const double u3 = fma(a2, r2, un);
             const double r3 = fma(a2, kr2, rn);
             const double u4 = fma(a3, r3, un);
+            if (Y3) {
+                y3u = u3;
+                y3r = r3;
+            }
             du0 = fma(b3, r3, fma(b2, r2, fma(1.0 / 3.0, u2 - un, un)));
             dr0 = fma(b2, kr2, fma(1.0 / 3.0, r2 - rn, rn));
             double *R2 = ring2 + (k & 3) * 2 * P2;
@@ -771,9 +780,16 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         // drain these stores.
         const int p2 = P.z0 + t - 8, pc = p2 < 0 ? 0 : p2 < nz ? p2 : nz - 1;
         const int64_t pz = (int64_t)(pc + w.g) * w.sz;
-        const unsigned off = wr ? (unsigned)(w.i + w.g + (int64_t)(w.j + w.g) * B.sy) * 8u : NO_STORE;
+        const unsigned off = wr ? xy : NO_STORE;
         st_or_drop(B.q[0] + pz, plane_bytes, off, yu);
         st_or_drop(B.q[1] + pz, plane_bytes, off, yr);
+        if (Y3) { // phase A's plane f - 2 = z0 + t - 6, when it is an output plane
+            const int p3 = P.z0 + t - 6, pc3 = p3 < 0 ? 0 : p3 < nz ? p3 : nz - 1;
+            const unsigned off3 = out && t >= 6 && t - 6 < tz ? xy : NO_STORE;
+            const int64_t pz3 = (int64_t)(pc3 + w.g) * w.sz;
+            st_or_drop(B.q[2] + pz3, plane_bytes, off3, y3u);
+            st_or_drop(B.q[3] + pz3, plane_bytes, off3, y3r);
+        }
         if (t >= 4) {
             du2 = du1;
             du1 = du0;
@@ -802,7 +818,7 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_step4_batched(const DevBox *__r
         if (item >= Q.nitems)
             break;
         const DevBox B = tab[box_of(tab, nbox, item)];
-        run_step4<TXE, NW, HASC2>(B, item_pos(B, item - B.item0, TXE - 4, TYE - 4), K, lds);
+        run_step4<TXE, NW, HASC2, false>(B, item_pos(B, item - B.item0, TXE - 4, TYE - 4), K, lds);
     }
     if (threadIdx.x == 0)
         queue_finish(Q);
@@ -813,14 +829,13 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_step4_batched(const DevBox *__r
 // workgroups of one XCD march a compact patch of tiles through the same
 // planes and share their halo lines in its L2 -- or, with run > 0, planes
 // [g * run, (g + 1) * run) of the box's tile-plane sequence.
-template <int TXE, int NW, bool HASC2>
-__global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
+template <int TXE, int NW, bool HASC2, bool Y3>
+__device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, int run, int nxcd, double *lds)
 {
-    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
     constexpr int TYE = Tile<TXE, NW>::TY;
     const int g = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     if (run == 0) {
-        run_step4<TXE, NW, HASC2>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
+        run_step4<TXE, NW, HASC2, Y3>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
         return;
     }
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
@@ -828,9 +843,24 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, in
     const int64_t e = s + run < total ? s + run : total;
     ItemPos P;
     while (run_piece(B, TXE - 4, TYE - 4, s, e, P)) {
-        run_step4<TXE, NW, HASC2>(B, P, K, lds);
+        run_step4<TXE, NW, HASC2, Y3>(B, P, K, lds);
         __syncthreads(); // the next piece rewrites the LDS rings
     }
+}
+
+template <int TXE, int NW, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
+{
+    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    step4_grid<TXE, NW, HASC2, false>(B, K, run, nxcd, lds);
+}
+
+// the same step, also storing the third stage state (u_3, rho_3)
+template <int TXE, int NW, bool HASC2>
+__global__ __launch_bounds__(NW * 64) void k_rk4_step4_y3(DevBox B, Step4Coef K, int run, int nxcd)
+{
+    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    step4_grid<TXE, NW, HASC2, true>(B, K, run, nxcd, lds);
 }
 
 
@@ -1575,19 +1605,25 @@ hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[
                             hipStream_t s)
 {
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
-    // the output stores address one z plane with 31-bit byte offsets
-    if (run < 0 || total <= 0 || B.sz * 8 >= (int64_t)NO_STORE)
+    // the output stores address one z plane with 31-bit byte offsets; y_3
+    // goes to q[2] and q[3] when both are given
+    const bool y3 = B.q[2] != nullptr;
+    if (run < 0 || total <= 0 || B.sz * 8 >= (int64_t)NO_STORE || y3 != (B.q[3] != nullptr))
         return hipErrorInvalidValue;
     const int64_t grid = run == 0 ? (int64_t)B.tiles[0] * B.tiles[1] * B.tiles[2] : (total + run - 1) / run;
     const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};
-#define Y(TXE_, NW_, C_)                                                                               \
-    hipLaunchKernelGGL((k_rk4_step4<TXE_, NW_, C_>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, B, C, run, nxcd)
+#define Y(K_, TXE_, NW_, C_)                                                                           \
+    hipLaunchKernelGGL((K_<TXE_, NW_, C_>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, B, C, run, nxcd)
 #define X(TXE_, NW_)                                                                                   \
     if (txe == TXE_ && nw == NW_) {                                                                    \
-        if (B.p[5] != nullptr)                                                                         \
-            Y(TXE_, NW_, true);                                                                        \
+        if (y3 && B.p[5] != nullptr)                                                                   \
+            Y(k_rk4_step4_y3, TXE_, NW_, true);                                                        \
+        else if (y3)                                                                                   \
+            Y(k_rk4_step4_y3, TXE_, NW_, false);                                                       \
+        else if (B.p[5] != nullptr)                                                                    \
+            Y(k_rk4_step4, TXE_, NW_, true);                                                           \
         else                                                                                           \
-            Y(TXE_, NW_, false);                                                                       \
+            Y(k_rk4_step4, TXE_, NW_, false);                                                          \
         return hipGetLastError();                                                                      \
     }
     X(32, 8) X(64, 16) X(32, 16)

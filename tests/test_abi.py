@@ -79,6 +79,13 @@ def test_entry_points_reject_null_context():
     assert L.s4_fill_ghosts_periodic(None, arr, 1, p, None) == S.S4_EINVAL
     assert L.s4_rk4(None, arr, 1, p, p, None, 0.1, 1, 0, None, 0, None) == S.S4_EINVAL
     assert L.s4_rk4_adjoint_step(None, arr, None, None, None, 0.1, None, None, None, None, 0, None) == S.S4_EINVAL
+    assert L.s4_rk4_step_to_y3(None, arr, p, p, None, 0.1, p, p, p, p, p, 1 << 20, None) == S.S4_EINVAL
+    assert L.s4_rk4_step_to_y3(None, arr, p, p, None, 0.1, p, p, None, p, p, 1 << 20, None) == S.S4_EINVAL
+    assert L.s4_rk4_adjoint_step_y3(None, arr, p, p, p, p, None, 0.1, p, p, None, p, 1 << 20, None) == S.S4_EINVAL
+    # with c2_bar the stage state is required
+    assert L.s4_rk4_adjoint_step_y3(None, arr, p, p, None, None, None, 0.1, p, p, p, p, 1 << 20, None) == \
+        S.S4_EINVAL
+    assert "u3" in S.s4_last_error()
     assert L.s4_copy(None, None, None, 16, None) == S.S4_EINVAL
     assert L.s4_tune(None, S.S4_OP_RK4, arr, 1, 0, None, 0, None) == S.S4_EINVAL
     out = (ctypes.c_int * 8)()

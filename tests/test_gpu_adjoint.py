@@ -9,7 +9,7 @@ import torch
 import oracle as O
 import paper_1308_1343_amd as S
 import workload as W
-from _gpu import host, inner, rel
+from _gpu import dev, ghosts_untouched, host, inner, rel
 from paper_1308_1343_amd.autograd import wave_rk4
 
 pytestmark = pytest.mark.gpu
@@ -116,6 +116,83 @@ def test_step_adjoint_identity(ctx):
     lhs = ip(Mv[0], w[0]) + ip(Mv[1], w[1])
     rhs = ip(v[0], lam[0]) + ip(v[1], lam[1])
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs) * 10
+
+
+def third_stage_state(un, rn, c2n, g, dx, dt):
+    """y_3 = y_n + dt/2 k_2 of classical RK4, from the oracle's periodic ghost
+    fill and wave RHS (interior points)."""
+    u = O.fill_ghosts_periodic(un.copy(), g)
+    k1 = O.wave_rhs(u, g, dx, c2n)
+    u2 = O.fill_ghosts_periodic(un + dt / 2 * rn, g)
+    r2 = rn + dt / 2 * k1
+    k2 = O.wave_rhs(u2, g, dx, c2n)
+    return un + dt / 2 * r2, rn + dt / 2 * k2
+
+
+@pytest.mark.parametrize("n,hasc2", [((37, 29, 23), True), ((20, 18, 16), False)])
+def test_step_to_y3_every_kernel_set(ctx, n, hasc2):
+    """s4_rk4_step_to_y3 on every RK4 candidate: the step bit for bit that of
+    s4_rk4_step_to, y_3 bit for bit the same on every kernel set, within
+    1e-12 of the oracle's third stage state, and ghosts left alone."""
+    g = 2
+    nn = n[::-1]
+    dx = tuple(1.0 / v for v in n)
+    dt = 0.25 * min(dx)
+    un, rn = (O.embed(W.uniform_pm1(5, s, nn), g) for s in (1, 2))
+    c2n = O.embed(1.0 + 0.5 * W.uniform_pm1(5, 3, nn), g, 1.0) if hasc2 else None
+    eu, er = third_stage_state(un, rn, c2n, g, dx, dt)
+    u, r = dev(un, g), dev(rn, g)
+    c2 = dev(c2n, g, ghost_value=1.0) if hasc2 else None
+    b = S.box_of(u, g, dx)
+    nc = S.s4_get_choice(ctx, S.S4_OP_RK4, b)["ncandidates"]
+    first = None
+    try:
+        for c in range(nc):
+            S.s4_set_choice(ctx, S.S4_OP_RK4, b, c)
+            yu, yr, zu, zr, u3, r3 = (S.alloc_field(n, g, fill=float("nan")) for _ in range(6))
+            S.s4_rk4_step_to(ctx, b, u, r, c2, dt, yu, yr)
+            S.s4_rk4_step_to_y3(ctx, b, u, r, c2, dt, zu, zr, u3, r3)
+            got = [host(t) for t in (yu, yr, zu, zr, u3, r3)]
+            for a, e in ((got[2], got[0]), (got[3], got[1])):
+                assert np.array_equal(inner(a, g), inner(e, g)), c
+            if first is None:
+                first = got[4:]
+                assert rel(got[4], eu, g) <= 1e-12
+                assert rel(got[5], er, g) <= 1e-12
+            else:
+                assert np.array_equal(inner(got[4], g), inner(first[0], g)), c
+                assert np.array_equal(inner(got[5], g), inner(first[1], g)), c
+            assert all(ghosts_untouched(a, g) for a in got), c
+    finally:
+        S.s4_set_choice(ctx, S.S4_OP_RK4, b, -1)
+
+
+def test_adjoint_step_y3_matches(ctx):
+    """The backward step given y_3 from s4_rk4_step_to_y3 equals the one that
+    forms y_3 itself, bit for bit (with and without c2_bar)."""
+    n, g = (26, 21, 19), 2
+    nn = n[::-1]
+    dx = tuple(1.0 / v for v in n)
+    dt = 0.25 * min(dx)
+    un, rn, lu, lr = (O.embed(W.uniform_pm1(6, s, nn), g) for s in (1, 2, 3, 4))
+    c2n = O.embed(1.0 + 0.5 * W.uniform_pm1(6, 5, nn), g, 1.0)
+    u, r, c2 = dev(un, g), dev(rn, g), dev(c2n, g, ghost_value=1.0)
+    b = S.box_of(u, g, dx)
+    yu, yr, u3, r3 = (S.alloc_field(n, g, fill=float("nan")) for _ in range(4))
+    S.s4_rk4_step_to_y3(ctx, b, u, r, c2, dt, yu, yr, u3, r3)
+    for with_bar in (True, False):
+        outs = []
+        for y3 in (False, True):
+            la, lb = dev(lu, g), dev(lr, g)
+            cb = dev(0.5 * un, g) if with_bar else None
+            if y3:
+                S.s4_rk4_adjoint_step_y3(ctx, b, u, r, u3 if with_bar else None, r3 if with_bar else None, c2, dt,
+                                         la, lb, cb)
+            else:
+                S.s4_rk4_adjoint_step(ctx, b, u, r, c2, dt, la, lb, cb)
+            outs.append([host(t) for t in (la, lb) + ((cb,) if with_bar else ())])
+        for a, e in zip(outs[1], outs[0]):
+            assert np.array_equal(inner(a, g), inner(e, g)), with_bar
 
 
 def test_adjoint128_full_size(ctx):
