@@ -294,6 +294,9 @@ struct s4_ctx {
     int device = 0;
     int ncu = 256;
     int nxcd = 8;
+    // resident workgroups per CU of the whole-step shapes 32 x 16, 64 x 16
+    // and 32 x 32 lanes (LDS-bound; queried from the device at creation)
+    int step4_per[3] = {2, 1, 1};
     std::string name;
     std::string cache_path;
     hipStream_t cap = nullptr; // private stream used only to capture graphs
@@ -373,19 +376,73 @@ static int tile_heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
 // 32 x 16; the longest z chunk that gives every CU four items (eight over
 // several boxes, whose uneven sizes the work queue balances best in small
 // pieces).
+// Whole-step setting for one periodic box, by a cost model of the two work
+// orders.  z chunks: rounds of resident workgroups times the planes one item
+// streams (its chunk plus the 8-plane start-up of the pipeline).  Equal runs
+// (tz 0): the planes of the busiest run plus 8 for every tile column it
+// touches, in one round.  Each shape and order has its own cost per plane,
+// measured on whole-step runs over periodic cubes of side 128 to 512
+// (relative to 32 x 16 lanes in z chunks): equal runs lose L2 locality, and a
+// 1024-lane workgroup alone on its CU hides less latency per lane.
+static int step4_single(const s4_ctx *ctx, const s4_box &b)
+{
+    struct Opt {
+        int tx, nw, tz, shape;
+        double per_plane;
+    };
+    static const Opt opts[] = {{32, 8, 32, 0, 1.0},    {32, 8, 0, 0, 1.184},    {64, 16, 128, 1, 1.006},
+                               {64, 16, 64, 1, 1.006}, {64, 16, 0, 1, 1.110}, {32, 16, 0, 2, 1.270}};
+    int best = cand_index(32, 8, 32, 4);
+    {
+        // too few tile-planes to give every resident 512-lane workgroup 8
+        // planes: equal 8-plane runs on that shape (a larger workgroup would
+        // sit alone on its CU with twice the lanes per plane)
+        const Cand &c = cands()[cand_index(32, 8, 0, 4)];
+        const int64_t tiles = (int64_t)((b.n[0] + out_tx(c) - 1) / out_tx(c)) * ((b.n[1] + out_ty(c) - 1) / out_ty(c));
+        if (cand_fits(c, &b, 1) && tiles * b.n[2] <= 8 * (int64_t)std::max(1, ctx->step4_per[0]) * ctx->ncu)
+            return cand_index(32, 8, 0, 4);
+    }
+    double best_cost = 1e300;
+    for (const Opt &o : opts) {
+        const int ci = cand_index(o.tx, o.nw, o.tz, 4);
+        const Cand &c = cands()[ci];
+        if (!cand_fits(c, &b, 1))
+            continue;
+        const int64_t slots = (int64_t)std::max(1, ctx->step4_per[o.shape]) * ctx->ncu;
+        const int64_t nz = b.n[2];
+        const int64_t tiles = (int64_t)((b.n[0] + out_tx(c) - 1) / out_tx(c)) * ((b.n[1] + out_ty(c) - 1) / out_ty(c));
+        double planes;
+        if (o.tz > 0) {
+            const int64_t tz = std::min<int64_t>(o.tz, nz);
+            const int64_t items = tiles * ((nz + tz - 1) / tz);
+            planes = (double)((items + slots - 1) / slots) * (double)(tz + 8);
+        } else {
+            // the runs step4_run hands out: R planes each (the last one shorter)
+            const int64_t total = tiles * nz;
+            const int64_t R = std::max<int64_t>(8, (total + slots - 1) / slots);
+            int64_t worst = 0;
+            for (int64_t s0 = 0; s0 < total; s0 += R) {
+                const int64_t e = std::min(total, s0 + R);
+                worst = std::max(worst, (e - s0) + 8 * ((e - 1) / nz - s0 / nz + 1));
+            }
+            planes = (double)worst;
+        }
+        const double cost = planes * o.per_plane;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = ci;
+        }
+    }
+    return best;
+}
+
 static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool level = false)
 {
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
     const int whole = cand_index(32, 8, 32, 4);
-    if (!level && cand_fits(cands()[whole], b, nbox)) {
-        // one box with fewer than two rounds of 32-plane items (two 512-lane
-        // workgroups per CU): equal runs of its tile-plane sequence instead,
-        // so every resident workgroup has planes and runs pay one start-up
-        if (nbox == 1 && items_of(b[0], cands()[whole]) < 4 * (int64_t)ctx->ncu)
-            return cand_index(32, 8, 0, 4);
-        return whole;
-    }
+    if (!level && cand_fits(cands()[whole], b, nbox))
+        return nbox == 1 ? step4_single(ctx, b[0]) : whole;
     double pts = 0, lanes = 0;
     for (int i = 0; i < nbox; ++i) {
         pts += (double)b[i].n[0] * b[i].n[1] * b[i].n[2];
@@ -887,6 +944,14 @@ int s4_create(int device, s4_ctx **out)
         size_t cut = c->name.find(':');
         if (cut != std::string::npos)
             c->name = c->name.substr(0, cut);
+    }
+    {
+        const int shapes[3][2] = {{32, 8}, {64, 16}, {32, 16}};
+        for (int k = 0; k < 3; ++k) {
+            const int per = max_blocks_step4(shapes[k][0], shapes[k][1]);
+            if (per > 0)
+                c->step4_per[k] = per;
+        }
     }
     int nx = 0;
     if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, device) == hipSuccess && nx > 0)

@@ -1,6 +1,7 @@
 """Full-size workloads, in the launch configuration the benchmark times:
 256^3 wave RK4 for all 100 steps against the oracle, the pure-mode closed
-form at 256^3, and the 60-box bboxset steps in all three launch modes."""
+form at 256^3, the 60-box bboxset steps in all three launch modes, and
+large single cubes in their untuned setting."""
 import math
 
 import numpy as np
@@ -111,3 +112,22 @@ def test_bboxset60_step_all_modes_vs_oracle(ctx, nsteps):
         ri = wr[g:-g, g:-g, g:-g]
         assert np.max(np.abs(res["graph"][0][i] - wi)) <= 1e-12 * np.max(np.abs(wi))
         assert np.max(np.abs(res["graph"][1][i] - ri)) <= 1e-12 * np.max(np.abs(ri))
+
+
+@pytest.mark.parametrize("n,shape", [(224, (32, 32)), (320, (64, 16))])
+def test_large_cubes_default_setting_vs_oracle(n, shape):
+    """Two steps on single periodic cubes whose untuned whole-step setting is a
+    1024-lane shape (28 x 28 output tiles dividing 224^3 exactly; 60 x 12
+    tiles in equal runs at 320^3), against the oracle."""
+    fresh = S.Context(0)
+    g, nn = 2, (n, n, n)
+    u0, r0 = W.uniform_pm1(7, 1, nn), W.uniform_pm1(7, 2, nn)
+    u, r = to_dev(u0, nn, g), to_dev(r0, nn, g)
+    b = S.box_of(u, g, 1.0 / n)
+    ch = S.s4_get_choice(fresh, S.S4_OP_RK4, b)
+    assert ch["kernel_op"] == 102 and (ch["tile_x"], ch["tile_y"]) == shape, ch
+    dt = 0.25 / n
+    S.s4_rk4(fresh, b, [u], [r], None, dt, 2, "graph")
+    wu, wr = O.rk4(O.embed(u0, g), O.embed(r0, g), g, (1.0 / n,) * 3, dt, 2)
+    assert rel(host(u), wu, g) <= 1e-12
+    assert rel(host(r), wr, g) <= 1e-12
