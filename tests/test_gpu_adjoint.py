@@ -211,3 +211,29 @@ def test_adjoint128_full_size(ctx):
     assert rel(host(u0.grad), gu, g) <= 1e-12
     assert rel(host(r0.grad), gr, g) <= 1e-12
     assert rel(host(c2.grad), gc, g) <= 1e-12
+
+
+def test_step_to_y3_under_online_tuning():
+    """With on-line tuning active, s4_rk4_step_to trials other settings while
+    s4_rk4_step_to_y3 runs the best so far; every call gives the same step and
+    the same y_3, bit for bit."""
+    n, g = (30, 26, 22), 2
+    nn = n[::-1]
+    dx = tuple(1.0 / v for v in n)
+    dt = 0.25 * min(dx)
+    fresh = S.Context(0)
+    S.s4_set_online_tuning(fresh, True, 0.3, 5)
+    un, rn = (O.embed(W.uniform_pm1(8, s, nn), g) for s in (1, 2))
+    u, r = dev(un, g), dev(rn, g)
+    b = S.box_of(u, g, dx)
+    ref = None
+    for _ in range(12):
+        yu, yr, zu, zr, u3, r3 = (S.alloc_field(n, g, fill=float("nan")) for _ in range(6))
+        S.s4_rk4_step_to(fresh, b, u, r, None, dt, yu, yr)
+        S.s4_rk4_step_to_y3(fresh, b, u, r, None, dt, zu, zr, u3, r3)
+        got = [inner(host(t), g) for t in (yu, yr, zu, zr, u3, r3)]
+        if ref is None:
+            ref = got
+        for a, e in zip(got, ref):
+            assert np.array_equal(a, e)
+        assert np.array_equal(got[0], got[2]) and np.array_equal(got[1], got[3])
