@@ -59,6 +59,17 @@ __device__ __forceinline__ void st_or_drop(double *base, unsigned nbytes, unsign
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(s4_u32x2, v), r, off, 0, 2 /* nt */);
 }
 
+// load through a buffer resource over one z plane of nbytes at base (an
+// address uniform over the workgroup): the byte offset stays a 32-bit lane
+// value across planes (AUX: cache policy bits, 2 = non-temporal)
+template <int AUX>
+__device__ __forceinline__ double ld_plane(const double *base, unsigned nbytes, unsigned off)
+{
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), 0, (int)nbytes, 0x00020000);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+
 __device__ __forceinline__ void st(double *p, double v)
 {
     __builtin_nontemporal_store(v, p);
@@ -692,24 +703,41 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     const int nt = P.z1 - P.z0 + 8, tz = P.z1 - P.z0;
     const int nz = B.n[2];
     int kz = readable(P.z0 - 4, nz, true, false); // wrapped index of the plane fetched next
-    double nu, nr, nc = 1.0, hu[T::HS], hr[T::HS];
-    auto fetch = [&]() {
+    // The loads of a plane are issued PD steps before it is taken: PD = 2
+    // where the registers allow (without the c^2 queue), from two buffers
+    // used by alternate steps, so that no register a load is still filling
+    // is ever copied (a copy would wait for the load).  Plane loads go
+    // through buffer resources: one 32-bit lane offset serves every plane.
+    constexpr int PD = HASC2 ? 1 : 2;
+    struct Fetched {
+        double u, r, c, hu[T::HS], hr[T::HS];
+    };
+    Fetched F0, F1;
+    F0.c = F1.c = 1.0;
+    // byte offsets within a plane of the lane's column and halo slots
+    const unsigned col8 = (unsigned)w.col * 8u;
+    unsigned h8[T::HS];
+#pragma unroll
+    for (int s = 0; s < T::HS; ++s)
+        h8[s] = (unsigned)w.hcol[s] * 8u;
+    auto fetch = [&](Fetched &F) {
         const int64_t zo = (int64_t)(kz + w.g) * w.sz;
-        nu = uf[w.col + zo];
-        nr = rf[w.col + zo];
+        const double *pu = uf + zo, *pr = rf + zo;
+        F.u = ld_plane<0>(pu, plane_bytes, col8);
+        F.r = ld_plane<0>(pr, plane_bytes, col8);
         if (HASC2) // per box in a batched launch: no c^2 reads as 1, an exact factor
-            nc = c2 ? ldp(c2 + w.col + zo) : 1.0;
+            F.c = c2 ? ld_plane<2>(c2 + zo, plane_bytes, col8) : 1.0;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
-            if (w.hl[s] >= 0) {
-                hu[s] = uf[w.hcol[s] + zo];
-                hr[s] = rf[w.hcol[s] + zo];
+            if (w.hl[s] >= 0) { // whole wavefronts without halo points skip these
+                F.hu[s] = ld_plane<0>(pu, plane_bytes, h8[s]);
+                F.hr[s] = ld_plane<0>(pr, plane_bytes, h8[s]);
             }
         kz = kz + 1 == nz ? 0 : kz + 1;
     };
-    fetch();
-    for (int t = 0; t < nt; ++t) {
+    auto step = [&](const int t, Fetched &F) {
         const int k = t & 3;
+        const double nu = F.u, nr = F.r, nc = F.c;
         qa0 = qa1; qa1 = qa2; qa2 = qa3; qa3 = qa4; qa4 = nu;
         qr0 = qr1; qr1 = qr2; qr2 = qr3; qr3 = qr4; qr4 = nr;
         if (HASC2) {
@@ -721,13 +749,14 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0) {
-                R1[w.hl[s]] = hu[s];
-                R1[P1 + w.hl[s]] = fma(a1, hr[s], hu[s]);
+                R1[w.hl[s]] = F.hu[s];
+                R1[P1 + w.hl[s]] = fma(a1, F.hr[s], F.hu[s]);
             }
-        // the next plane's loads fly across the barrier (their registers
-        // were consumed just above), as do the stores of the last plane
-        if (t + 1 < nt)
-            fetch();
+        // the loads of the plane taken PD steps on fly across the barrier
+        // (this buffer's registers were consumed just above), as do the
+        // stores of the last plane
+        if (t + PD < nt)
+            fetch(F);
         lds_barrier();
         if (t >= 4) {
             // phase A (stages 1 and 2) at plane f - 2, every lane
@@ -796,13 +825,26 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             dr2 = dr1;
             dr1 = dr0;
         }
+    };
+    fetch(F0);
+    if constexpr (PD == 2) {
+        if (nt > 1)
+            fetch(F1);
+        for (int t = 0; t < nt; t += 2) {
+            step(t, F0);
+            if (t + 1 < nt)
+                step(t + 1, F1);
+        }
+    } else {
+        for (int t = 0; t < nt; ++t)
+            step(t, F0);
     }
 }
 
 // persistent form over the per-XCD work queue of a table of periodic boxes
 // (items: box, tile, z chunk of B.tz planes), as k_tiles_batched
 template <int TXE, int NW, bool HASC2>
-__global__ __launch_bounds__(NW * 64) void k_rk4_step4_batched(const DevBox *__restrict__ tab, int nbox,
+__global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_batched(const DevBox *__restrict__ tab, int nbox,
                                                                ItemQueue Q, Step4Coef K)
 {
     __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
@@ -848,8 +890,10 @@ __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, 
     }
 }
 
+// (the launch bound asks for four wavefronts per SIMD: two 512-lane or one
+// 1024-lane workgroup per CU, as many as the LDS rings allow)
 template <int TXE, int NW, bool HASC2>
-__global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
+__global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
 {
     __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
     step4_grid<TXE, NW, HASC2, false>(B, K, run, nxcd, lds);
@@ -857,7 +901,7 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_step4(DevBox B, Step4Coef K, in
 
 // the same step, also storing the third stage state (u_3, rho_3)
 template <int TXE, int NW, bool HASC2>
-__global__ __launch_bounds__(NW * 64) void k_rk4_step4_y3(DevBox B, Step4Coef K, int run, int nxcd)
+__global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_y3(DevBox B, Step4Coef K, int run, int nxcd)
 {
     __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
     step4_grid<TXE, NW, HASC2, true>(B, K, run, nxcd, lds);
