@@ -949,20 +949,13 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
     // stencil fields: pair 0: u_n, rho_n; pair 1: u_3, rho_3, u_n
     const double *F[3] = {B.in, B.p[0], B.p[1]};
 
-    double q[NF][5], hv[NF][T::HS];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-#pragma unroll
-        for (int d = 0; d < 5; ++d)
-            q[f][d] = F[f][w.col + w.zoff(P.z0 - 2 + d)];
-        const int64_t zo = w.zoff(P.z0);
-#pragma unroll
-        for (int s = 0; s < T::HS; ++s)
-            if (w.hl[s] >= 0)
-                hv[f][s] = F[f][w.hcol[s] + zo];
-    }
-    // pointwise streams at the point: c^2; pair 1 also rho_n, acc_u, acc_rho
-    double pw[4] = {1.0, 0.0, 0.0, 0.0}, pwn[4] = {1.0, 0.0, 0.0, 0.0};
+    // The loads of plane k (halo, pointwise streams) and of the column's
+    // plane k+2 are issued two steps before step k, into one of two buffers
+    // used by alternate steps, so no register a load is still filling is
+    // copied.
+    struct Fetched {
+        double q4[NF], hv[NF][T::HS], pw[4];
+    };
     auto load_pw = [&](int k, double *v) {
         const int64_t c = w.point(B, k);
         if (hasc2)
@@ -973,39 +966,57 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
             v[3] = ldp(B.p[4] + c);
         }
     };
-    if (w.active)
-        load_pw(P.z0, pw);
-    int buf = 0;
-    for (int k = P.z0; k < P.z1; ++k) {
-        double *L = lds + buf * NF * PLANE;
+    auto fetch = [&](int k, Fetched &X) {
+        const int64_t z2 = w.zoff(k + 2), z0 = w.zoff(k);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
+            X.q4[f] = F[f][w.col + z2];
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (w.hl[s] >= 0)
+                    X.hv[f][s] = F[f][w.hcol[s] + z0];
+        }
+        if (w.active)
+            load_pw(k, X.pw);
+    };
+    // the column's planes k-2 .. k+2 at step k (q[f][4] arrives with the step)
+    double q[NF][5];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int d = 1; d < 5; ++d)
+            q[f][d] = F[f][w.col + w.zoff(P.z0 - 3 + d)];
+    Fetched F0, F1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        F0.pw[v] = F1.pw[v] = v == 0 ? 1.0 : 0.0;
+    auto step = [&](const int k, Fetched &X) {
+        double *L = lds + ((k - P.z0) & 1) * NF * PLANE;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            q[f][0] = q[f][1];
+            q[f][1] = q[f][2];
+            q[f][2] = q[f][3];
+            q[f][3] = q[f][4];
+            q[f][4] = X.q4[f];
             L[f * PLANE + lc] = q[f][2];
 #pragma unroll
             for (int s = 0; s < T::HS; ++s)
                 if (w.hl[s] >= 0)
-                    L[f * PLANE + w.hl[s]] = hv[f][s];
+                    L[f * PLANE + w.hl[s]] = X.hv[f][s];
         }
+        double pwc[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            pwc[v] = X.pw[v];
+        if (k + 2 < P.z1)
+            fetch(k + 2, X);
         lds_barrier();
-        double q4n[NF], hvn[NF][T::HS];
-        if (k + 1 < P.z1) {
-            const int64_t z3 = w.zoff(k + 3), z1 = w.zoff(k + 1);
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                q4n[f] = F[f][w.col + z3];
-#pragma unroll
-                for (int s = 0; s < T::HS; ++s)
-                    if (w.hl[s] >= 0)
-                        hvn[f][s] = F[f][w.hcol[s] + z1];
-            }
-            if (w.active)
-                load_pw(k + 1, pwn);
-        }
         if (w.active) {
             const double *L0 = L, *L1 = L + PLANE;
             const double a1 = K1.a, a2 = K2.a;
             const int X1 = 1, X2 = 2, Y1 = T::LX, Y2 = 2 * T::LX;
-            const double c2 = pw[0];
+            const double c2 = pwc[0];
             if constexpr (PAIR == 0) {
                 // stage 1: L u_n
                 const double un = q[0][2], rn = q[1][2];
@@ -1031,7 +1042,7 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
                 const double *L2 = L + 2 * PLANE;
                 // stage 3: L u_3
                 const double u3 = q[0][2], r3 = q[1][2], un = q[2][2];
-                const double rn = pw[1], au = pw[2], ar = pw[3];
+                const double rn = pwc[1], au = pwc[2], ar = pwc[3];
                 const double lap3 = lap4(B, u3, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
                                          L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
                 const double kr3 = c2 * lap3;
@@ -1050,27 +1061,20 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
                 st(B.q[1] + c, fma(K2.b, kr4, ar4));
             }
         }
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            q[f][0] = q[f][1];
-            q[f][1] = q[f][2];
-            q[f][2] = q[f][3];
-            q[f][3] = q[f][4];
-            q[f][4] = q4n[f];
-#pragma unroll
-            for (int s = 0; s < T::HS; ++s)
-                hv[f][s] = hvn[f][s];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            pw[v] = pwn[v];
-        buf ^= 1;
+    };
+    fetch(P.z0, F0);
+    if (P.z0 + 1 < P.z1)
+        fetch(P.z0 + 1, F1);
+    for (int k = P.z0; k < P.z1; k += 2) {
+        step(k, F0);
+        if (k + 1 < P.z1)
+            step(k + 1, F1);
     }
 }
 
 
 template <int TX, int NW, int PAIR, bool WRAP>
-__global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
+__global__ __launch_bounds__(NW * 64, 4) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
 {
     __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
     const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
@@ -1080,7 +1084,7 @@ __global__ __launch_bounds__(NW * 64) void k_pair2(DevBox B, StageCoef K1, Stage
 
 // persistent form over the per-XCD work queue, as k_tiles_batched
 template <int TX, int NW, int PAIR, bool WRAP>
-__global__ __launch_bounds__(NW * 64) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
+__global__ __launch_bounds__(NW * 64, 4) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
                                                           StageCoef K1, StageCoef K2)
 {
     __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
