@@ -155,9 +155,11 @@ __device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, in
 
 // ---------------------------------------------------------------------------
 // one work item: an xy tile marched over its z chunk.  Software pipelined:
-// right after the barrier of plane k the loads of plane k+1 (the column's
-// next z value, the halo, the pointwise streams) are issued, so they are in
-// flight while plane k is computed and stored.
+// the loads step k needs (its halo and pointwise streams, the column's plane
+// k+2) are issued PD steps ahead, right after a barrier, into one of PD
+// buffers used by alternate steps, so no register a load is still filling is
+// copied.  PD = 2 for the one-input ops (RHS, adjoint RHS); 1 for the RK4
+// stages, whose six pointwise streams would cost occupancy.
 
 template <int TX, int NW, bool WRAP, int OPK>
 __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, const StageCoef &K,
@@ -165,6 +167,7 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
 {
     using T = Tile<TX, NW>;
     constexpr int PLANE = T::LY * T::LX;
+    constexpr int PD = OPK == OP_STAGE ? 1 : 2;
     const Walker<TX, NW, WRAP> w(B, P, threadIdx.x);
     const int lc = w.lc;
     const double *in = B.in;
@@ -172,60 +175,60 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
 
     // input transform: mul * in (mul optional)
     auto ldw = [&](int64_t e) -> double { return mul ? mul[e] * in[e] : in[e]; };
-
-    double q0 = ldw(w.col + w.zoff(P.z0 - 2));
-    double q1 = ldw(w.col + w.zoff(P.z0 - 1));
-    double q2 = ldw(w.col + w.zoff(P.z0));
-    double q3 = ldw(w.col + w.zoff(P.z0 + 1));
-    double q4 = ldw(w.col + w.zoff(P.z0 + 2));
-    double hv[T::HS];
-    {
-        const int64_t zo = w.zoff(P.z0);
+    struct Fetched {
+        double q4, hv[T::HS];
+        PW pw;
+    };
+    auto fetch = [&](int k, Fetched &X) {
+        X.q4 = ldw(w.col + w.zoff(k + 2));
+        const int64_t zo = w.zoff(k);
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
-                hv[s] = ldw(w.hcol[s] + zo);
-    }
-    PW pw;
-    if (w.active)
-        pw_load<OPK>(B, K, w.point(B, P.z0), pw);
-    int buf = 0;
-    for (int k = P.z0; k < P.z1; ++k) {
-        double *L = lds + buf * PLANE;
+                X.hv[s] = ldw(w.hcol[s] + zo);
+        if (w.active)
+            pw_load<OPK>(B, K, w.point(B, k), X.pw);
+    };
+    // the column's planes k-2 .. k+2 at step k (q4 arrives with the step)
+    double q0 = 0.0, q1 = ldw(w.col + w.zoff(P.z0 - 2)), q2 = ldw(w.col + w.zoff(P.z0 - 1)),
+           q3 = ldw(w.col + w.zoff(P.z0)), q4 = ldw(w.col + w.zoff(P.z0 + 1));
+    auto step = [&](const int k, Fetched &X) {
+        q0 = q1;
+        q1 = q2;
+        q2 = q3;
+        q3 = q4;
+        q4 = X.q4;
+        double *L = lds + ((k - P.z0) & 1) * PLANE;
         L[lc] = q2;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (w.hl[s] >= 0)
-                L[w.hl[s]] = hv[s];
+                L[w.hl[s]] = X.hv[s];
+        const PW pw = X.pw;
+        if (k + PD < P.z1)
+            fetch(k + PD, X);
         lds_barrier();
-        double q4n = 0.0, hvn[T::HS];
-        PW pwn;
-        if (k + 1 < P.z1) {
-            q4n = ldw(w.col + w.zoff(k + 3));
-            const int64_t zo = w.zoff(k + 1);
-#pragma unroll
-            for (int s = 0; s < T::HS; ++s)
-                if (w.hl[s] >= 0)
-                    hvn[s] = ldw(w.hcol[s] + zo);
-            if (w.active)
-                pw_load<OPK>(B, K, w.point(B, k + 1), pwn);
-        }
         if (w.active) {
             const double lap = lap4(B, q2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2],
                                     L[lc - 2 * T::LX], L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX],
                                     q0, q1, q3, q4);
             pw_apply<OPK>(B, K, w.point(B, k), q2, lap, pw);
         }
-        q0 = q1;
-        q1 = q2;
-        q2 = q3;
-        q3 = q4;
-        q4 = q4n;
-#pragma unroll
-        for (int s = 0; s < T::HS; ++s)
-            hv[s] = hvn[s];
-        pw = pwn;
-        buf ^= 1;
+    };
+    Fetched F0, F1;
+    fetch(P.z0, F0);
+    if constexpr (PD == 2) {
+        if (P.z0 + 1 < P.z1)
+            fetch(P.z0 + 1, F1);
+        for (int k = P.z0; k < P.z1; k += 2) {
+            step(k, F0);
+            if (k + 1 < P.z1)
+                step(k + 1, F1);
+        }
+    } else {
+        (void)F1;
+        for (int k = P.z0; k < P.z1; ++k)
+            step(k, F0);
     }
 }
 
