@@ -365,12 +365,12 @@ static int tile_heuristic(const s4_ctx *ctx, const s4_box *b, int nbox)
     return cand_index(tx, nw, 8);
 }
 
-// Starting setting of an op.  RK4 runs a whole step per pass (variant 4)
-// on 32 x 16 lanes (two workgroups per CU) in 32-plane chunks, the setting
-// the sweep picks on one 256^3 box and on sets of small boxes alike (equal
-// runs per workgroup on one box too small to fill two rounds).  On a
-// level (level: radius-2 ghost zones only), and for z planes of 2 GiB or
-// more, RK4 runs two stages per pass with
+// Starting setting of an op.  RK4 runs a whole step per pass (variant 4):
+// on one box the setting of least modelled cost (step4_single), on a set of
+// boxes 32 x 16 lanes (two workgroups per CU) in 32-plane chunks, the
+// sweep's pick on the 60-box set.  On a level (level: radius-2 ghost zones
+// only), and for z planes of 2 GiB or more, RK4 runs two stages per pass
+// with
 // the per-tap stage pairs (variant 3): tile 64 x 4 (whole 512-byte rows)
 // unless idle lanes of ragged boxes would pass a fifth of the lanes, then
 // 32 x 16; the longest z chunk that gives every CU four items (eight over
@@ -436,8 +436,25 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
     return best;
 }
 
+// Multi-field kernel: workgroups of 32 x 8 lanes (four wavefronts; the
+// kernel's two barriers per plane favour many small workgroups per CU) and
+// the longest z chunk that gives every CU one item per field.  A launch
+// covers several fields (each a range of items of its own), so that is
+// several items per CU, of long chunks that pay the 4-plane start-up
+// rarely.
+static int mixed_heuristic(const s4_ctx *ctx, const s4_box &b)
+{
+    const int tx = b.n[0] >= 24 ? 32 : 16, nw = 4;
+    for (int tz : {0, 64, 32, 16})
+        if (items_of(b, {tx, nw, tz, 0, 0}) >= (int64_t)ctx->ncu)
+            return cand_index(tx, nw, tz);
+    return cand_index(tx, nw, 8);
+}
+
 static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool level = false)
 {
+    if (op == S4_OP_DERIV_MIXED)
+        return mixed_heuristic(ctx, b[0]);
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
     const int whole = cand_index(32, 8, 32, 4);

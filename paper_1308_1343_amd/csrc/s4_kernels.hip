@@ -167,7 +167,7 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
 {
     using T = Tile<TX, NW>;
     constexpr int PLANE = T::LY * T::LX;
-    constexpr int PD = OPK == OP_STAGE ? 1 : 2;
+    constexpr int PD = OPK == OP_STAGE ? 1 : 3;
     const Walker<TX, NW, WRAP> w(B, P, threadIdx.x);
     const int lc = w.lc;
     const double *in = B.in;
@@ -215,18 +215,23 @@ __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, cons
             pw_apply<OPK>(B, K, w.point(B, k), q2, lap, pw);
         }
     };
-    Fetched F0, F1;
+    Fetched F0, F1, F2;
     fetch(P.z0, F0);
-    if constexpr (PD == 2) {
+    if constexpr (PD == 3) {
         if (P.z0 + 1 < P.z1)
             fetch(P.z0 + 1, F1);
-        for (int k = P.z0; k < P.z1; k += 2) {
+        if (P.z0 + 2 < P.z1)
+            fetch(P.z0 + 2, F2);
+        for (int k = P.z0; k < P.z1; k += 3) {
             step(k, F0);
             if (k + 1 < P.z1)
                 step(k + 1, F1);
+            if (k + 2 < P.z1)
+                step(k + 2, F2);
         }
     } else {
         (void)F1;
+        (void)F2;
         for (int k = P.z0; k < P.z1; ++k)
             step(k, F0);
     }

@@ -369,7 +369,8 @@ def test_fused_candidates_only_for_single_box_rk4(ctx):
 def test_heuristic_kernel_sets(ctx):
     """Untuned RK4 starts on whole steps (one box or a set), and on the per-tap
     stage pairs where a z plane reaches 2 GiB (the whole-step stores address a
-    plane with 31-bit byte offsets).  Descriptors only: nothing is allocated."""
+    plane with 31-bit byte offsets); the multi-field kernel on small
+    workgroups.  Descriptors only: nothing is allocated."""
     fresh = S.Context(0)
     b = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, b)["kernel_op"] == 102
@@ -378,6 +379,10 @@ def test_heuristic_kernel_sets(ctx):
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, big)["kernel_op"] == 101
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, big])["kernel_op"] == 101
     assert S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, b)["kernel_op"] == 0
+    # the multi-field kernel: 32 x 8 lanes, the longest z chunk giving each CU one item per field
+    m = S.make_box((192, 192, 192), 2, (1, 208, 208 * 196), 1 / 192)
+    ch = S.s4_get_choice(fresh, S.S4_OP_DERIV_MIXED, m)
+    assert (ch["tile_x"], ch["tile_y"], ch["z_chunk"]) == (32, 8, 64), ch
 
 
 def test_errors_on_device_calls(ctx):
