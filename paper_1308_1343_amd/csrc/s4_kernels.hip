@@ -157,9 +157,9 @@ __device__ __forceinline__ void pw_apply(const DevBox &B, const StageCoef &K, in
 // one work item: an xy tile marched over its z chunk.  Software pipelined:
 // the loads step k needs (its halo and pointwise streams, the column's plane
 // k+2) are issued PD steps ahead, right after a barrier, into one of PD
-// buffers used by alternate steps, so no register a load is still filling is
-// copied.  PD = 2 for the one-input ops (RHS, adjoint RHS); 1 for the RK4
-// stages, whose six pointwise streams would cost occupancy.
+// buffers used in turn, so no register a load is still filling is copied.
+// PD = 3 for the one-input ops (RHS, adjoint RHS); 1 for the RK4 stages,
+// whose six pointwise streams would cost occupancy.
 
 template <int TX, int NW, bool WRAP, int OPK>
 __device__ __forceinline__ void run_item(const DevBox &B, const ItemPos &P, const StageCoef &K,
