@@ -663,8 +663,9 @@ struct Step4Coef {
     double a1, a2, b2, a3, b3, b4;
 };
 
-// one tile and z range of a whole step
-template <int TXE, int NW, bool HASC2, bool Y3>
+// one tile and z range of a whole step (C2PD2: with c^2, load two planes
+// ahead too where the workgroup has 1024 lanes)
+template <int TXE, int NW, bool HASC2, bool Y3, bool C2PD2 = false>
 __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, const Step4Coef &K, double *lds)
 {
     using T = Tile<TXE, NW>;
@@ -711,12 +712,16 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     const int nt = P.z1 - P.z0 + 8, tz = P.z1 - P.z0;
     const int nz = B.n[2];
     int kz = readable(P.z0 - 4, nz, true, false); // wrapped index of the plane fetched next
-    // The loads of a plane are issued PD steps before it is taken: PD = 2
-    // where the registers allow (without the c^2 queue), from two buffers
-    // used by alternate steps, so that no register a load is still filling
-    // is ever copied (a copy would wait for the load).  Plane loads go
+    // The loads of a plane are issued PD steps before it is taken: PD = 2,
+    // from two buffers used by alternate steps, so that no register a load
+    // is still filling is ever copied (a copy would wait for the load).
+    // With the c^2 queue on 512-lane workgroups the second buffer would
+    // cost a wavefront per SIMD (about 139 VGPRs), so those load one plane
+    // ahead; 1024-lane workgroups are held to 128 VGPRs anyway, and the
+    // plain whole-step kernel gains from it despite 7 spilled registers
+    // (C2PD2; the batched and y_3 forms would spill 17).  Plane loads go
     // through buffer resources: one 32-bit lane offset serves every plane.
-    constexpr int PD = HASC2 ? 1 : 2;
+    constexpr int PD = HASC2 && !(C2PD2 && NW * 64 == 1024) ? 1 : 2;
     struct Fetched {
         double u, r, c, hu[T::HS], hr[T::HS];
     };
@@ -885,7 +890,7 @@ __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, 
     constexpr int TYE = Tile<TXE, NW>::TY;
     const int g = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     if (run == 0) {
-        run_step4<TXE, NW, HASC2, Y3>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
+        run_step4<TXE, NW, HASC2, Y3, !Y3>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
         return;
     }
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
@@ -893,7 +898,7 @@ __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, 
     const int64_t e = s + run < total ? s + run : total;
     ItemPos P;
     while (run_piece(B, TXE - 4, TYE - 4, s, e, P)) {
-        run_step4<TXE, NW, HASC2, Y3>(B, P, K, lds);
+        run_step4<TXE, NW, HASC2, Y3, !Y3>(B, P, K, lds);
         __syncthreads(); // the next piece rewrites the LDS rings
     }
 }
