@@ -133,3 +133,37 @@ def test_whole_steps_skipped_for_huge_planes():
     assert all(CANDS[t][0] != 4 for t in tr)
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.3, ncalls=400)
     assert CANDS[tr[-1]][0] == 4
+
+
+def cube(n):
+    return S.make_box((n, n, n), 2, (1, n + 4, (n + 4) * (n + 4)), 1.0 / n)
+
+
+def start_of(op, box):
+    return CANDS[S.s4_online_simulate(op, box, [1.0] * len(CANDS), restart_prob=0.0, ncalls=1)[0]]
+
+
+def test_whole_step_start_follows_the_cost_model():
+    """The untuned whole-step setting of one periodic box (the search's start):
+    equal 8-plane runs on 32 x 16 lanes for boxes too small to fill the GPU,
+    else the shape and work order the cost model rates cheapest -- 28 x 28
+    output tiles where the box divides into them (224^3, 448^3), 60 x 12
+    tiles on most large cubes."""
+    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 0, 0), 160: (4, 32, 8, 32, 0), 192: (4, 64, 16, 0, 0),
+            224: (4, 32, 16, 0, 0), 256: (4, 64, 16, 128, 0), 384: (4, 64, 16, 0, 0), 448: (4, 32, 16, 0, 0)}
+    for n, w in want.items():
+        assert start_of(S.S4_OP_RK4, cube(n)) == w, n
+    # a set of boxes keeps 32-plane chunks on 32 x 16 lanes
+    assert CANDS[S.s4_online_simulate(S.S4_OP_RK4, [cube(64), cube(96)], [1.0] * len(CANDS), restart_prob=0.0,
+                                      ncalls=1)[0]] == (4, 32, 8, 32, 0)
+
+
+def test_mixed_kernel_start():
+    """The multi-field kernel starts on 32 x 8 lanes (16 x 16 for boxes narrower
+    than 24) with the longest z chunk giving every CU one item per field, and
+    8-plane chunks where none does."""
+    assert start_of(S.S4_OP_DERIV_MIXED, cube(192)) == (0, 32, 4, 64, 0)
+    assert start_of(S.S4_OP_DERIV_MIXED, cube(128)) == (0, 32, 4, 32, 0)
+    assert start_of(S.S4_OP_DERIV_MIXED, cube(112)) == (0, 32, 4, 16, 0)
+    assert start_of(S.S4_OP_DERIV_MIXED, cube(64)) == (0, 32, 4, 8, 0)
+    assert start_of(S.S4_OP_DERIV_MIXED, cube(20)) == (0, 16, 4, 8, 0)
