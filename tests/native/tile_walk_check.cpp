@@ -650,7 +650,8 @@ static void runs_check(int nx, int ny, int nz, int txo, int tyo, int run)
 int main()
 {
     const int RS[][6] = {{256, 256, 256, 60, 12, 110}, {256, 256, 256, 28, 12, 64}, {5, 7, 3, 60, 12, 2},
-                         {70, 9, 5, 28, 28, 1},         {1, 1, 1, 60, 4, 16},       {97, 33, 41, 60, 4, 1000}};
+                         {70, 9, 5, 28, 28, 1},         {1, 1, 1, 60, 4, 16},       {97, 33, 41, 60, 4, 1000},
+                         {32, 32, 32, 28, 12, 1},       {48, 48, 48, 28, 12, 2},    {96, 96, 96, 28, 12, 6}};
     for (auto &r : RS)
         runs_check(r[0], r[1], r[2], r[3], r[4], r[5]);
     const int QS[][3] = {{1000, 8, 64}, {7, 8, 3}, {0, 8, 4}, {1, 8, 16}, {5000, 8, 1}, {123, 1, 9}, {97, 15, 40}};
