@@ -409,7 +409,7 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
     int best = cand_index(32, 8, 32, 4);
     {
         // too few tile-planes to give every resident 512-lane workgroup 8
-        // planes: equal 8-plane runs on that shape (a larger workgroup would
+        // planes: equal runs on that shape (a larger workgroup would
         // sit alone on its CU with twice the lanes per plane)
         const Cand &c = cands()[cand_index(32, 8, 0, 4)];
         const int64_t tiles = (int64_t)((b.n[0] + out_tx(c) - 1) / out_tx(c)) * ((b.n[1] + out_ty(c) - 1) / out_ty(c));
