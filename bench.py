@@ -549,6 +549,24 @@ def main():
                "sample": f"{m} RK4 steps of the 256^3 wave workload (after one untimed warm-up step), "
                          f"plain C FP64 oracle with OpenMP on {model}, {el:.1f} s"}
         log(f"[bench] cpu: {cpu}")
+        # the same oracle on one thread, a few steps (about 5 s)
+        nthr = O.num_threads()
+        O.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            O.rk4(u0, r0, g, d["dx"], d["dt"], 1)
+            one1 = time.perf_counter() - t0
+            m1 = int(min(20, max(1, math.ceil(4.0 / max(one1, 1e-3)))))
+            t0 = time.perf_counter()
+            O.rk4(u0, r0, g, d["dx"], d["dt"], m1)
+            el1 = time.perf_counter() - t0
+        finally:
+            O.set_num_threads(nthr)
+        out["cpu_single_thread"] = {"value": round(npts * m1 / el1 / 1e9, 5), "unit": "Gpoint-updates/s",
+                                    "cores": 1, "kind": "oracle",
+                                    "sample": f"{m1} RK4 steps of the 256^3 wave workload on one thread, "
+                                              f"{model}, {el1:.1f} s"}
+        log(f"[bench] cpu single thread: {out['cpu_single_thread']}")
 
     rec = {"metric": METRIC, "value": round(value, 3), "unit": "Gpoint-updates/s", "n_gpus": 1, "steps": K,
            "warmup": WU, "ms_per_step": round(wall * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",

@@ -31,6 +31,7 @@ def lib():
         P = ctypes.POINTER(ctypes.c_double)
         i, d = ctypes.c_int, ctypes.c_double
         L.o4_num_threads.restype = i
+        L.o4_set_num_threads.argtypes = [i]
         L.o4_fill_ghosts_periodic.argtypes = [i, i, i, i, P]
         L.o4_d1.argtypes = [i, i, i, i, i, d, P, P]
         L.o4_d2.argtypes = [i, i, i, i, i, d, P, P]
@@ -49,6 +50,11 @@ def lib():
 
 def num_threads() -> int:
     return lib().o4_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (timing only; results are independent of it)."""
+    lib().o4_set_num_threads(int(n))
 
 
 def _p(a):

@@ -88,6 +88,17 @@ int o4_num_threads(void)
 #endif
 }
 
+/* threads of the following oracle calls (n >= 1); timing only, results do not depend on it */
+void o4_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* --------------------------------------------------------------------------
  * Periodic ghost fill.  Ghost zones hold copies of interior points of the
  * same box, point index taken modulo n (the box is its own periodic
