@@ -247,8 +247,10 @@ int s4_rk4_adjoint_step_y3(s4_ctx *ctx, const s4_box *b, const double *u_n, cons
                            size_t ws_bytes, void *stream);
 
 /* Time the candidate tile shapes and kernel variants of `op` on these boxes
- * (median of hipEvent timings after warm-up, ties to the lowest candidate
- * index) and keep the fastest for this "loop setup": the op, box sizes,
+ * (median of hipEvent timings after warm-up; the candidates within 3 % of
+ * the fastest are timed again, interleaved, in three rounds, each keeping
+ * its best median; ties to the lowest candidate index) and keep the
+ * fastest for this "loop setup": the op, box sizes,
  * ghost width, strides and alignment, and device (the key the paper's
  * LoopControl tunes per loop setup, Sec. III-B).  Scratch buffers are
  * taken from `scratch` (device memory of at least s4_tune_scratch_size

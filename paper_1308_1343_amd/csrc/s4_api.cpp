@@ -2403,12 +2403,10 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     hipEvent_t e0, e1;
     S4_HIP(hipEventCreate(&e0));
     S4_HIP(hipEventCreate(&e1));
-    int best = -1, best_level = -1;
-    float best_t = 0, best_level_t = 0;
-    for (int ci = 0; ci < (int)cands().size() && !r; ++ci) {
+    // time candidate ci: the median of nrep timed calls after two warm-up calls
+    auto time_cand = [&](int ci, int nrep, float &med) -> int {
+        int r = S4_OK;
         const Cand &c = cands()[ci];
-        if (!cand_allowed(c, op, nbox) || !cand_fits(c, b, nbox))
-            continue;
         // per candidate: what one call of the op launches, on scratch buffers
         std::vector<DevBox> tab;
         int64_t nitems = 0;
@@ -2447,7 +2445,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
                 std::vector<char> bytes(rk4_table_bytes(nbox), 0);
                 memcpy(bytes.data(), tab.data(), tab.size() * sizeof(DevBox));
                 if ((r = upload_table(dtab, bytes, s)))
-                    break;
+                    return r;
             }
         }
         int rot = 0;
@@ -2516,7 +2514,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         for (int w = 0; w < 2 && !r; ++w)
             r = run();
         std::vector<float> ts;
-        for (int k = 0; k < reps && !r; ++k) {
+        for (int k = 0; k < nrep && !r; ++k) {
             if (hipEventRecord(e0, s) != hipSuccess) {
                 r = fail(S4_EDEVICE, "event record");
                 break;
@@ -2529,17 +2527,45 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             ts.push_back(ms);
         }
         if (r)
-            break;
+            return r;
         std::sort(ts.begin(), ts.end());
-        const float med = ts[ts.size() / 2];
-        if (best < 0 || med < best_t) {
+        med = ts[ts.size() / 2];
+        return S4_OK;
+    };
+    std::vector<float> t(cands().size(), -1.0f);
+    for (int ci = 0; ci < (int)cands().size() && !r; ++ci)
+        if (cand_allowed(cands()[ci], op, nbox) && cand_fits(cands()[ci], b, nbox))
+            r = time_cand(ci, reps, t[(size_t)ci]);
+    // The candidates within 3 % of the fastest are timed again, interleaved,
+    // in three rounds, each keeping its best median: settings a few per cent
+    // apart are then not ranked by when in the sweep they ran (clocks and
+    // temperature drift over it).
+    if (!r) {
+        float t0 = -1.0f;
+        for (float x : t)
+            if (x >= 0 && (t0 < 0 || x < t0))
+                t0 = x;
+        std::vector<int> close;
+        for (int ci = 0; ci < (int)t.size(); ++ci)
+            if (t[(size_t)ci] >= 0 && t[(size_t)ci] <= 1.03f * t0)
+                close.push_back(ci);
+        if (close.size() > 1)
+            for (int round = 0; round < 3 && !r; ++round)
+                for (int ci : close) {
+                    float m = 0;
+                    if ((r = time_cand(ci, reps, m)))
+                        break;
+                    t[(size_t)ci] = round == 0 ? m : std::min(t[(size_t)ci], m);
+                }
+    }
+    int best = -1, best_level = -1;
+    for (int ci = 0; ci < (int)t.size() && !r; ++ci) {
+        if (t[(size_t)ci] < 0)
+            continue;
+        if (best < 0 || t[(size_t)ci] < t[(size_t)best])
             best = ci;
-            best_t = med;
-        }
-        if (level_capable(c) && (best_level < 0 || med < best_level_t)) {
+        if (level_capable(cands()[ci]) && (best_level < 0 || t[(size_t)ci] < t[(size_t)best_level]))
             best_level = ci;
-            best_level_t = med;
-        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
