@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--sections", default="rk4,tuning,rhs,latency32,copy,mixed,batched,level,adjoint,cpu")
+    ap.add_argument("--sections", default="rk4,tuning,rhs,latency32,rk4c2,copy,mixed,batched,level,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
     args = ap.parse_args()
@@ -301,6 +301,29 @@ def main():
                             "rk4_kernel_set": kernel_set(S.s4_get_choice(ctx, S.S4_OP_RK4, b32))}
         log(f"[bench] latency32: {out['latency32']}")
         del u32, r32, o32, ws32
+
+    # ------------------------------------------------------------------ 256^3 RK4 with variable c^2
+    if "rk4c2" in sections:
+        # the headline box with a variable wave speed (c^2 = 1 + 0.5 U[-1,1), the
+        # adjoint workload's form): its own tile choice; 40 B per point-step
+        uc, rc = to_dev(d["u"]), to_dev(d["rho"])
+        cc = to_dev(1.0 + 0.5 * W.uniform_pm1(d["seed"], 99, tuple(n[::-1])))  # c^2 is read at interior points only
+        wsc = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
+        S.s4_rk4(ctx, box, [uc], [rc], [cc], d["dt"], 20, "graph", ws=wsc)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        S.s4_rk4(ctx, box, [uc], [rc], [cc], d["dt"], 100, "graph", ws=wsc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 100
+        chc = S.s4_get_choice(ctx, S.S4_OP_RK4, box)
+        out["rk4_c2"] = {"workload": "wave256 RK4 step with variable c^2", "ms_per_step": round(ms, 4),
+                         "gpoint_steps_per_s": round(npts / (ms / 1e3) / 1e9, 2),
+                         "achieved_GBs": round(npts * 40 / (ms / 1e3) / 1e9, 1), "bytes_per_point_step": 40,
+                         "tile": [chc["tile_x"], chc["tile_y"], chc["z_chunk"], chc["threads"]],
+                         "kernel_set": kernel_set(chc), "finite": bool(torch.isfinite(uc).all().item())}
+        log(f"[bench] rk4_c2: {out['rk4_c2']}")
+        del uc, rc, cc, wsc
 
     # ------------------------------------------------------------------ copy probe
     if "copy" in sections:
