@@ -81,6 +81,16 @@ extern "C" {
 #define S4_OP_ADJOINT_STEP 6
 #define S4_OP_LEVEL_SYNC 7
 
+/* ORed into S4_OP_RK4 for s4_tune, s4_tune_scratch_size, s4_get_choice and
+ * s4_set_choice: the loop setup of RK4 calls that pass a variable c^2
+ * (s4_rk4 with any c2[i] non-NULL, s4_rk4_step_to and s4_rk4_step_to_y3 with
+ * c2 non-NULL).  It reads one more field per point and needs more registers,
+ * so its tile choice is kept and tuned apart from that of the same boxes
+ * without c^2 (Sec. III-B keys the tuning on the loop setup).  A choice
+ * forced without this bit applies to both; a tuned one only to its own.
+ * Levels (s4_level_rk4) keep one setup.  Any other op with it: S4_EINVAL. */
+#define S4_WITH_C2 0x100
+
 /* bboxset operations (s4_bset_op) */
 #define S4_SET_UNION 0
 #define S4_SET_INTERSECTION 1
@@ -255,7 +265,9 @@ int s4_rk4_adjoint_step_y3(s4_ctx *ctx, const s4_box *b, const double *u_n, cons
  * LoopControl tunes per loop setup, Sec. III-B).  Scratch buffers are
  * taken from `scratch` (device memory of at least s4_tune_scratch_size
  * bytes); the caller's data are not touched.  flags: 0 = quick sweep,
- * 1 = full sweep.  Persists to S4_TUNE_CACHE when set.  For RK4 on several
+ * 1 = full sweep.  op S4_OP_RK4 | S4_WITH_C2 times the step with a c^2
+ * field in scratch and keeps the choice for calls that pass c^2.
+ * Persists to S4_TUNE_CACHE when set.  For RK4 on several
  * boxes it also keeps the fastest candidate that can run on a level
  * (s4_level_choice), for the same boxes coupled as a level. */
 int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scratch,

@@ -27,6 +27,7 @@ S4_OK, S4_EINVAL, S4_EGHOST, S4_ELAYOUT, S4_EALIAS, S4_EDEVICE, S4_ENOMEM, S4_EN
 S4_PERBOX, S4_BATCHED, S4_GRAPH = 0, 1, 2
 S4_OP_FILL, S4_OP_WAVE_RHS, S4_OP_RK4, S4_OP_DERIV_MIXED, S4_OP_ADJOINT_RHS, S4_OP_ADJOINT_STEP = 1, 2, 3, 4, 5, 6
 S4_OP_LEVEL_SYNC = 7
+S4_WITH_C2 = 0x100  # ORed into S4_OP_RK4: the loop setup of RK4 calls that pass c^2
 S4_SET_UNION, S4_SET_INTERSECTION, S4_SET_DIFFERENCE, S4_SET_SYMDIFF = 0, 1, 2, 3
 SET_OPS = {"union": S4_SET_UNION, "intersection": S4_SET_INTERSECTION, "difference": S4_SET_DIFFERENCE,
            "symmetric_difference": S4_SET_SYMDIFF}

@@ -310,14 +310,37 @@ struct s4_ctx {
     std::mutex mu;
 };
 
-static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbox)
+// c2: RK4 calls that pass a variable c^2 (one more field read per point
+// and different register pressure) form a loop setup of their own
+static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool c2 = false)
 {
     std::ostringstream o;
     o << "op" << op << "|" << ctx->name << "|" << nbox;
     for (int i = 0; i < nbox; ++i)
         o << "|" << b[i].n[0] << "," << b[i].n[1] << "," << b[i].n[2] << ",g" << b[i].ghost << ",s"
           << b[i].stride[1] << "," << b[i].stride[2];
+    if (c2)
+        o << "|c2";
     return o.str();
+}
+
+// whether an RK4 call passes c^2 for any box
+static bool has_c2(const double *const *c2, int nbox)
+{
+    for (int i = 0; c2 && i < nbox; ++i)
+        if (c2[i])
+            return true;
+    return false;
+}
+
+// strips S4_WITH_C2 from op; only S4_OP_RK4 takes it
+static int split_op(int &op, bool &c2)
+{
+    c2 = (op & S4_WITH_C2) != 0;
+    op &= ~S4_WITH_C2;
+    if (c2 && op != S4_OP_RK4)
+        return fail(S4_EINVAL, "S4_WITH_C2 applies to S4_OP_RK4 only (op %d)", op);
+    return S4_OK;
 }
 
 static int tile_ty(const Cand &c)
@@ -556,15 +579,20 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
 // peek: report the choice without advancing the on-line tuner.  level: the
 // RK4 steps of a level (its own setup key; level-capable candidates only,
 // a forced or tuned choice of the boxes is taken if it is one)
-static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false, bool level = false)
+// c2: the call passes c^2 (its own setup; a choice forced without c^2
+// applies to it too, a tuned one does not)
+static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false, bool level = false,
+                     bool c2 = false)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const std::string bkey = setup_key(ctx, op, b, nbox);
+    const std::string bkey = setup_key(ctx, op, b, nbox, c2);
     const std::string key = level ? bkey + LEVEL_SUFFIX : bkey;
     auto ok = [&](int c) { return !level || level_capable(cands()[c]); };
-    auto f = ctx->forced.find(bkey);
-    if (f != ctx->forced.end() && ok(f->second))
-        return {f->second, 0, key};
+    for (const std::string &k : {bkey, setup_key(ctx, op, b, nbox)}) {
+        auto f = ctx->forced.find(k);
+        if (f != ctx->forced.end() && ok(f->second))
+            return {f->second, 0, key};
+    }
     if (ctx->online) {
         OnlineSetup &st = online_setup(ctx, key, op, b, nbox, level);
         online_harvest(st);
@@ -927,10 +955,10 @@ int s4_workspace_size(const s4_box *b, int nbox, int op, int mode, size_t *bytes
 
 // fields of tuning scratch per box: the buffers one timed call of the op
 // touches, in as many independent sets as the tuner rotates through
-static int tune_fields(int op)
+static int tune_fields(int op, bool c2 = false)
 {
     switch (op) {
-    case S4_OP_RK4: return 2 + RK4_FIELDS;               // u, rho + the RK4 workspace
+    case S4_OP_RK4: return 2 + RK4_FIELDS + (c2 ? 1 : 0); // u, rho + the RK4 workspace (+ c^2)
     case S4_OP_WAVE_RHS: return 2 * TUNE_SETS;           // (u, rho_t) per set
     case S4_OP_ADJOINT_RHS: return 5 * 2;                // (lu, lrho, c2, out_u, out_rho) x 2 sets
     case S4_OP_ADJOINT_STEP: return 6 + ADJ_FIELDS;      // u_n rho_n c2 lam_u lam_rho c2_bar + workspace
@@ -943,12 +971,13 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes)
 {
     if (!bytes)
         return fail(S4_EINVAL, "bytes is NULL");
-    int r = s4_check_boxes(b, nbox, op);
-    if (r)
+    bool c2 = false;
+    int r = split_op(op, c2);
+    if (r || (r = s4_check_boxes(b, nbox, op)))
         return r;
     size_t t = 0;
     for (int i = 0; i < nbox; ++i)
-        t += (size_t)tune_fields(op) * field_bytes(b[i]);
+        t += (size_t)tune_fields(op, c2) * field_bytes(b[i]);
     *bytes = t + rk4_table_bytes(nbox);
     return S4_OK;
 }
@@ -1084,10 +1113,11 @@ int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
 {
     if (!ctx || !out)
         return fail(S4_EINVAL, "NULL argument");
-    int r = s4_check_boxes(b, nbox, op);
-    if (r)
+    bool c2 = false;
+    int r = split_op(op, c2);
+    if (r || (r = s4_check_boxes(b, nbox, op)))
         return r;
-    fill_choice(op, nbox, choose(ctx, op, b, nbox, true), out);
+    fill_choice(op, nbox, choose(ctx, op, b, nbox, true, false, c2), out);
     return S4_OK;
 }
 
@@ -1129,8 +1159,9 @@ int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
 {
     if (!ctx)
         return fail(S4_EINVAL, "ctx is NULL");
-    int r = s4_check_boxes(b, nbox, op);
-    if (r)
+    bool c2 = false;
+    int r = split_op(op, c2);
+    if (r || (r = s4_check_boxes(b, nbox, op)))
         return r;
     if (candidate >= (int)cands().size() || candidate < -1)
         return fail(S4_EINVAL, "candidate %d out of range", candidate);
@@ -1140,7 +1171,7 @@ int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
     if (candidate >= 0 && !cand_fits(cands()[candidate], b, nbox))
         return fail(S4_ENOTSUP, "candidate %d (whole RK4 steps) needs z planes below 2 GiB", candidate);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const std::string key = setup_key(ctx, op, b, nbox);
+    const std::string key = setup_key(ctx, op, b, nbox, c2);
     if (candidate < 0)
         ctx->forced.erase(key);
     else
@@ -1597,7 +1628,7 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
     if (r || nsteps == 0)
         return r;
     hipStream_t s = (hipStream_t)stream;
-    const Choice ch = choose(ctx, S4_OP_RK4, b, nbox);
+    const Choice ch = choose(ctx, S4_OP_RK4, b, nbox, false, false, has_c2(c2, nbox));
     OnlineTimer tm(ctx, ch, s);
     r = rk4_run(ctx, ch, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, s);
     if (r)
@@ -1650,14 +1681,14 @@ static int rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const d
         // the current choice without a trial of the on-line tuner (these calls
         // are not timed); per-stage kernel sets give way to the stage pairs,
         // whose first pass stores y_3
-        int ci = choose(ctx, S4_OP_RK4, b, 1, true).cand;
+        int ci = choose(ctx, S4_OP_RK4, b, 1, true, false, c2 != nullptr).cand;
         const int v = cands()[ci].variant;
         if (v != 1 && v != 3 && v != 4)
             ci = heuristic(ctx, S4_OP_RK4, b, 1, true);
         return rk4_pair_step(ctx, cands()[ci], b[0], u_in, rho_in, u_out, rho_out, c2,
                              pair_fields(b[0], (char *)workspace), dt, s, u3o, r3o);
     }
-    const Choice ch = choose(ctx, S4_OP_RK4, b, 1);
+    const Choice ch = choose(ctx, S4_OP_RK4, b, 1, false, false, c2 != nullptr);
     OnlineTimer tm(ctx, ch, s);
     const Cand &c = cands()[ch.cand];
     if (c.variant == 1 || c.variant == 3 || c.variant == 4) {
@@ -2379,6 +2410,8 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     int r = s4_tune_scratch_size(b, nbox, op, &need);
     if (r)
         return r;
+    bool with_c2 = false;
+    split_op(op, with_c2);
     const int kop = kernel_op(op);
     if (kop < 0)
         return fail(S4_EINVAL, "op %d has no tunable kernel", op);
@@ -2388,7 +2421,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         return fail(S4_ENOMEM, "scratch %zu bytes < %zu needed", scratch_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     S4_HIP(hipMemsetAsync(scratch, 0, need, s));
-    const int nf = tune_fields(op);
+    const int nf = tune_fields(op, with_c2);
     std::vector<std::vector<double *>> F(nbox);
     size_t off = 0;
     for (int i = 0; i < nbox; ++i) {
@@ -2399,7 +2432,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
     }
     char *tail = (char *)scratch + off; // box tables and counters (batched RK4)
     const double dt = 1e-9 * std::min({b[0].dx[0], b[0].dx[1], b[0].dx[2]});
-    const int reps = flags ? 15 : 5;
+    const int reps = flags & 1 ? 15 : 5;
     hipEvent_t e0, e1;
     S4_HIP(hipEventCreate(&e0));
     S4_HIP(hipEventCreate(&e1));
@@ -2415,17 +2448,21 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         const bool batched = op == S4_OP_RK4 && nbox > 1;
         if (op == S4_OP_RK4) {
             std::vector<double *> us(nbox), rs(nbox);
+            std::vector<const double *> cs(nbox, nullptr);
             for (int i = 0; i < nbox; ++i) {
                 us[i] = F[i][0];
                 rs[i] = F[i][1];
+                if (with_c2)
+                    cs[i] = F[i][(size_t)nf - 1];
             }
+            const double *const *c2a = with_c2 ? cs.data() : nullptr;
             // the RK4 workspace of box i is its fields 2..7, contiguous per box
             std::vector<char *> wsb(nbox);
             for (int i = 0; i < nbox; ++i)
                 wsb[i] = (char *)F[i][2] - field_shift(b[i]);
             if (c.variant == 3 || c.variant == 4) {
                 std::vector<PairFields> pfs;
-                pair_tables(b, nbox, us.data(), rs.data(), nullptr, wsb, c, tab, pfs);
+                pair_tables(b, nbox, us.data(), rs.data(), c2a, wsb, c, tab, pfs);
                 for (int i = 0; i < nbox; ++i)
                     nitems += dev_items(tab[(size_t)i]);
             } else {
@@ -2433,7 +2470,8 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
                 for (int i = 0; i < nbox; ++i) {
                     std::vector<DevBox> one;
                     double *ui[1] = {us[i]}, *ri[1] = {rs[i]};
-                    rk4_tables(&b[i], 1, ui, ri, nullptr, wsb[i], c, one);
+                    const double *ci1[1] = {cs[i]};
+                    rk4_tables(&b[i], 1, ui, ri, with_c2 ? ci1 : nullptr, wsb[i], c, one);
                     for (int st = 0; st < 4; ++st) {
                         one[st].item0 = (int)nitems;
                         tab[(size_t)st * nbox + i] = one[st];
@@ -2458,8 +2496,8 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
                     return pair_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, set & 1, s, nullptr);
                 if (c.variant == 1) // one fused step: (u, rho) -> ping-pong buffers, alternating
                     return rk4_pair_step(ctx, c, b[0], set & 1 ? pf.Up : F[0][0], set & 1 ? pf.Rp : F[0][1],
-                                         set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp, nullptr, pf, dt,
-                                         s);
+                                         set & 1 ? F[0][0] : pf.Up, set & 1 ? F[0][1] : pf.Rp,
+                                         with_c2 ? F[0][(size_t)nf - 1] : nullptr, pf, dt, s);
                 return rk4_step(ctx, c, tab, nbox, batched, dtab, counters, nitems, dt, s);
             case S4_OP_WAVE_RHS: {
                 StageCoef K{};
@@ -2573,10 +2611,10 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
         return r;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        const std::string key = setup_key(ctx, op, b, nbox);
+        const std::string key = setup_key(ctx, op, b, nbox, with_c2);
         ctx->tuned[key] = best;
         // the same boxes as a level run the best level-capable setting
-        if (op == S4_OP_RK4 && nbox > 1 && best_level >= 0)
+        if (op == S4_OP_RK4 && !with_c2 && nbox > 1 && best_level >= 0)
             ctx->tuned[key + LEVEL_SUFFIX] = best_level;
     }
     save_cache(ctx);

@@ -90,3 +90,17 @@ def test_entry_points_reject_null_context():
     assert L.s4_tune(None, S.S4_OP_RK4, arr, 1, 0, None, 0, None) == S.S4_EINVAL
     out = (ctypes.c_int * 8)()
     assert L.s4_get_choice(None, S.S4_OP_RK4, arr, 1, out) == S.S4_EINVAL
+
+
+def test_with_c2_modifier_on_tune_scratch():
+    # one more field (the c^2 the timed step reads) per box; RK4 only
+    b = good_box((16, 16, 16), 2)
+    field = 8 * (16 + 4) * (16 + 4) * (16 + 4)
+    plain = S.s4_tune_scratch_size(b, S.S4_OP_RK4)
+    withc = S.s4_tune_scratch_size(b, S.S4_OP_RK4 | S.S4_WITH_C2)
+    assert withc - plain >= field
+    two = S.s4_tune_scratch_size([b, b], S.S4_OP_RK4 | S.S4_WITH_C2) - S.s4_tune_scratch_size([b, b], S.S4_OP_RK4)
+    assert two == 2 * (withc - plain)
+    with pytest.raises(S.Sten4Error):
+        S.s4_tune_scratch_size(b, S.S4_OP_WAVE_RHS | S.S4_WITH_C2)
+    assert "S4_WITH_C2" in S.s4_last_error()

@@ -68,3 +68,45 @@ def test_results_independent_of_online_search():
     ref = run(S.Context(0), 25)
     np.testing.assert_array_equal(a[0], ref[0])
     np.testing.assert_array_equal(a[1], ref[1])
+
+
+def test_c2_calls_have_their_own_setup():
+    # calls that pass c^2 are tuned and chosen apart from those without it
+    d = W.wave_cube(48, 3, "gauss")
+    g = d["ghost"]
+    RK4C2 = S.S4_OP_RK4 | S.S4_WITH_C2
+
+    def fields():
+        u = S.alloc_field(d["n"], g, fill=0.0)
+        r = S.alloc_field(d["n"], g, fill=0.0)
+        c = S.alloc_field(d["n"], g, fill=0.0)
+        S.interior(u, g).copy_(torch.from_numpy(d["u"]))
+        S.interior(r, g).copy_(torch.from_numpy(d["rho"]))
+        S.interior(c, g).copy_(torch.from_numpy(1.0 + 0.5 * d["u"] ** 2))
+        return u, r, c
+
+    u, r, c = fields()
+    b = S.box_of(u, g, d["dx"])
+    ctx = S.Context(0)
+    S.s4_tune(ctx, RK4C2, b, flags=0)
+    assert S.s4_get_choice(ctx, RK4C2, b)["tuned"] == 1
+    assert S.s4_get_choice(ctx, S.S4_OP_RK4, b)["tuned"] == 0
+    S.s4_rk4(ctx, b, [u], [r], [c], d["dt"], 3, "graph")
+    # every kernel set rounds alike: the tuned c^2 setting matches each forced one
+    n_allowed = S.s4_get_choice(ctx, RK4C2, b)["ncandidates"]
+    for cand in (0, n_allowed - 1, S.s4_get_choice(ctx, S.S4_OP_RK4, b)["candidate"]):
+        f = S.Context(0)
+        S.s4_set_choice(f, S.S4_OP_RK4, b, cand)  # forced without the bit: applies to c^2 calls too
+        assert S.s4_get_choice(f, RK4C2, b)["candidate"] == cand
+        u2, r2, c2 = fields()
+        S.s4_rk4(f, S.box_of(u2, g, d["dx"]), [u2], [r2], [c2], d["dt"], 3, "graph")
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(u2), host(u))
+        np.testing.assert_array_equal(host(r2), host(r))
+    # a choice forced for c^2 calls leaves the plain setup alone
+    f = S.Context(0)
+    S.s4_set_choice(f, RK4C2, b, 0)
+    assert S.s4_get_choice(f, RK4C2, b)["candidate"] == 0
+    assert S.s4_get_choice(f, S.S4_OP_RK4, b)["candidate"] == S.s4_get_choice(S.Context(0), S.S4_OP_RK4, b)["candidate"]
+    with pytest.raises(S.Sten4Error):
+        S.s4_get_choice(f, S.S4_OP_WAVE_RHS | S.S4_WITH_C2, b)
