@@ -521,7 +521,8 @@ def main():
         u0, r0, c2, ut = compact(ad["u0"]), compact(ad["rho0"]), compact(ad["c2"], 1.0), compact(ad["u_target"])
         if not args.no_tune:
             abox = S.box_of(u0, ga, ad["dx"])
-            for op in (S.S4_OP_RK4, S.S4_OP_ADJOINT_STEP):
+            # the forward steps and their replays pass c^2: that loop setup is tuned
+            for op in (S.S4_OP_RK4 | S.S4_WITH_C2, S.S4_OP_ADJOINT_STEP):
                 S.s4_tune(ctx, op, abox, flags=1)
             torch.cuda.empty_cache()
         times = []
