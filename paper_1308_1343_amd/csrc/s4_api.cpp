@@ -118,7 +118,7 @@ static const std::vector<Cand> &cands()
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 3, 0});
         for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}}) // 64 x 8 wastes half its lanes
-            for (int tz : {0, 128, 64, 32})
+            for (int tz : {0, 128, 64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 4, 0});
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})

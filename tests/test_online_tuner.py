@@ -14,7 +14,7 @@ CANDS = [(0, tx, nw, tz, 0) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0
         [(2, tx, 4, tz, ry) for tx in (256, 128, 64) for ry in (4, 2) for tz in (64, 32, 16)] + \
         [(3, tx, nw, tz, 0) for tx, nw in ((64, 4), (64, 8), (32, 8), (32, 4), (16, 8), (16, 4))
          for tz in (64, 32, 16)] + \
-        [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8)) for tz in (0, 128, 64, 32)] + \
+        [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8)) for tz in (0, 128, 64, 32, 16)] + \
         [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
 ORD_TX = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}
 ORD_NW = {4: 0, 8: 1, 16: 2}
@@ -41,7 +41,7 @@ def test_candidate_table_matches_library():
         assert max(tr) < n  # stage pairs only for RK4, row kernels only for the RHS and RK4
     tr = S.s4_online_simulate(S.S4_OP_RK4, [BOX, BOX], list(np.linspace(1, 2, len(CANDS))), ncalls=400,
                               restart_prob=0.2)
-    assert max(tr) < 78  # widened stage pairs only on one box
+    assert max(tr) < 81  # widened stage pairs only on one box
 
 
 def test_converges_on_a_smooth_landscape():
