@@ -421,6 +421,9 @@ static int64_t step4_run_length(int64_t total, int64_t slots, int ncu)
 // measured on whole-step runs over periodic cubes of side 128 to 512
 // (relative to 32 x 16 lanes in z chunks): equal runs lose L2 locality, and a
 // 1024-lane workgroup alone on its CU hides less latency per lane.
+// 16-plane chunks count only where all their items fit one round (on 128^3
+// they beat 32-plane chunks, which leave CUs idle, by 6 %; over several rounds
+// the start-up term prices them far below what they measure).
 static int step4_single(const s4_ctx *ctx, const s4_box &b)
 {
     struct Opt {
@@ -428,7 +431,8 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
         double per_plane;
     };
     static const Opt opts[] = {{32, 8, 32, 0, 1.0},    {32, 8, 0, 0, 1.184},    {64, 16, 128, 1, 1.006},
-                               {64, 16, 64, 1, 1.006}, {64, 16, 0, 1, 1.110}, {32, 16, 0, 2, 1.270}};
+                               {64, 16, 64, 1, 1.006}, {64, 16, 0, 1, 1.110}, {32, 16, 0, 2, 1.270},
+                               {32, 8, 16, 0, 1.0}};
     int best = cand_index(32, 8, 32, 4);
     {
         // too few tile-planes to give every resident 512-lane workgroup 8
@@ -452,6 +456,8 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
         if (o.tz > 0) {
             const int64_t tz = std::min<int64_t>(o.tz, nz);
             const int64_t items = tiles * ((nz + tz - 1) / tz);
+            if (o.tz == 16 && items > slots)
+                continue;
             planes = (double)((items + slots - 1) / slots) * (double)(tz + 8);
         } else {
             // the runs step4_run hands out: R planes each (the last one shorter)

@@ -375,6 +375,13 @@ def test_heuristic_kernel_sets(ctx):
     b = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, b)["kernel_op"] == 102
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, b])["kernel_op"] == 102
+    # 128^3: 32-plane chunks of 28 x 12 output tiles leave CUs idle (220 items);
+    # 16-plane chunks fit one round of resident workgroups
+    c128 = S.make_box((128, 128, 128), 2, (1, 144, 144 * 132), 1 / 128)
+    ch = S.s4_get_choice(fresh, S.S4_OP_RK4, c128)
+    assert (ch["kernel_op"], ch["tile_x"], ch["tile_y"], ch["z_chunk"]) == (102, 32, 16, 16), ch
+    ch = S.s4_get_choice(fresh, S.S4_OP_RK4, b)
+    assert ch["z_chunk"] != 16, ch
     big = S.make_box((16384, 16384, 4), 2, (1, 16400, 16400 * 16388), 1.0)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, big)["kernel_op"] == 101
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, big])["kernel_op"] == 101

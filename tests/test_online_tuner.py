@@ -149,7 +149,7 @@ def test_whole_step_start_follows_the_cost_model():
     else the shape and work order the cost model rates cheapest -- 28 x 28
     output tiles where the box divides into them (224^3, 448^3), 60 x 12
     tiles on most large cubes."""
-    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 0, 0), 160: (4, 32, 8, 32, 0), 192: (4, 64, 16, 0, 0),
+    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 16, 0), 160: (4, 32, 8, 32, 0), 192: (4, 64, 16, 0, 0),
             224: (4, 32, 16, 0, 0), 256: (4, 64, 16, 128, 0), 384: (4, 64, 16, 0, 0), 448: (4, 32, 16, 0, 0)}
     for n, w in want.items():
         assert start_of(S.S4_OP_RK4, cube(n)) == w, n
