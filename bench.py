@@ -18,7 +18,8 @@ The same JSON line also reports, each on its own workload:
            256 MB last-level cache
   latency32  microseconds per RHS and per RK4 step on the cache-resident
            32^3 box
-  copy     a streaming copy of 1 GiB (achievable HBM bandwidth)
+  copy     a streaming copy of 1 GiB (achievable HBM bandwidth: one 16-byte
+           vector per lane in a single pass)
   batched  one RK4 step over a 60-box, 3-level bboxset (sides 16..96, 3
            ghosts) in per-box launches, one persistent batched launch per
            stage, and the batched step replayed as a hipGraph
@@ -29,7 +30,11 @@ The same JSON line also reports, each on its own workload:
            launch modes, beside one box spanning the same domain
   adjoint  loss and gradient through 50 RK4 steps on a 128^3 box with
            variable c^2, checkpoint every 10 steps
-and, on rank 0 at N=1, the CPU oracle timed on a bounded sample.
+and, on rank 0 at N=1, the CPU oracle: it runs the headline's warm-up and
+timed steps from the same inputs, its final state is compared with the timed
+GPU outputs (max_rel_err, max-norm relative error over interior points of u
+and rho; the run fails above 1e-12), and its time, continued to about 20 s
+of CPU work, is the cpu_baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections ...]
 """
@@ -71,6 +76,18 @@ def kernel_set(ch):
             else "rows" if k >= 200 else "tiles")
 
 
+def kernels_per_step(ch, nbox, level=False):
+    """Kernel launches of one RK4 step on nbox boxes, per launch mode, for the
+    kernel set of tile choice ch: whole steps 1 per box (1 batched), stage
+    pairs 2, per-stage sets 4; on a level every pass is preceded by one
+    exchange launch (all boxes).  A graph replays the batched launches as one
+    graph launch per step."""
+    k = ch["kernel_op"]
+    per = 1 if k == 102 else 2 if k in (100, 101) else 4
+    sync = per if level else 0
+    return {"perbox": per * nbox + sync, "batched": per + sync, "graph_kernels": per + sync, "graph_launches": 1}
+
+
 def traffic_from_profile(kernel_key, tile):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source with the same tile choice; else None."""
@@ -88,8 +105,8 @@ def traffic_from_profile(kernel_key, tile):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections", default="rk4,tuning,rhs,latency32,rk4c2,copy,mixed,batched,level,adjoint,cpu")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile sweep (heuristic or cached choice)")
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile choices to load and update")
@@ -126,8 +143,12 @@ def main():
         S.interior(t, g).copy_(torch.from_numpy(a))
         return t
 
+    # the timed state and its workspace are allocated (and touched) before
+    # the tile sweep, so the timed steps run on memory already in use
     u, rho = to_dev(d["u"]), to_dev(d["rho"])
     box = S.box_of(u, g, d["dx"])
+    ws = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
+    ws.zero_()
     tuned = {}
     if not args.no_tune:
         # the library's tile sweep for each loop setup timed below (run before any timing)
@@ -135,8 +156,6 @@ def main():
         for op in (S.S4_OP_RK4, S.S4_OP_WAVE_RHS):
             S.s4_tune(ctx, op, box, flags=1)
         tuned["wave256_s"] = round(time.perf_counter() - t0, 3)
-        torch.cuda.empty_cache()
-    ws = S.workspace(S.s4_workspace_size(box, S.S4_OP_RK4, S.S4_GRAPH))
     choice = S.s4_get_choice(ctx, S.S4_OP_RK4, box)
     stream = torch.cuda.current_stream()
     log(f"[bench] rk4 256^3: warmup {WU} steps, tile {choice}")
@@ -151,7 +170,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
-    finite = bool(torch.isfinite(S.interior(u, g)).all().item())
+    # the timed outputs (after WU + K steps), checked against the oracle in the CPU leg
+    timed_u, timed_rho = u.cpu().numpy(), rho.cpu().numpy()
+    finite = bool(np.isfinite(timed_u).all() and np.isfinite(timed_rho).all())
     log(f"[bench] rk4 256^3: {K} steps in {wall * 1e3:.2f} ms wall, {ev_ms:.2f} ms events, finite={finite}")
     value = npts * K / wall / 1e9
     # dominant kernel: the only kernel in the timed region.  Per-stage kernel set:
@@ -425,8 +446,8 @@ def main():
                           "interior_points": bpts, "steps": kb, "modes": res,
                           "speedup_batched_vs_perbox": round(res["perbox"]["ms_per_step"] / res["batched"]["ms_per_step"], 3),
                           "speedup_graph_vs_perbox": round(res["perbox"]["ms_per_step"] / res["graph"]["ms_per_step"], 3),
-                          "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch), "kernel_set": kernel_set(ch),
-                          "launches_per_step": {"perbox": 4 * len(boxes), "batched": 4, "graph": 1}}
+                          "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch),
+                          "launches_per_step": kernels_per_step(ch, len(boxes))}
         log(f"[bench] batched: {out['batched']}")
         del fields, us_, rs_, wsb
 
@@ -502,7 +523,7 @@ def main():
                         "single_box_same_domain_ms_per_step": round(one_ms, 4),
                         "level_graph_over_single_box": round(res["graph"]["ms_per_step"] / one_ms, 3),
                         "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch),
-                        "launches_per_step": {"perbox": 4 * (len(lboxes) + 1), "batched": 8, "graph": 1}}
+                        "launches_per_step": kernels_per_step(ch, len(lboxes), level=True)}
         log(f"[bench] level: {out['level']}")
 
     # ------------------------------------------------------------------ adjoint
@@ -554,19 +575,35 @@ def main():
         log(f"[bench] adjoint: {out['adjoint']}")
 
     # ------------------------------------------------------------------ CPU oracle baseline
+    # The oracle runs the headline's WU + K steps from the same inputs: its
+    # final state is the parity reference for the timed outputs, and its time
+    # (continued by more steps up to about 20 s of CPU work) is the baseline.
     cpu = None
+    parity = None
     if "cpu" in sections:
         import oracle as O
         u0 = O.embed(d["u"], g)
         r0 = O.embed(d["rho"], g)
-        O.rk4(u0, r0, g, d["dx"], d["dt"], 1)  # untimed: first touch of the oracle's scratch
+        nrun = WU + K
         t0 = time.perf_counter()
-        O.rk4(u0, r0, g, d["dx"], d["dt"], 1)
-        one = time.perf_counter() - t0
-        m = int(min(300, max(2, math.ceil(20.0 / max(one, 1e-3)))))  # about 10-30 s of CPU work
-        t0 = time.perf_counter()
-        O.rk4(u0, r0, g, d["dx"], d["dt"], m)
+        ou, orr = O.rk4(u0, r0, g, d["dx"], d["dt"], nrun)
         el = time.perf_counter() - t0
+        sl = (slice(g, -g),) * 3
+
+        def rel_err(got, want):
+            return float(np.max(np.abs(got[sl] - want[sl])) / np.max(np.abs(want[sl])))
+
+        parity = {"u": rel_err(timed_u, ou), "rho": rel_err(timed_rho, orr), "steps": nrun,
+                  "reference": "FP64 oracle from the same inputs", "tolerance": 1e-12}
+        parity["max"] = max(parity["u"], parity["rho"])
+        log(f"[bench] parity of the timed 256^3 outputs: {parity}")
+        m = nrun
+        if el < 10.0:  # continue to about 20 s of CPU work
+            more = int(min(300, max(1, math.ceil((20.0 - el) / max(el / nrun, 1e-3)))))
+            t0 = time.perf_counter()
+            O.rk4(ou, orr, g, d["dx"], d["dt"], more)
+            el += time.perf_counter() - t0
+            m += more
         model = "unknown CPU"
         try:
             with open("/proc/cpuinfo") as f:
@@ -575,8 +612,9 @@ def main():
             pass
         cpu = {"value": round(npts * m / el / 1e9, 5), "unit": "Gpoint-updates/s", "cores": O.num_threads(),
                "kind": "oracle",
-               "sample": f"{m} RK4 steps of the 256^3 wave workload (after one untimed warm-up step), "
-                         f"plain C FP64 oracle with OpenMP on {model}, {el:.1f} s"}
+               "sample": f"{m} RK4 steps of the 256^3 wave workload ({nrun} from the inputs of the timed GPU run, "
+                         f"the parity reference, then {m - nrun} more), plain C FP64 oracle with OpenMP on {model}, "
+                         f"{el:.1f} s"}
         log(f"[bench] cpu: {cpu}")
         # the same oracle on one thread, a few steps (about 5 s)
         nthr = O.num_threads()
@@ -605,9 +643,14 @@ def main():
                       "points": npts, "seed": d["seed"], "tile": [choice["tile_x"], choice["tile_y"],
                                                                    choice["z_chunk"], choice["threads"]],
                       "tile_from_tuner": bool(choice["tuned"])},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "max_rel_err": None if parity is None else parity["max"],
+           "parity": parity}
     rec.update(out)
     print(json.dumps(rec), flush=True)
+    if parity is not None and not parity["max"] <= parity["tolerance"]:
+        log(f"[bench] PARITY FAILURE: timed outputs differ from the oracle by {parity['max']:.3e} "
+            f"(> {parity['tolerance']:.0e})")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -116,7 +116,13 @@ typedef struct {
 /* Create a context bound to HIP device `device`.  Reads the device's
  * properties (CU count, XCD count, name), which seed the default tile
  * choice.  The environment variable S4_TUNE_CACHE names a JSON file of tuned
- * choices that is read here and rewritten by s4_tune. */
+ * choices that is read here and rewritten by s4_tune: one object mapping a
+ * loop-setup key to the parameters of the chosen candidate,
+ *   "op<op>|<device>|<nbox>|<nx>,<ny>,<nz>,g<ghost>,s<stride1>,<stride2>
+ *    (one such group per box)[|c2][|level]": "v<variant> x<tx> w<waves>
+ *    z<z chunk> r<rows>".
+ * Entries that name no candidate of this build, or a candidate the setup's
+ * op cannot run on its boxes, are ignored (the heuristic applies). */
 int s4_create(int device, s4_ctx **out);
 
 /* Free the context's host caches and captured graphs.  NULL is ignored. */
@@ -162,7 +168,12 @@ int s4_wave_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *u,
  * Axes a, b in {x, y, z} = {0, 1, 2}; A is host memory, row major, used as
  * given.  Ghosts of every g[k] must be filled including edges (the mixed
  * terms read them).  out[k] is written at interior points only and must not
- * overlap any g[j]. */
+ * overlap any g[j].  Definition: the textbook 4th-order centred first and
+ * second differences (the paper leaves the discretisation to the
+ * application code; it prints only a 2nd-order example loop in Sec. IV-C4),
+ * with the mixed derivative read as the tensor product of two first
+ * differences.  The loop over the box is the tiled traversal of Sec. III-A
+ * with the aligned, padded iteration of Sec. IV-C4. */
 int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const *g,
                    const double A[9], double *const *out, void *stream);
 
@@ -180,6 +191,13 @@ int s4_deriv_mixed(s4_ctx *ctx, const s4_box *b, int nfield, const double *const
  * c2 as in s4_wave_rhs.  `workspace` is device memory of at least
  * s4_workspace_size(b, nbox, S4_OP_RK4, mode) bytes, 256-byte aligned, owned
  * by the caller and not used by anything else while the call's work runs.
+ * Definition: Kutta's classical RK4 tableau (textbook; the paper names no
+ * time integrator) over the wave RHS above.  The stage kernels are the
+ * traversal of Sec. III-A; the stage-pair and whole-step sets fuse stages
+ * into one loop, the loop fusion the paper proposes as future work
+ * (Sec. III-C); S4_BATCHED runs every box of the set in one launch that
+ * hands out work items at run time, as LoopControl assigns loop regions to
+ * threads on the fly to balance uneven cost (Sec. III).
  * mode: S4_PERBOX, S4_BATCHED or S4_GRAPH.  S4_GRAPH caches one captured
  * step per (boxes, pointers, dt, workspace) in the context; the cache entry
  * is invalid once any of those buffers is freed (s4_destroy drops it). */
@@ -192,7 +210,8 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
  * not modified and must not overlap the outputs (S4_EALIAS).  Gives the same
  * values as s4_rk4 on a copy of the inputs.  For recomputing the states of a
  * checkpointed segment during backpropagation.  c2 and the workspace as for
- * s4_rk4 (S4_OP_RK4 on this machine). */
+ * s4_rk4 (S4_OP_RK4 on this machine).  Definition: one step of the classical RK4
+ * tableau of s4_rk4 (textbook); traversal Sec. III-A, fused as Sec. III-C. */
 int s4_rk4_step_to(s4_ctx *ctx, const s4_box *b, const double *u_in, const double *rho_in, const double *c2,
                    double dt, double *u_out, double *rho_out, void *workspace, size_t ws_bytes, void *stream);
 
@@ -217,7 +236,10 @@ int s4_rk4_step_to_y3(s4_ctx *ctx, const s4_box *b, const double *u_in, const do
  * where L_p is "periodic ghost fill, then L", a symmetric operator.  out_u
  * receives L_p(c^2 lrho): the kernel forms c^2*lrho at each interior point and
  * reads lrho (and c2) at periodically wrapped indices, so lrho's ghosts are
- * not read.  out_rho receives a copy of lu.  Interior points only. */
+ * not read.  out_rho receives a copy of lu.  Interior points only.
+ * Definition: the transpose of the linear map of s4_wave_rhs on periodic
+ * boxes (textbook linear algebra; the paper has no adjoint), in which the
+ * periodic 4th-order Laplacian is symmetric.  Traversal as Sec. III-A. */
 int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *const *lu,
                         const double *const *lrho, const double *const *c2,
                         double *const *out_u, double *const *out_rho, void *stream);
@@ -237,7 +259,11 @@ int s4_wave_adjoint_rhs(s4_ctx *ctx, const s4_box *b, int nbox, const double *co
  * 4 and 3, then 2 and 1, each stencilling c^2 kb_rho formed at every tap.  lam_u, lam_rho: on entry
  * ybar = dJ/dy_{n+1}, on return dJ/dy_n (interior).  c2_bar, if not NULL,
  * is accumulated into at interior points; c2 == NULL means c = 1.
- * Workspace as for s4_rk4 with S4_OP_ADJOINT_STEP. */
+ * Workspace as for s4_rk4 with S4_OP_ADJOINT_STEP.  Definition: reverse-mode
+ * differentiation of one classical RK4 step (textbook; the paper has no
+ * adjoint): the step is linear in y, so its transpose is the same tableau
+ * applied with the transposed RHS of s4_wave_adjoint_rhs in reverse stage
+ * order.  Traversal Sec. III-A; two stages per pass as Sec. III-C's fusion. */
 int s4_rk4_adjoint_step(s4_ctx *ctx, const s4_box *b, const double *u_n, const double *rho_n,
                         const double *c2, double dt, double *lam_u, double *lam_rho,
                         double *c2_bar, void *workspace, size_t ws_bytes, void *stream);
@@ -272,6 +298,15 @@ int s4_rk4_adjoint_step_y3(s4_ctx *ctx, const s4_box *b, const double *u_n, cons
  * (s4_level_choice), for the same boxes coupled as a level. */
 int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scratch,
             size_t scratch_bytes, void *stream);
+
+/* Host-only reading of a tuning cache file in the S4_TUNE_CACHE format:
+ * *candidate = the candidate index a context on device `device` (its
+ * architecture name, e.g. "gfx950") would take from that file for `op`
+ * (with S4_WITH_C2 for RK4 calls that pass c^2) on these boxes, as a level
+ * if level != 0, or -1 when the file holds no usable entry for that setup.
+ * S4_EINVAL if the file cannot be read.  No device call. */
+int s4_tune_cache_lookup(const char *path, const char *device, int op, const s4_box *b, int nbox, int level,
+                         int *candidate);
 
 /* Scratch bytes s4_tune needs for these boxes. */
 int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
@@ -455,9 +490,11 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
  * Sec. III-B (a loop setup's execution parameters). */
 int s4_level_choice(s4_ctx *ctx, const s4_level *L, int out[8]);
 
-/* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned):
- * the streaming-copy probe that calibrates achievable HBM bandwidth and the
- * byte counters against a kernel of known traffic. */
+/* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned,
+ * at most 64 GiB: S4_EINVAL beyond): the streaming-copy probe that
+ * calibrates achievable HBM bandwidth and the byte counters against a
+ * kernel of known traffic.  One lane per 16 bytes, in a single pass over
+ * the buffers (non-temporal loads and stores). */
 int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream);
 
 #ifdef __cplusplus

@@ -39,7 +39,7 @@ MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
            "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
            "s4_rk4_step_to", "s4_rk4_step_to_y3", "s4_rk4_adjoint_step", "s4_rk4_adjoint_step_y3", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
-           "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
+           "s4_tune_cache_lookup", "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
            "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
            "s4_bset_derivative", "s4_bset_info", "s4_bset_keys", "s4_bset_boxes", "s4_bset_contains",
            "s4_bset_equal", "s4_level_create", "s4_level_destroy", "s4_level_info", "s4_level_pieces",
@@ -94,6 +94,7 @@ def lib():
     L.s4_tune.argtypes = [vp, i, BP, i, i, vp, sz, vp]
     L.s4_get_choice.argtypes = [vp, i, BP, i, ctypes.POINTER(i)]
     L.s4_set_choice.argtypes = [vp, i, BP, i, i]
+    L.s4_tune_cache_lookup.argtypes = [ctypes.c_char_p, ctypes.c_char_p, i, BP, i, i, ctypes.POINTER(i)]
     L.s4_copy.argtypes = [vp, vp, vp, sz, vp]
     L.s4_set_online_tuning.argtypes = [vp, i, d, ctypes.c_uint64]
     L.s4_online_simulate.argtypes = [i, BP, i, ctypes.POINTER(d), i, d, d, ctypes.c_uint64, i, i,
@@ -373,6 +374,16 @@ def s4_set_choice(ctx, op, boxes, candidate):
     _check(lib().s4_set_choice(ctx.handle, op, arr, n, int(candidate)))
 
 
+def s4_tune_cache_lookup(path, device, op, boxes, level=False) -> int:
+    """Candidate a context on `device` would take from the cache file at
+    `path` for this loop setup, or -1 (host only)."""
+    arr, n = _boxes(boxes)
+    out = ctypes.c_int()
+    _check(lib().s4_tune_cache_lookup(os.fsencode(path), device.encode(), int(op), arr, n, int(bool(level)),
+                                      ctypes.byref(out)))
+    return out.value
+
+
 def s4_set_online_tuning(ctx, enable=True, restart_prob=0.02, seed=1):
     _check(lib().s4_set_online_tuning(ctx.handle, int(bool(enable)), float(restart_prob), int(seed)))
 
@@ -551,3 +562,5 @@ def s4_level_rk4(ctx, level: Level, u, rho, c2, dt, nsteps, mode=S4_GRAPH, ws=No
 
 
 lib()  # fail at import when the HIP library is missing: there is no other implementation
+
+from .tensors import BoxSet, default_context, deriv_mixed, fill_ghosts, rk4, wave_rhs  # noqa: E402

@@ -9,8 +9,11 @@
 // measured timings replace them with faster candidates: either an explicit
 // sweep (s4_tune) or, as in the paper, on-line random-restart hill climbing
 // inside the calls (s4_set_online_tuning).  Sweep results persist in a JSON
-// file (the paper's "save and restore execution parameter settings",
-// Sec. III-C).
+// file, the keeping of tuned parameters across runs that the paper proposes
+// as future work (Sec. III-C).  Each entry names its candidate by its
+// parameters, so a file written against another candidate table is read
+// safely: entries that match no candidate, or one the op cannot run on
+// those boxes, are dropped.
 
 #include <hip/hip_runtime.h>
 
@@ -183,7 +186,23 @@ static int kernel_op(int op)
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr; // recorded after the entry's latest launches
+    uint64_t used = 0;         // context tick of the latest use (LRU eviction)
 };
+
+// Wait for an entry's launches, then free it.
+static void graph_free(GraphEntry &ge)
+{
+    if (ge.done) {
+        (void)hipEventSynchronize(ge.done);
+        (void)hipEventDestroy(ge.done);
+    }
+    if (ge.exec)
+        (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph)
+        (void)hipGraphDestroy(ge.graph);
+    ge = GraphEntry{};
+}
 
 // ---------------------------------------------------------------------------
 // On-line tuning of one loop setup: the paper's run-time random-restart hill
@@ -303,6 +322,7 @@ struct s4_ctx {
     std::map<std::string, int> tuned;
     std::map<std::string, int> forced;
     std::map<std::string, GraphEntry> graphs;
+    uint64_t graph_tick = 0;
     bool online = false; // on-line hill climbing of every loop setup
     double restart_prob = 0.02;
     uint64_t seed = 1;
@@ -312,16 +332,21 @@ struct s4_ctx {
 
 // c2: RK4 calls that pass a variable c^2 (one more field read per point
 // and different register pressure) form a loop setup of their own
-static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool c2 = false)
+static std::string setup_key_on(const std::string &device, int op, const s4_box *b, int nbox, bool c2 = false)
 {
     std::ostringstream o;
-    o << "op" << op << "|" << ctx->name << "|" << nbox;
+    o << "op" << op << "|" << device << "|" << nbox;
     for (int i = 0; i < nbox; ++i)
         o << "|" << b[i].n[0] << "," << b[i].n[1] << "," << b[i].n[2] << ",g" << b[i].ghost << ",s"
           << b[i].stride[1] << "," << b[i].stride[2];
     if (c2)
         o << "|c2";
     return o.str();
+}
+
+static std::string setup_key(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool c2 = false)
+{
+    return setup_key_on(ctx->name, op, b, nbox, c2);
 }
 
 // whether an RK4 call passes c^2 for any box
@@ -554,6 +579,16 @@ static std::vector<int> allowed_cands(int op, const s4_box *b, int nbox, bool le
     return v;
 }
 
+// whether a tuned or loaded choice ci can serve op on these boxes (as a
+// level: level-capable candidates only)
+static bool cand_valid(int ci, int op, const s4_box *b, int nbox, bool level)
+{
+    if (ci < 0 || ci >= (int)cands().size())
+        return false;
+    const Cand &c = cands()[ci];
+    return cand_allowed(c, op, nbox) && cand_fits(c, b, nbox) && (!level || level_capable(c));
+}
+
 // setup key of the RK4 steps of a level: the boxes' key, marked, so that a
 // level keeps its own choice among the level-capable candidates
 static const char *const LEVEL_SUFFIX = "|level";
@@ -576,7 +611,9 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
     OnlineSetup &st = ctx->online_state[key];
     st.hill.allowed = allowed_cands(op, b, nbox, level);
     auto t = ctx->tuned.find(key);
-    st.hill.start = t != ctx->tuned.end() ? t->second : heuristic(ctx, op, b, nbox, level);
+    st.hill.start = t != ctx->tuned.end() && cand_valid(t->second, op, b, nbox, level)
+                        ? t->second
+                        : heuristic(ctx, op, b, nbox, level);
     st.hill.restart_prob = ctx->restart_prob;
     st.hill.rng ^= ctx->seed * 0xD1342543DE82EF95ull + std::hash<std::string>()(key);
     return st;
@@ -608,7 +645,7 @@ static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek =
     }
     for (const std::string &k : {key, bkey}) {
         auto t = ctx->tuned.find(k);
-        if (t != ctx->tuned.end() && ok(t->second))
+        if (t != ctx->tuned.end() && cand_valid(t->second, op, b, nbox, level))
             return {t->second, 1, key};
     }
     return {heuristic(ctx, op, b, nbox, level), 0, key};
@@ -1101,12 +1138,8 @@ void s4_destroy(s4_ctx *ctx)
         for (hipEvent_t e : kv.second.pool)
             (void)hipEventDestroy(e);
     }
-    for (auto &kv : ctx->graphs) {
-        if (kv.second.exec)
-            (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph)
-            (void)hipGraphDestroy(kv.second.graph);
-    }
+    for (auto &kv : ctx->graphs)
+        graph_free(kv.second);
     if (ctx->cap)
         (void)hipStreamDestroy(ctx->cap);
     delete ctx;
@@ -1531,18 +1564,19 @@ static std::string graph_key(const s4_box *b, int nbox, double *const *u, double
 
 // Replay a captured piece of work nrep times on stream s.  The capture is
 // made once per key (recorded on the context's private stream) and cached
-// in the context; the cache is bounded by dropping every entry at 64.
+// in the context, at most GRAPH_CACHE entries: the least recently used one
+// is dropped, once the launches recorded before its event have run.  The
+// launches are enqueued with the context's lock held, so no other thread
+// drops the entry in between.
+static const size_t GRAPH_CACHE = 64;
+
 static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<int(hipStream_t)> &record, int nrep,
                      hipStream_t s)
 {
-    GraphEntry ge;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        auto it = ctx->graphs.find(key);
-        if (it != ctx->graphs.end())
-            ge = it->second;
-    }
-    if (!ge.exec) {
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    if (ctx->graphs.find(key) == ctx->graphs.end()) {
+        lk.unlock();
+        GraphEntry ge;
         S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
         int r = record(ctx->cap);
         hipGraph_t g = nullptr;
@@ -1554,26 +1588,36 @@ static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<in
         }
         if (e != hipSuccess)
             return hip_fail(e, "hipStreamEndCapture");
+        ge.graph = g;
         e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
         if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
+            graph_free(ge);
             return hip_fail(e, "hipGraphInstantiate");
         }
-        ge.graph = g;
         if (g_timer)
             g_timer->restart();
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->graphs.size() >= 64) {
-            for (auto &kv : ctx->graphs) {
-                (void)hipGraphExecDestroy(kv.second.exec);
-                (void)hipGraphDestroy(kv.second.graph);
+        lk.lock();
+        if (ctx->graphs.find(key) != ctx->graphs.end()) {
+            graph_free(ge); // another thread captured the same work meanwhile
+        } else {
+            while (ctx->graphs.size() >= GRAPH_CACHE) {
+                auto lru = ctx->graphs.begin();
+                for (auto it = ctx->graphs.begin(); it != ctx->graphs.end(); ++it)
+                    if (it->second.used < lru->second.used)
+                        lru = it;
+                graph_free(lru->second);
+                ctx->graphs.erase(lru);
             }
-            ctx->graphs.clear();
+            ctx->graphs[key] = ge;
         }
-        ctx->graphs[key] = ge;
     }
+    GraphEntry &ge = ctx->graphs[key];
+    ge.used = ++ctx->graph_tick;
     for (int k = 0; k < nrep; ++k)
         S4_HIP(hipGraphLaunch(ge.exec, s));
+    S4_HIP(hipEventRecord(ge.done, s));
     return S4_OK;
 }
 
@@ -2395,8 +2439,10 @@ int s4_copy(s4_ctx *ctx, void *dst, const void *src, size_t bytes, void *stream)
         return fail(S4_EALIAS, "copy source and destination overlap");
     if (bytes == 0)
         return S4_OK;
-    const int grid = ctx->ncu * 8;
-    hipError_t e = launch_copy(dst, src, bytes, grid, (hipStream_t)stream);
+    // one lane per 16 bytes; a launch holds fewer than 2^32 lanes
+    if (bytes / 16 > (size_t)0xffffff00u)
+        return fail(S4_EINVAL, "copy of %zu bytes exceeds one launch (64 GiB)", bytes);
+    hipError_t e = launch_copy(dst, src, bytes, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "copy launch");
     return S4_OK;
@@ -2628,28 +2674,76 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
 }
 
 // JSON cache: {"<setup key>": candidate index, ...}; keys contain no quotes.
-static void load_cache(s4_ctx *ctx)
+// A candidate in the cache file: its parameters, "v<variant> x<tx> w<waves>
+// z<chunk> r<rows>", so an entry keeps its meaning when the candidate list
+// changes between builds.
+static std::string cand_tag(const Cand &c)
 {
-    std::ifstream f(ctx->cache_path);
-    if (!f)
-        return;
-    std::stringstream ss;
-    ss << f.rdbuf();
-    const std::string t = ss.str();
+    std::ostringstream o;
+    o << "v" << c.variant << " x" << c.tx << " w" << c.nw << " z" << c.tz << " r" << c.ry;
+    return o.str();
+}
+
+// index of the candidate with this tag, -1 if none
+static int cand_from_tag(const std::string &tag)
+{
+    for (size_t i = 0; i < cands().size(); ++i)
+        if (cand_tag(cands()[i]) == tag)
+            return (int)i;
+    return -1;
+}
+
+// Entries "key": "tag" of a cache file, mapped to candidate indices; entries
+// whose value is not a string naming a current candidate (an index written
+// by an older build, a candidate no longer built) are left out.
+static std::map<std::string, int> parse_cache(const std::string &t)
+{
+    std::map<std::string, int> out;
     size_t p = 0;
     while ((p = t.find('"', p)) != std::string::npos) {
-        size_t q = t.find('"', p + 1);
+        const size_t q = t.find('"', p + 1);
         if (q == std::string::npos)
             break;
-        std::string key = t.substr(p + 1, q - p - 1);
-        size_t colon = t.find(':', q);
-        if (colon == std::string::npos)
+        const std::string key = t.substr(p + 1, q - p - 1);
+        size_t v = t.find_first_not_of(" \t\r\n:", q + 1);
+        if (v == std::string::npos)
             break;
-        int v = atoi(t.c_str() + colon + 1);
-        if (v >= 0 && v < (int)cands().size())
-            ctx->tuned[key] = v;
-        p = colon + 1;
+        if (t[v] != '"') { // not a tag: skip to the next entry
+            const size_t comma = t.find_first_of(",}", v);
+            if (comma == std::string::npos)
+                break;
+            p = comma + 1;
+            continue;
+        }
+        const size_t ve = t.find('"', v + 1);
+        if (ve == std::string::npos)
+            break;
+        const int ci = cand_from_tag(t.substr(v + 1, ve - v - 1));
+        if (ci >= 0)
+            out[key] = ci;
+        p = ve + 1;
     }
+    return out;
+}
+
+static bool read_file(const std::string &path, std::string &out)
+{
+    std::ifstream f(path);
+    if (!f)
+        return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    out = ss.str();
+    return true;
+}
+
+static void load_cache(s4_ctx *ctx)
+{
+    std::string t;
+    if (!read_file(ctx->cache_path, t))
+        return;
+    for (auto &kv : parse_cache(t))
+        ctx->tuned[kv.first] = kv.second;
 }
 
 static void save_cache(s4_ctx *ctx)
@@ -2661,10 +2755,38 @@ static void save_cache(s4_ctx *ctx)
     f << "{\n";
     size_t k = 0;
     for (auto &kv : ctx->tuned)
-        f << "  \"" << kv.first << "\": " << kv.second << (++k < ctx->tuned.size() ? ",\n" : "\n");
+        f << "  \"" << kv.first << "\": \"" << cand_tag(cands()[(size_t)kv.second]) << "\""
+          << (++k < ctx->tuned.size() ? ",\n" : "\n");
     f << "}\n";
     f.close();
     std::rename((ctx->cache_path + ".tmp").c_str(), ctx->cache_path.c_str());
+}
+
+int s4_tune_cache_lookup(const char *path, const char *device, int op, const s4_box *b, int nbox, int level,
+                         int *candidate)
+{
+    if (!path || !device || !candidate)
+        return fail(S4_EINVAL, "NULL argument");
+    *candidate = -1;
+    bool c2 = false;
+    int r = split_op(op, c2);
+    if (r)
+        return r;
+    if (kernel_op(op) < 0)
+        return fail(S4_EINVAL, "op %d has no tunable kernel", op);
+    if ((r = check_boxes(b, nbox, op)))
+        return r;
+    if (level && op != S4_OP_RK4)
+        return fail(S4_EINVAL, "levels keep RK4 choices only");
+    std::string t;
+    if (!read_file(path, t))
+        return fail(S4_EINVAL, "cannot read %s", path);
+    const auto m = parse_cache(t);
+    const std::string key = setup_key_on(device, op, b, nbox, c2) + (level ? LEVEL_SUFFIX : "");
+    auto it = m.find(key);
+    if (it != m.end() && cand_valid(it->second, op, b, nbox, level != 0))
+        *candidate = it->second;
+    return S4_OK;
 }
 
 } // extern "C"

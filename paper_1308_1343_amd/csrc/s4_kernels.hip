@@ -1456,19 +1456,20 @@ __global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, c
 }
 
 // ---------------------------------------------------------------------------
-// streaming copy probe (16-byte vectors, grid stride)
+// streaming copy probe: one 16-byte vector per lane and one launch-wide pass
+// (workgroup w copies bytes [4096 w, 4096 (w + 1))), non-temporal both ways.
+// Workgroups are dispatched in index order, so the waves in flight at any
+// time cover one compact window of both buffers.  On MI355X this pattern
+// streams faster than a fixed grid that strides through the buffers.
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void k_copy(dvec2 *__restrict__ dst, const dvec2 *__restrict__ src,
                                              int64_t n)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (; i < n; i += stride) {
-        dvec2 v = __builtin_nontemporal_load(src + i);
-        __builtin_nontemporal_store(v, dst + i);
-    }
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // ---------------------------------------------------------------------------
@@ -1830,10 +1831,11 @@ hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int n
     return hipGetLastError();
 }
 
-hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s)
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, s, (dvec2 *)dst, (const dvec2 *)src,
-                       (int64_t)(bytes / 16));
+    const int64_t n = (int64_t)(bytes / 16);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (dvec2 *)dst,
+                       (const dvec2 *)src, n);
     return hipGetLastError();
 }
 

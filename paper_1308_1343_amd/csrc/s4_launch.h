@@ -82,6 +82,6 @@ hipError_t launch_fill(const DevBox &B, hipStream_t s);
 hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int nf, int nbox, int nblocks,
                        hipStream_t s);
 
-hipError_t launch_copy(void *dst, const void *src, size_t bytes, int grid, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 } // namespace s4

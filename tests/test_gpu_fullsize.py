@@ -38,6 +38,77 @@ def test_wave256_rk4_100_steps_vs_oracle(ctx):
     assert rel(host(r), wr, g) <= 1e-12
 
 
+def find_cand(ctx, op, b, kernel_op, tile_x, threads, z_chunk):
+    """Index of the candidate with these parameters (as s4_get_choice reports them)."""
+    nc = S.s4_get_choice(ctx, op, b)["ncandidates"]
+    try:
+        for c in range(nc):
+            S.s4_set_choice(ctx, op, b, c)
+            ch = S.s4_get_choice(ctx, op, b)
+            if (ch["kernel_op"], ch["tile_x"], ch["threads"], ch["z_chunk"]) == (kernel_op, tile_x, threads, z_chunk):
+                return c
+    finally:
+        S.s4_set_choice(ctx, op, b, -1)
+    raise AssertionError(f"no candidate {kernel_op, tile_x, threads, z_chunk}")
+
+
+def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
+    """The 256^3 RHS in the tile the sweep picks for the benchmark (64 x 8
+    lanes, 64-plane chunks: kernel op 1 of the tile traversal) and in every
+    other RHS candidate, against the oracle."""
+    d = W.wave256()
+    g, n = d["ghost"], d["n"]
+    uf = O.fill_ghosts_periodic(O.embed(d["u"], g), g)
+    u = S.alloc_field(n, g, fill=float("nan"))
+    u.copy_(torch.from_numpy(uf))
+    b = S.box_of(u, g, d["dx"])
+    want = O.wave_rhs(uf, g, d["dx"])
+    tuned = find_cand(ctx, S.S4_OP_WAVE_RHS, b, 1, 64, 512, 64)
+    nc = S.s4_get_choice(ctx, S.S4_OP_WAVE_RHS, b)["ncandidates"]
+    ref = None
+    for cand in [tuned] + [c for c in range(nc) if c != tuned]:
+        out = S.alloc_field(n, g, fill=float("nan"))
+        S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, cand)
+        S.s4_wave_rhs(ctx, b, [u], None, [out])
+        got = host(out)
+        assert rel(got, want, g) <= 1e-12, f"candidate {cand}"
+        if ref is None:
+            ref = got
+        else:
+            np.testing.assert_array_equal(got[g:-g, g:-g, g:-g], ref[g:-g, g:-g, g:-g], err_msg=f"candidate {cand}")
+    S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, -1)
+
+
+def test_wave256_rk4_c2_benchmarked_setting_vs_oracle(ctx):
+    """The 256^3 RK4 with variable c^2 in the setting its sweep picks for the
+    benchmark: whole steps on 64 x 16 lanes (1024-lane workgroups, loads two
+    planes ahead) in 128-plane chunks, 20 steps against the oracle and bit for
+    bit against the per-stage kernels."""
+    d = W.wave256()
+    g, n = d["ghost"], d["n"]
+    c2h = 1.0 + 0.5 * W.uniform_pm1(d["seed"], 99, tuple(n[::-1]))
+    u, r = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
+    c2 = to_dev(c2h, n, g, fill=float("nan"))  # read at interior points only
+    b = S.box_of(u, g, d["dx"])
+    op = S.S4_OP_RK4 | S.S4_WITH_C2
+    whole = find_cand(ctx, op, b, 102, 64, 1024, 128)
+    S.s4_set_choice(ctx, op, b, whole)
+    S.s4_rk4(ctx, b, [u], [r], [c2], d["dt"], 20, "graph")
+    S.s4_set_choice(ctx, op, b, -1)
+    wu, wr = O.rk4(O.embed(d["u"], g), O.embed(d["rho"], g), g, d["dx"], d["dt"], 20, O.embed(c2h, g, 1.0))
+    gu, gr = host(u), host(r)
+    assert rel(gu, wu, g) <= 1e-12
+    assert rel(gr, wr, g) <= 1e-12
+    # the per-stage tile kernels (candidate 2) from the same inputs, bit for bit
+    u2, r2 = to_dev(d["u"], n, g), to_dev(d["rho"], n, g)
+    S.s4_set_choice(ctx, op, b, 2)
+    S.s4_rk4(ctx, b, [u2], [r2], [c2], d["dt"], 20, "graph")
+    S.s4_set_choice(ctx, op, b, -1)
+    sl = (slice(g, -g),) * 3
+    np.testing.assert_array_equal(host(u2)[sl], gu[sl])
+    np.testing.assert_array_equal(host(r2)[sl], gr[sl])
+
+
 def test_wave256_fused_pairs_match_stage_kernels(ctx):
     """Every fused stage-pair and row-register candidate against the per-stage tile kernels, bit for bit, at 256^3."""
     d = W.wave256()
