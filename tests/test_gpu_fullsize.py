@@ -38,23 +38,27 @@ def test_wave256_rk4_100_steps_vs_oracle(ctx):
     assert rel(host(r), wr, g) <= 1e-12
 
 
-def find_cand(ctx, op, b, kernel_op, tile_x, threads, z_chunk):
-    """Index of the candidate with these parameters (as s4_get_choice reports them)."""
+def find_cand(ctx, op, b, kind, tile_x, threads, z_chunk):
+    """Index of the candidate with these parameters (as s4_get_choice reports
+    them); kind "tiles" (the tile traversal: kernel op below 100) or "whole"
+    (the whole-step kernels: 102)."""
     nc = S.s4_get_choice(ctx, op, b)["ncandidates"]
     try:
         for c in range(nc):
             S.s4_set_choice(ctx, op, b, c)
             ch = S.s4_get_choice(ctx, op, b)
-            if (ch["kernel_op"], ch["tile_x"], ch["threads"], ch["z_chunk"]) == (kernel_op, tile_x, threads, z_chunk):
+            k = ch["kernel_op"]
+            if ((k < 100) if kind == "tiles" else (k == 102)) and \
+                    (ch["tile_x"], ch["threads"], ch["z_chunk"]) == (tile_x, threads, z_chunk):
                 return c
     finally:
         S.s4_set_choice(ctx, op, b, -1)
-    raise AssertionError(f"no candidate {kernel_op, tile_x, threads, z_chunk}")
+    raise AssertionError(f"no candidate {kind, tile_x, threads, z_chunk}")
 
 
 def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
     """The 256^3 RHS in the tile the sweep picks for the benchmark (64 x 8
-    lanes, 64-plane chunks: kernel op 1 of the tile traversal) and in every
+    lanes, 64-plane chunks, on the tile traversal) and in every
     other RHS candidate, against the oracle."""
     d = W.wave256()
     g, n = d["ghost"], d["n"]
@@ -63,7 +67,7 @@ def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
     u.copy_(torch.from_numpy(uf))
     b = S.box_of(u, g, d["dx"])
     want = O.wave_rhs(uf, g, d["dx"])
-    tuned = find_cand(ctx, S.S4_OP_WAVE_RHS, b, 1, 64, 512, 64)
+    tuned = find_cand(ctx, S.S4_OP_WAVE_RHS, b, "tiles", 64, 512, 64)
     nc = S.s4_get_choice(ctx, S.S4_OP_WAVE_RHS, b)["ncandidates"]
     ref = None
     for cand in [tuned] + [c for c in range(nc) if c != tuned]:
@@ -91,7 +95,7 @@ def test_wave256_rk4_c2_benchmarked_setting_vs_oracle(ctx):
     c2 = to_dev(c2h, n, g, fill=float("nan"))  # read at interior points only
     b = S.box_of(u, g, d["dx"])
     op = S.S4_OP_RK4 | S.S4_WITH_C2
-    whole = find_cand(ctx, op, b, 102, 64, 1024, 128)
+    whole = find_cand(ctx, op, b, "whole", 64, 1024, 128)
     S.s4_set_choice(ctx, op, b, whole)
     S.s4_rk4(ctx, b, [u], [r], [c2], d["dt"], 20, "graph")
     S.s4_set_choice(ctx, op, b, -1)
