@@ -205,6 +205,28 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
            const double *const *c2, double dt, int nsteps, int mode, void *workspace,
            size_t ws_bytes, void *stream);
 
+/* Bytes of the device scratch array behind s4_rk4_noalloc (one per device,
+ * held from the library's first use on that device until the process ends). */
+#define S4_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* s4_rk4 for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is the library's own static scratch array of
+ * S4_NOALLOC_SCRATCH_BYTES on the context's device instead of a caller
+ * buffer, and the call allocates nothing (no hipMalloc, hipFree, graph
+ * instantiation or timing events).  Same arguments, results and kernel sets
+ * as s4_rk4 with mode S4_PERBOX or S4_BATCHED; S4_GRAPH gives S4_ENOTSUP.
+ * Boxes whose s4_workspace_size exceeds S4_NOALLOC_SCRATCH_BYTES give
+ * S4_ENOMEM before anything is launched (one box of up to 128^3 interior
+ * points with 2 ghosts fits).  Every call on one device shares that
+ * device's array: calls that overlap on one device, on any streams or
+ * contexts, race and give undefined results; the array keeps the last
+ * call's contents, and everything a call needs zeroed it clears itself.
+ * The on-line tuner is not advanced (the current choice of the loop setup
+ * runs). */
+int s4_rk4_noalloc(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                   const double *const *c2, double dt, int nsteps, int mode, void *stream);
+
 /* One RK4 step of s4_rk4 on one periodic box, out of place: reads
  * (u_in, rho_in), writes (u_out, rho_out) at interior points; the inputs are
  * not modified and must not overlap the outputs (S4_EALIAS).  Gives the same

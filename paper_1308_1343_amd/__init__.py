@@ -37,7 +37,7 @@ MODES = {"perbox": S4_PERBOX, "batched": S4_BATCHED, "graph": S4_GRAPH}
 
 # the entry points include/sten4.h declares
 EXPORTS = ("s4_create", "s4_destroy", "s4_last_error", "s4_check_boxes", "s4_workspace_size",
-           "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_wave_adjoint_rhs",
+           "s4_fill_ghosts_periodic", "s4_wave_rhs", "s4_deriv_mixed", "s4_rk4", "s4_rk4_noalloc", "s4_wave_adjoint_rhs",
            "s4_rk4_step_to", "s4_rk4_step_to_y3", "s4_rk4_adjoint_step", "s4_rk4_adjoint_step_y3", "s4_tune", "s4_tune_scratch_size", "s4_get_choice", "s4_set_choice",
            "s4_tune_cache_lookup", "s4_set_online_tuning", "s4_online_simulate", "s4_copy",
            "s4_bset_from_boxes", "s4_bset_free", "s4_bset_op", "s4_bset_shift", "s4_bset_expand",
@@ -86,6 +86,7 @@ def lib():
     L.s4_wave_rhs.argtypes = [vp, BP, i, PP, PP, PP, vp]
     L.s4_deriv_mixed.argtypes = [vp, BP, i, PP, ctypes.POINTER(d), PP, vp]
     L.s4_rk4.argtypes = [vp, BP, i, PP, PP, PP, d, i, i, vp, sz, vp]
+    L.s4_rk4_noalloc.argtypes = [vp, BP, i, PP, PP, PP, d, i, i, vp]
     L.s4_wave_adjoint_rhs.argtypes = [vp, BP, i, PP, PP, PP, PP, PP, vp]
     L.s4_rk4_adjoint_step.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, vp, sz, vp]
     L.s4_rk4_step_to.argtypes = [vp, BP, vp, vp, vp, d, vp, vp, vp, sz, vp]
@@ -298,6 +299,17 @@ def s4_rk4(ctx, boxes, u, rho, c2, dt, nsteps, mode=S4_GRAPH, ws=None, stream=No
     _check(lib().s4_rk4(ctx.handle, arr, n, _ptrs(u), _ptrs(rho), None if c2 is None else _ptrs(c2),
                         float(dt), int(nsteps), int(mode), _ptr(ws), ws.numel(), _stream(stream)))
     return ws
+
+
+S4_NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def s4_rk4_noalloc(ctx, boxes, u, rho, c2, dt, nsteps, mode=S4_BATCHED, stream=None):
+    """s4_rk4 on the library's own scratch array (no workspace, no allocation)."""
+    arr, n = _boxes(boxes)
+    mode = MODES.get(mode, mode)
+    _check(lib().s4_rk4_noalloc(ctx.handle, arr, n, _ptrs(u), _ptrs(rho), None if c2 is None else _ptrs(c2),
+                                float(dt), int(nsteps), int(mode), _stream(stream)))
 
 
 def s4_rk4_step_to(ctx, box, u_in, rho_in, c2, dt, u_out, rho_out, ws=None, stream=None):

@@ -319,6 +319,8 @@ struct s4_ctx {
     std::string name;
     std::string cache_path;
     hipStream_t cap = nullptr; // private stream used only to capture graphs
+    void *scratch = nullptr;   // device address of s4_rk4_noalloc's array on this device
+    std::string scratch_err;   // why it has none
     std::map<std::string, int> tuned;
     std::map<std::string, int> forced;
     std::map<std::string, GraphEntry> graphs;
@@ -1062,6 +1064,15 @@ int s4_create(int device, s4_ctx **out)
     else
         c->nxcd = (c->name.rfind("gfx94", 0) == 0 || c->name.rfind("gfx95", 0) == 0) ? 8 : 1;
     (void)hipGetLastError();
+    {
+        // the device address of the no-allocation scratch array, once per device
+        hipError_t e = noalloc_scratch(&c->scratch);
+        if (e != hipSuccess) {
+            c->scratch = nullptr;
+            c->scratch_err = hipGetErrorString(e);
+            (void)hipGetLastError();
+        }
+    }
     if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(S4_EDEVICE, "cannot create the capture stream");
@@ -1685,6 +1696,29 @@ int s4_rk4(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *con
         return r;
     tm.stop((double)nsteps);
     return S4_OK;
+}
+
+int s4_rk4_noalloc(s4_ctx *ctx, const s4_box *b, int nbox, double *const *u, double *const *rho,
+                   const double *const *c2, double dt, int nsteps, int mode, void *stream)
+{
+    if (!ctx)
+        return fail(S4_EINVAL, "ctx is NULL");
+    if (!b || nbox <= 0 || nbox > (1 << 20))
+        return check_boxes(b, nbox, S4_OP_RK4);
+    if (mode == S4_GRAPH)
+        return fail(S4_ENOTSUP, "s4_rk4_noalloc runs S4_PERBOX or S4_BATCHED (S4_GRAPH instantiates a graph)");
+    if (!ctx->scratch)
+        return fail(S4_EDEVICE, "no scratch array address on device %d: %s", ctx->device, ctx->scratch_err.c_str());
+    const size_t need = rk4_fields_bytes(b, nbox) + rk4_table_bytes(nbox);
+    if (need > (size_t)S4_NOALLOC_SCRATCH_BYTES)
+        return fail(S4_ENOMEM, "these boxes need %zu bytes of scratch, s4_rk4_noalloc holds %zu (use s4_rk4)",
+                    need, (size_t)S4_NOALLOC_SCRATCH_BYTES);
+    int r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, ctx->scratch, S4_NOALLOC_SCRATCH_BYTES, need);
+    if (r || nsteps == 0)
+        return r;
+    // the loop setup's current choice without an on-line trial (no events)
+    const Choice ch = choose(ctx, S4_OP_RK4, b, nbox, true, false, has_c2(c2, nbox));
+    return rk4_run(ctx, ch, b, nbox, u, rho, c2, dt, nsteps, mode, ctx->scratch, (hipStream_t)stream);
 }
 
 // s4_rk4_step_to and s4_rk4_step_to_y3: one step out of place, optionally

@@ -14,6 +14,10 @@
 
 #include "s4_internal.h"
 #include "s4_launch.h"
+#include "sten4.h"
+
+#include <map>
+#include <mutex>
 
 namespace s4 {
 
@@ -1837,6 +1841,36 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
     hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (dvec2 *)dst,
                        (const dvec2 *)src, n);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of s4_rk4_noalloc: one array per device, zero when the code
+// object loads, held until the process ends.  Its name in host code stands
+// for the host-side shadow, not a device address, so it is never passed to
+// a kernel or a copy: noalloc_scratch looks the device address up once per
+// device (with that device current) and callers use that address.
+
+static __device__ __attribute__((aligned(256))) unsigned char scratch[S4_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
 }
 
 } // namespace s4

@@ -84,4 +84,9 @@ hipError_t launch_sync(const SyncPiece *P, const int *W, double *const *F, int n
 
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// Device address, on the current device, of the scratch array of
+// s4_rk4_noalloc (S4_NOALLOC_SCRATCH_BYTES, 256-byte aligned); looked up once
+// per device.
+hipError_t noalloc_scratch(void **ptr);
+
 } // namespace s4
