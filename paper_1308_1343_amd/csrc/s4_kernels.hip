@@ -18,6 +18,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace s4 {
 
@@ -695,14 +696,16 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     const unsigned plane_bytes = (unsigned)(B.sz * 8);
     const double a1 = K.a1, a2 = K.a2, b2 = K.b2, a3 = K.a3, b3 = K.b3, b4 = K.b4;
 
-    // column queues: planes f-4 .. f of u_n, rho_n, c^2 (u_2 at a plane is
-    // fma(a1, rho_n, u_n), formed where needed); planes f-6 .. f-2 of u_3,
-    // u_4; phase A's running sums delayed to phase B
-    double qa0 = 0, qa1 = 0, qa2 = 0, qa3 = 0, qa4 = 0;
-    double qr0 = 0, qr1 = 0, qr2 = 0, qr3 = 0, qr4 = 0;
-    double qc0 = 1, qc1 = 1, qc2 = 1, qc3 = 1, qc4 = 1;
-    double qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, qb4 = 0;
-    double qd0 = 0, qd1 = 0, qd2 = 0, qd3 = 0, qd4 = 0;
+    // Column queues, five planes each: f-4 .. f of u_n, rho_n and c^2 (u_2 at
+    // a plane is fma(a1, rho_n, u_n), formed where needed), f-6 .. f-2 of
+    // u_3 and u_4.  Step t writes the newest plane of a queue to slot t mod 5,
+    // so the planes rotate through fixed registers: the loop below is
+    // unrolled ten-fold (five queue slots times the two fetch buffers) and
+    // every slot index is a compile-time constant, with no register copies.
+    // Phase A's running sums are delayed to phase B through du0..du2 and
+    // dr0..dr2.
+    double qa[5] = {0, 0, 0, 0, 0}, qr[5] = {0, 0, 0, 0, 0}, qc[5] = {1, 1, 1, 1, 1};
+    double qb[5] = {0, 0, 0, 0, 0}, qd[5] = {0, 0, 0, 0, 0};
     double du0 = 0, du1 = 0, du2 = 0; // acc_u after stage 3
     double dr0 = 0, dr1 = 0, dr2 = 0; // acc_rho after stage 2
     double y3u = 0, y3r = 0;          // u_3, rho_3 of phase A's plane (Y3)
@@ -720,11 +723,11 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     // from two buffers used by alternate steps, so that no register a load
     // is still filling is ever copied (a copy would wait for the load).
     // With the c^2 queue on 512-lane workgroups the second buffer would
-    // cost a wavefront per SIMD (about 139 VGPRs), so those load one plane
-    // ahead; 1024-lane workgroups are held to 128 VGPRs anyway, and the
-    // plain whole-step kernel gains from it despite 7 spilled registers
-    // (C2PD2; the batched and y_3 forms would spill 17).  Plane loads go
-    // through buffer resources: one 32-bit lane offset serves every plane.
+    // cost a wavefront per SIMD, so those load one plane ahead; 1024-lane
+    // workgroups are held to 128 VGPRs anyway, and the plain whole-step
+    // kernel gains from it (C2PD2; the batched and y_3 forms would spill).
+    // Plane loads go through buffer resources: one 32-bit lane offset serves
+    // every plane.
     constexpr int PD = HASC2 && !(C2PD2 && NW * 64 == 1024) ? 1 : 2;
     struct Fetched {
         double u, r, c, hu[T::HS], hr[T::HS];
@@ -752,16 +755,20 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             }
         kz = kz + 1 == nz ? 0 : kz + 1;
     };
-    auto step = [&](const int t, Fetched &F) {
+    // step t = t0 + J with t0 a multiple of 10: queue slot of plane f - 4 + m
+    // (m = 0 .. 4) is (J + 1 + m) mod 5
+    auto step = [&](auto Jc, const int t) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int S0 = (J + 1) % 5, S1 = (J + 2) % 5, S2 = (J + 3) % 5, S3 = (J + 4) % 5, S4 = J % 5;
+        Fetched &F = PD == 2 && (J & 1) ? F1 : F0;
         const int k = t & 3;
-        const double nu = F.u, nr = F.r, nc = F.c;
-        qa0 = qa1; qa1 = qa2; qa2 = qa3; qa3 = qa4; qa4 = nu;
-        qr0 = qr1; qr1 = qr2; qr2 = qr3; qr3 = qr4; qr4 = nr;
-        if (HASC2) {
-            qc0 = qc1; qc1 = qc2; qc2 = qc3; qc3 = qc4; qc4 = nc;
-        }
-        double *R1 = ring1 + (k & 3) * 2 * P1;
-        R1[w.lc] = qa4;
+        const double nu = F.u, nr = F.r;
+        qa[S4] = nu;
+        qr[S4] = nr;
+        if (HASC2)
+            qc[S4] = F.c;
+        double *R1 = ring1 + k * 2 * P1;
+        R1[w.lc] = nu;
         R1[P1 + w.lc] = fma(a1, nr, nu);
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
@@ -780,14 +787,15 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             const double *L = ring1 + ((k + 2) & 3) * 2 * P1; // taken at step t - 2
             const double *V = L + P1;
             const int lc = w.lc;
-            const double la = lap4(B, qa2, L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
-                                   L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa0, qa1, qa3, qa4);
-            const double un = qa2, rn = qr2, u2 = fma(a1, qr2, qa2);
+            const double la = lap4(B, qa[S2], L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
+                                   L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa[S0], qa[S1], qa[S3],
+                                   qa[S4]);
+            const double un = qa[S2], rn = qr[S2], u2 = fma(a1, qr[S2], qa[S2]);
             const double lv = lap4(B, u2, V[lc - 2], V[lc - 1], V[lc + 1], V[lc + 2], V[lc - 2 * T::LX],
-                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], fma(a1, qr0, qa0),
-                                   fma(a1, qr1, qa1), fma(a1, qr3, qa3), fma(a1, qr4, qa4));
-            const double kr1 = HASC2 ? qc2 * la : la;
-            const double kr2 = HASC2 ? qc2 * lv : lv;
+                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], fma(a1, qr[S0], qa[S0]),
+                                   fma(a1, qr[S1], qa[S1]), fma(a1, qr[S3], qa[S3]), fma(a1, qr[S4], qa[S4]));
+            const double kr1 = HASC2 ? qc[S2] * la : la;
+            const double kr2 = HASC2 ? qc[S2] * lv : lv;
             const double r2 = fma(a1, kr1, rn);
             const double u3 = fma(a2, r2, un);
             const double r3 = fma(a2, kr2, rn);
@@ -798,25 +806,27 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             }
             du0 = fma(b3, r3, fma(b2, r2, fma(1.0 / 3.0, u2 - un, un)));
             dr0 = fma(b2, kr2, fma(1.0 / 3.0, r2 - rn, rn));
-            double *R2 = ring2 + (k & 3) * 2 * P2;
+            double *R2 = ring2 + k * 2 * P2;
             R2[l2] = u3;
             R2[P2 + l2] = u4;
-            qb0 = qb1; qb1 = qb2; qb2 = qb3; qb3 = qb4; qb4 = u3;
-            qd0 = qd1; qd1 = qd2; qd2 = qd3; qd3 = qd4; qd4 = u4;
+            qb[S4] = u3;
+            qd[S4] = u4;
         }
         const bool wr = out && t >= 8 && t - 8 < tz;
         double yu = 0.0, yr = 0.0;
         if (wr) {
-            // phase B (stages 3 and 4) at plane f - 4, the output tile
+            // phase B (stages 3 and 4) at plane f - 4, the output tile; u_3
+            // and u_4 of planes f - 6 .. f - 2 sit in the slots of steps
+            // t - 4 .. t, rho_n and c^2 of plane f - 4 in slot S0
             const double *L = ring2 + ((k + 2) & 3) * 2 * P2; // written at step t - 2
             const double *V = L + P2;
-            const double l3 = lap4(B, qb2, L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
-                                   L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb0, qb1, qb3, qb4);
-            const double l4 = lap4(B, qd2, V[l2 - 2], V[l2 - 1], V[l2 + 1], V[l2 + 2], V[l2 - 2 * TXE],
-                                   V[l2 - TXE], V[l2 + TXE], V[l2 + 2 * TXE], qd0, qd1, qd3, qd4);
-            const double kr3 = HASC2 ? qc0 * l3 : l3;
-            const double kr4 = HASC2 ? qc0 * l4 : l4;
-            const double r4 = fma(a3, kr3, qr0);
+            const double l3 = lap4(B, qb[S2], L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
+                                   L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb[S0], qb[S1], qb[S3], qb[S4]);
+            const double l4 = lap4(B, qd[S2], V[l2 - 2], V[l2 - 1], V[l2 + 1], V[l2 + 2], V[l2 - 2 * TXE],
+                                   V[l2 - TXE], V[l2 + TXE], V[l2 + 2 * TXE], qd[S0], qd[S1], qd[S3], qd[S4]);
+            const double kr3 = HASC2 ? qc[S0] * l3 : l3;
+            const double kr4 = HASC2 ? qc[S0] * l4 : l4;
+            const double r4 = fma(a3, kr3, qr[S0]);
             yu = fma(b4, r4, du2);
             yr = fma(b4, kr4, fma(b3, kr3, dr2));
         }
@@ -844,17 +854,29 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         }
     };
     fetch(F0);
-    if constexpr (PD == 2) {
-        if (nt > 1)
-            fetch(F1);
-        for (int t = 0; t < nt; t += 2) {
-            step(t, F0);
-            if (t + 1 < nt)
-                step(t + 1, F1);
-        }
-    } else {
-        for (int t = 0; t < nt; ++t)
-            step(t, F0);
+    if (PD == 2 && nt > 1)
+        fetch(F1);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    using I7 = std::integral_constant<int, 7>;
+    using I8 = std::integral_constant<int, 8>;
+    using I9 = std::integral_constant<int, 9>;
+    for (int t = 0; t < nt; t += 10) {
+        step(I0{}, t);
+        if (t + 1 < nt) step(I1{}, t + 1);
+        if (t + 2 < nt) step(I2{}, t + 2);
+        if (t + 3 < nt) step(I3{}, t + 3);
+        if (t + 4 < nt) step(I4{}, t + 4);
+        if (t + 5 < nt) step(I5{}, t + 5);
+        if (t + 6 < nt) step(I6{}, t + 6);
+        if (t + 7 < nt) step(I7{}, t + 7);
+        if (t + 8 < nt) step(I8{}, t + 8);
+        if (t + 9 < nt) step(I9{}, t + 9);
     }
 }
 
