@@ -73,7 +73,7 @@ def kernel_set(ch):
     """Name of the kernel set behind a tile choice (s4_get_choice's kernel op)."""
     k = ch["kernel_op"]
     return ("stage pairs" if k == 100 else "stage pairs per tap" if k == 101 else "whole steps" if k == 102
-            else "rows" if k >= 200 else "tiles")
+            else "pair-lane tiles" if k >= 300 else "rows" if k >= 200 else "tiles")
 
 
 def kernels_per_step(ch, nbox, level=False):

@@ -338,21 +338,27 @@ int s4_tune_scratch_size(const s4_box *b, int nbox, int op, size_t *bytes);
  * out[4] threads per workgroup, out[5] 1 if it came from s4_tune, 2 if
  * on-line tuning is active,
  * out[6] candidate index (with on-line tuning: the best setting so far),
- * out[7] number of candidates this op may use on
- * these boxes (candidates 0 .. out[7]-1).  out[0] is 100 or 101 when the
+ * out[7] one past the last candidate index this op may use on these boxes
+ * (the op uses those of 0 .. out[7]-1 that s4_set_choice accepts; RK4 uses
+ * all of them, the wave RHS skips the RK4-only sets).  out[0] is 100 or 101 when the
  * choice is one of RK4's two fused stage-pair kernel sets (widened tile,
  * per-tap second stage), 102 when it is the whole-step kernel set (one
- * launch per RK4 step on a tile widened by 4 points in total along x and y)
- * and 200 + the kernel op when it is
+ * launch per RK4 step on a tile widened by 4 points in total along x and y),
+ * 200 + the kernel op when it is
  * the row-register kernel set (out[1] is then the item's x extent, 64 per
- * wavefront along x, and out[2] its y extent). */
+ * wavefront along x, and out[2] its y extent), and 300 + the kernel op when
+ * it is the pair-lane tile set of the wave RHS (two x points per lane;
+ * out[1] is the tile's x extent in points; boxes with an even n[0] and even
+ * strides; a call whose fields' interior rows are not 16-byte aligned runs
+ * the same shape on the one-point tiles). */
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8]);
 
 /* Force a candidate (index into the op's candidate list) for this loop
  * setup, or -1 to drop the forced choice.  For tests that compare
  * candidates bit for bit, and for benchmark sweeps.  S4_ENOTSUP for a
  * candidate the op cannot use on these boxes (out[7] of s4_get_choice
- * bounds them; the whole-step kernels also need z planes below 2 GiB). */
+ * bounds them; the whole-step kernels also need z planes below 2 GiB, the
+ * pair-lane tiles an even n[0] and even strides). */
 int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate);
 
 /* On-line tuning: the paper's run-time random-restart hill climbing

@@ -96,9 +96,11 @@ static int hip_fail(hipError_t e, const char *where)
 // tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (any
 // number of periodic boxes, no levels) runs a whole RK4 step per pass on the
 // widened tile of variant 1, stages 1-2 on all lanes and 3-4 on the output
-// tile.  tz is the z chunk (0 = whole box; for variant 4 on one box, equal
-// shares of the tile-plane sequence).  The list is ordered so that the
-// candidates any op may use form a prefix of it.
+// tile; variant 5 (the wave RHS on boxes with an even n[0] and even
+// strides) is the tile traversal with two x points per lane, tile
+// 2 tx x (nw*64/tx).  tz is the z chunk (0 = whole box; for variant 4 on one
+// box, equal shares of the tile-plane sequence).  Candidate indices are
+// stable across ops: an op skips the candidates it cannot use.
 struct Cand {
     int tx, nw, tz;
     int variant;
@@ -126,6 +128,10 @@ static const std::vector<Cand> &cands()
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 1, 0});
+        for (int tx : {64, 32}) // pair-lane tiles: tx lanes of two points (wave RHS)
+            for (int nw : {8, 4})
+                for (int tz : {64, 32, 16})
+                    c.push_back({tx, nw, tz, 5, 0});
         return c;
     }();
     return v;
@@ -147,6 +153,8 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
         return true;
     if (c.variant == 2)
         return op == S4_OP_WAVE_RHS || op == S4_OP_RK4;
+    if (c.variant == 5)
+        return op == S4_OP_WAVE_RHS;
     if (c.variant == 3 || c.variant == 4)
         return op == S4_OP_RK4;
     return op == S4_OP_RK4 && nbox == 1; // variant 1
@@ -156,6 +164,12 @@ static bool cand_allowed(const Cand &c, int op, int nbox)
 // one z plane with 31-bit byte offsets
 static bool cand_fits(const Cand &c, const s4_box *b, int nbox)
 {
+    if (c.variant == 5) { // pair-lane tiles: 16-byte pairs along whole rows
+        for (int i = 0; i < nbox; ++i)
+            if (b[i].n[0] % 2 || b[i].stride[1] % 2 || b[i].stride[2] % 2)
+                return false;
+        return true;
+    }
     if (c.variant != 4)
         return true;
     for (int i = 0; i < nbox; ++i)
@@ -380,7 +394,7 @@ static int tile_ty(const Cand &c)
 // output tile extents in x and y
 static int out_tx(const Cand &c)
 {
-    return c.variant == 1 || c.variant == 4 ? c.tx - 4 : c.tx;
+    return c.variant == 1 || c.variant == 4 ? c.tx - 4 : c.variant == 5 ? 2 * c.tx : c.tx;
 }
 
 static int out_ty(const Cand &c)
@@ -525,6 +539,16 @@ static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool 
 {
     if (op == S4_OP_DERIV_MIXED)
         return mixed_heuristic(ctx, b[0]);
+    if (op == S4_OP_WAVE_RHS) {
+        // pair-lane tiles (two x points per lane, 128 x 8 points, 32-plane
+        // chunks) where the boxes fit them and give every CU two items
+        const int pl = cand_index(64, 8, 32, 5);
+        int64_t items = 0;
+        for (int i = 0; i < nbox; ++i)
+            items += items_of(b[i], cands()[pl]);
+        if (cand_fits(cands()[pl], b, nbox) && items >= 2 * (int64_t)ctx->ncu)
+            return pl;
+    }
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
     const int whole = cand_index(32, 8, 32, 4);
@@ -557,7 +581,7 @@ std::vector<int> Hill::neighbours(int c) const
                std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry));
     };
     std::vector<int> out;
-    int nearest[5] = {1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
+    int nearest[6] = {1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
     for (int d : allowed)
         if (cands()[d].variant != a.variant)
             nearest[cands()[d].variant] = std::min(nearest[cands()[d].variant], dist(cands()[d]));
@@ -900,6 +924,20 @@ static int64_t dev_items(const DevBox &D)
 static int launch_one(s4_ctx *ctx, int op, const Cand &c, const DevBox &D, const StageCoef &K, hipStream_t s,
                       bool ghosted = false)
 {
+    if (c.variant == 5) {
+        // pair-lane tiles need 16-byte aligned interior rows in every field;
+        // otherwise the same shape on the one-point tiles (same arithmetic)
+        auto al = [&](const double *p) { return !p || ((uintptr_t)(p + D.g) & 15) == 0; };
+        if (op == OP_RHS && al(D.in) && al(D.p[0]) && al(D.q[0])) {
+            hipError_t e = launch_pairs_rhs(c.tx, c.nw, D, (int)dev_items(D), ctx->nxcd, s);
+            return e == hipSuccess ? S4_OK : hip_fail(e, "stencil launch");
+        }
+        const Cand &c0 = cands()[cand_index(c.tx, c.nw, c.tz)];
+        DevBox D0 = D;
+        D0.tiles[0] = (D.n[0] + c0.tx - 1) / c0.tx;
+        D0.tiles[1] = (D.n[1] + tile_ty(c0) - 1) / tile_ty(c0);
+        return launch_one(ctx, op, c0, D0, K, s, ghosted);
+    }
     const int64_t items = dev_items(D);
     hipError_t e = c.variant == 2 ? launch_rows_single(op, c.tx / 64, c.ry, D, K, (int)items, ctx->nxcd, s, ghosted)
                                   : launch_tiles_single(op, c.tx, c.nw, D, K, (int)items, ctx->nxcd, s, ghosted);
@@ -1192,17 +1230,19 @@ static void fill_choice(int op, int nbox, const Choice &ch, int out[8])
              : c.variant == 3 ? 101
              : c.variant == 4 ? 102
              : c.variant == 2 ? 200 + kernel_op(op)
+             : c.variant == 5 ? 300 + kernel_op(op)
                               : kernel_op(op);
-    out[1] = c.tx;
+    out[1] = c.variant == 5 ? out_tx(c) : c.tx;
     out[2] = tile_ty(c);
     out[3] = c.tz;
     out[4] = c.nw * 64;
     out[5] = ch.tuned;
     out[6] = ch.cand;
-    int allowed = 0; // the candidates this op may use form a prefix of the list
-    while (allowed < (int)cands().size() && cand_allowed(cands()[allowed], op, nbox))
-        ++allowed;
-    out[7] = allowed;
+    int end = 0; // one past the last candidate this op may use on nbox boxes
+    for (int i = 0; i < (int)cands().size(); ++i)
+        if (cand_allowed(cands()[i], op, nbox))
+            end = i + 1;
+    out[7] = end;
 }
 
 int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
@@ -1219,7 +1259,10 @@ int s4_set_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int candidate)
         return fail(S4_ENOTSUP, "candidate %d (kernel set %d) does not apply to op %d on %d boxes", candidate,
                     cands()[candidate].variant, op, nbox);
     if (candidate >= 0 && !cand_fits(cands()[candidate], b, nbox))
-        return fail(S4_ENOTSUP, "candidate %d (whole RK4 steps) needs z planes below 2 GiB", candidate);
+        return fail(S4_ENOTSUP,
+                    "candidate %d does not fit these boxes (whole RK4 steps: z planes below 2 GiB; pair-lane "
+                    "tiles: even n[0] and strides)",
+                    candidate);
     std::lock_guard<std::mutex> lk(ctx->mu);
     const std::string key = setup_key(ctx, op, b, nbox, c2);
     if (candidate < 0)

@@ -252,6 +252,135 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_single(DevBox B, StageCoef K,
     run_item<TX, NW, WRAP, OPK>(B, P, K, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Pair-lane tiles: the tile traversal with two x points per lane, for the
+// wave RHS on boxes whose rows hold an even number of interior points and
+// start 16-byte aligned.  Every lane moves 16-byte vectors (its column, the
+// halo pairs, the c^2 pair, the output pair) and reads its x taps as two
+// 16-byte LDS words, so a wavefront covers 128 contiguous points of a row;
+// the loads of a plane are issued PD steps ahead (6, or 4 with c^2 or two
+// halo slots per lane), from PD buffers used in turn.  Per point the arithmetic is that of run_item, so both give the
+// same values bit for bit.  Tile: 2 TXL x TY points, TY = NW * 64 / TXL; the
+// halo is two full rows below and above (corner pairs included) and one pair
+// on each side of every tile row.
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+template <int TXL, int NW>
+struct PairTile {
+    static constexpr int NT = NW * 64;
+    static constexpr int TY = NT / TXL;
+    static constexpr int TXP = 2 * TXL;                // points along x
+    static constexpr int LX = TXP + 4, LY = TY + 4;    // LDS plane (doubles)
+    static constexpr int NH = 4 * (TXL + 2) + 2 * TY;  // halo pairs per plane
+    static constexpr int HS = (NH + NT - 1) / NT;      // halo slots per lane
+};
+
+template <int TXL, int NW, bool HASC2>
+__global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
+{
+    using T = PairTile<TXL, NW>;
+    // six planes of loads in flight; four where the c^2 pairs or a second
+    // halo slot would otherwise spill registers at four waves per SIMD
+    constexpr int PLANE = T::LY * T::LX, PD = HASC2 || T::HS > 1 ? 4 : 6;
+    __shared__ __attribute__((aligned(16))) double lds[2 * PLANE];
+    const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
+    const ItemPos P = item_pos(B, item, T::TXP, T::TY);
+    const int t = threadIdx.x, lx = t % TXL, ly = t / TXL;
+    const int nx = B.n[0], ny = B.n[1], nz = B.n[2], g = B.g;
+    const int i = P.x0 + 2 * lx, j = P.y0 + ly;
+    const bool active = i < nx && j < ny; // nx is even: the pair (i, i + 1) is inside or outside together
+    // readable pair origins: x up to nx (the pair nx, nx + 1 is a ghost pair), y up to ny + 1
+    const int64_t col = (int64_t)((i < nx ? i : nx) + g) + (int64_t)((j < ny + 1 ? j : ny + 1) + g) * B.sy;
+    const int lc = (ly + 2) * T::LX + 2 * lx + 2;
+    int hl[T::HS];
+    int64_t hcol[T::HS];
+#pragma unroll
+    for (int s = 0; s < T::HS; ++s) {
+        int h = t + s * T::NT;
+        hl[s] = -1;
+        hcol[s] = 0;
+        if (h < T::NH) {
+            int row, pc; // LDS row and pair column
+            constexpr int RP = TXL + 2; // pairs per full row
+            if (h < 4 * RP) {
+                row = h / RP;
+                row = row < 2 ? row : T::TY + row; // rows 0, 1 and TY + 2, TY + 3
+                pc = h % RP;
+            } else {
+                const int e = h - 4 * RP;
+                row = 2 + e / 2;
+                pc = e % 2 ? RP - 1 : 0;
+            }
+            hl[s] = row * T::LX + 2 * pc;
+            const int gx = P.x0 - 2 + 2 * pc, gy = P.y0 - 2 + row;
+            hcol[s] = (int64_t)((gx < nx ? gx : nx) + g) + (int64_t)((gy < ny + 1 ? gy : ny + 1) + g) * B.sy;
+        }
+    }
+    const double *in = B.in;
+    const double *c2 = HASC2 ? B.p[0] : nullptr;
+    auto zo = [&](int k) { return (int64_t)((k < nz + 1 ? k : nz + 1) + g) * B.sz; };
+    auto ld2 = [&](const double *p) { return *(const dvec2 *)p; };
+    struct Fetched {
+        dvec2 q4, h[T::HS], c;
+    };
+    auto fetch = [&](int k, Fetched &X) {
+        X.q4 = ld2(in + col + zo(k + 2));
+        const int64_t z = zo(k);
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (hl[s] >= 0)
+                X.h[s] = ld2(in + hcol[s] + z);
+        if (HASC2 && active)
+            X.c = __builtin_nontemporal_load((const dvec2 *)(c2 + col + z));
+    };
+    dvec2 q0 = 0.0, q1 = ld2(in + col + zo(P.z0 - 2)), q2 = ld2(in + col + zo(P.z0 - 1)),
+          q3 = ld2(in + col + zo(P.z0)), q4 = ld2(in + col + zo(P.z0 + 1));
+    Fetched F[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+        F[p].c = 0.0;
+        if (P.z0 + p < P.z1)
+            fetch(P.z0 + p, F[p]);
+    }
+    auto step = [&](const int k, Fetched &X) {
+        q0 = q1;
+        q1 = q2;
+        q2 = q3;
+        q3 = q4;
+        q4 = X.q4;
+        double *L = lds + ((k - P.z0) & 1) * PLANE;
+        *(dvec2 *)(L + lc) = q2;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (hl[s] >= 0)
+                *(dvec2 *)(L + hl[s]) = X.h[s];
+        const dvec2 cc = X.c;
+        if (k + PD < P.z1)
+            fetch(k + PD, X);
+        lds_barrier();
+        if (active) {
+            const dvec2 xm = *(const dvec2 *)(L + lc - 2), xp = *(const dvec2 *)(L + lc + 2);
+            const dvec2 ym2 = *(const dvec2 *)(L + lc - 2 * T::LX), ym1 = *(const dvec2 *)(L + lc - T::LX);
+            const dvec2 yp1 = *(const dvec2 *)(L + lc + T::LX), yp2 = *(const dvec2 *)(L + lc + 2 * T::LX);
+            dvec2 r;
+            r.x = lap4(B, q2.x, xm.x, xm.y, q2.y, xp.x, ym2.x, ym1.x, yp1.x, yp2.x, q0.x, q1.x, q3.x, q4.x);
+            r.y = lap4(B, q2.y, xm.y, q2.x, xp.x, xp.y, ym2.y, ym1.y, yp1.y, yp2.y, q0.y, q1.y, q3.y, q4.y);
+            if (HASC2) {
+                r.x = cc.x * r.x;
+                r.y = cc.y * r.y;
+            }
+            __builtin_nontemporal_store(r, (dvec2 *)(B.q[0] + col + zo(k)));
+        }
+    };
+    for (int k = P.z0; k < P.z1; k += PD) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            if (k + p < P.z1)
+                step(k + p, F[p]);
+    }
+}
+
 // next item of the calling workgroup (thread 0 only), see queue_next
 __device__ inline int queue_take(const ItemQueue &Q, int &q, int &left)
 {
@@ -1488,7 +1617,6 @@ __global__ __launch_bounds__(256) void k_sync(const SyncPiece *__restrict__ P, c
 // time cover one compact window of both buffers.  On MI355X this pattern
 // streams faster than a fixed grid that strides through the buffers.
 
-typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void k_copy(dvec2 *__restrict__ dst, const dvec2 *__restrict__ src,
                                              int64_t n)
@@ -1557,6 +1685,23 @@ hipError_t launch_tiles_batched(int op, int tx, int nw, const DevBox *tab, int n
     if (tx == TX_ && nw == NW_ && wrap == W_ && op == O_)                                              \
         return launch_batched_t<TX_, NW_, W_, O_>(tab, nbox, Q, grid, K, s);
     S4_FOR_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pairs_rhs(int txl, int nw, const DevBox &B, int nitems, int nxcd, hipStream_t s)
+{
+#define X(TXL_, NW_)                                                                                   \
+    if (txl == TXL_ && nw == NW_) {                                                                    \
+        if (B.p[0])                                                                                    \
+            hipLaunchKernelGGL((k_pairs_rhs<TXL_, NW_, true>), dim3(nitems), dim3(NW_ * 64), 0, s, B,  \
+                               nxcd);                                                                  \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_pairs_rhs<TXL_, NW_, false>), dim3(nitems), dim3(NW_ * 64), 0, s, B, \
+                               nxcd);                                                                  \
+        return hipGetLastError();                                                                      \
+    }
+    X(64, 8) X(64, 4) X(32, 8) X(32, 4)
 #undef X
     return hipErrorInvalidValue;
 }

@@ -30,6 +30,11 @@ hipError_t launch_rows_batched(int op, int wx, int ry, const DevBox *tab, int nb
                                int grid, const StageCoef &K, hipStream_t s, bool ghosted = false);
 int max_blocks_rows(int op, int wx, int ry, bool ghosted = false);
 
+// Wave RHS (OP_RHS, ghosts read) on pair-lane tiles: txl lanes of two x
+// points each along x, nw wavefronts.  Needs an even n[0], even strides and
+// 16-byte aligned interior row starts of every field.
+hipError_t launch_pairs_rhs(int txl, int nw, const DevBox &B, int nitems, int nxcd, hipStream_t s);
+
 // Multi-field mixed-derivative kernel over fields [0, nfield) of M (nfield <= 8);
 // one workgroup per (field, tile) item.
 hipError_t launch_mixed(int tx, int nw, const MixArgs &M, int nfield, int nxcd, hipStream_t s);

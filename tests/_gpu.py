@@ -48,13 +48,19 @@ def ghosts_untouched(a, g):
 
 def cands_by_kind(ctx, op, boxes):
     """Candidate indices this op may use on these boxes, by kernel set:
-    "tiles" (LDS tile traversal), "rows" (row-register traversal), "fused"
-    (both RK4 stage-pair sets and the whole-step kernels)."""
+    "tiles" (LDS tile traversal), "rows" (row-register traversal), "pairs"
+    (pair-lane tiles of the RHS), "fused" (both RK4 stage-pair sets and the
+    whole-step kernels)."""
     nc = S.s4_get_choice(ctx, op, boxes)["ncandidates"]
-    out = {"tiles": [], "rows": [], "fused": []}
+    out = {"tiles": [], "rows": [], "pairs": [], "fused": []}
     for c in range(nc):
-        S.s4_set_choice(ctx, op, boxes, c)
+        try:
+            S.s4_set_choice(ctx, op, boxes, c)
+        except S.Sten4Error as e:  # a candidate these boxes do not fit
+            assert e.code == S.S4_ENOTSUP
+            continue
         k = S.s4_get_choice(ctx, op, boxes)["kernel_op"]
-        out["fused" if k in (100, 101, 102) else "rows" if k >= 200 else "tiles"].append(c)
+        out["fused" if k in (100, 101, 102) else "pairs" if k >= 300 else "rows" if k >= 200
+            else "tiles"].append(c)
     S.s4_set_choice(ctx, op, boxes, -1)
     return out

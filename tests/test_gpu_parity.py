@@ -76,8 +76,9 @@ def test_wave32_rhs_and_candidates_bitwise(ctx):
     b = S.box_of(u, g, d["dx"])
     want = O.wave_rhs(a, g, d["dx"])
     ref = None
-    nc = S.s4_get_choice(ctx, S.S4_OP_WAVE_RHS, b)["ncandidates"]
-    for cand in range(nc):
+    k = cands_by_kind(ctx, S.S4_OP_WAVE_RHS, b)
+    assert k["pairs"] and not k["fused"]
+    for cand in k["tiles"] + k["rows"] + k["pairs"]:
         S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, cand)
         out = S.alloc_field(d["n"], g, fill=NAN)
         S.s4_wave_rhs(ctx, b, [u], None, [out])

@@ -9,13 +9,14 @@ import paper_1308_1343_amd as S
 
 # the library's candidate list, in its order (variant, tx, nw, tz, ry): one kernel per stage
 # on the tile traversal, on the row-register traversal, stage pairs per tap, whole steps,
-# widened stage pairs
+# widened stage pairs, pair-lane tiles (RHS only)
 CANDS = [(0, tx, nw, tz, 0) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0, 64, 32, 16, 8)] + \
         [(2, tx, 4, tz, ry) for tx in (256, 128, 64) for ry in (4, 2) for tz in (64, 32, 16)] + \
         [(3, tx, nw, tz, 0) for tx, nw in ((64, 4), (64, 8), (32, 8), (32, 4), (16, 8), (16, 4))
          for tz in (64, 32, 16)] + \
         [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8)) for tz in (0, 128, 64, 32, 16)] + \
-        [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)]
+        [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)] + \
+        [(5, tx, nw, tz, 0) for tx in (64, 32) for nw in (8, 4) for tz in (64, 32, 16)]
 ORD_TX = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}
 ORD_NW = {4: 0, 8: 1, 16: 2}
 ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 128: 4, 0: 5}
@@ -36,12 +37,20 @@ def bowl(center, slope=0.05, other_variant=2.0):
 def test_candidate_table_matches_library():
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, [1.0] * len(CANDS), ncalls=3)
     assert all(0 <= t < len(CANDS) for t in tr)
-    for op, n in ((S.S4_OP_WAVE_RHS, 48), (S.S4_OP_ADJOINT_STEP, 30)):
-        tr = S.s4_online_simulate(op, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400, restart_prob=0.2)
-        assert max(tr) < n  # stage pairs only for RK4, row kernels only for the RHS and RK4
+    first = {v: min(k for k, c in enumerate(CANDS) if c[0] == v) for v in (2, 3, 1, 5)}
+    rk4_only = set(range(first[3], first[5]))
+    tr = S.s4_online_simulate(S.S4_OP_WAVE_RHS, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400,
+                              restart_prob=0.2)
+    assert not rk4_only & set(tr)  # stage pairs and whole steps only for RK4
+    assert any(t >= first[5] for t in tr)  # the RHS reaches its pair-lane tiles
+    tr = S.s4_online_simulate(S.S4_OP_ADJOINT_STEP, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400,
+                              restart_prob=0.2)
+    assert max(tr) < first[2]  # row kernels only for the RHS and RK4
+    tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, list(np.linspace(1, 2, len(CANDS))), ncalls=400, restart_prob=0.2)
+    assert max(tr) < first[5]  # pair-lane tiles only for the RHS
     tr = S.s4_online_simulate(S.S4_OP_RK4, [BOX, BOX], list(np.linspace(1, 2, len(CANDS))), ncalls=400,
                               restart_prob=0.2)
-    assert max(tr) < 81  # widened stage pairs only on one box
+    assert max(tr) < first[1]  # widened stage pairs only on one box
 
 
 def test_converges_on_a_smooth_landscape():
