@@ -513,6 +513,45 @@ def main():
         one_ms = (time.perf_counter() - t0) * 1e3 / kl
         del one_u, one_r, wso
         ch = S.s4_level_choice(ctx, lev)
+        # the same level with 4 ghost layers and a full exchange of width 4:
+        # whole RK4 steps, one exchange of (u, rho) per step
+        lw = W.level_tiling(ghost=4)
+        wus, wrs, wboxes = [], [], []
+        for bx in lw["boxes"]:
+            sl = W.box_slice(bx)
+            fu = S.alloc_field(bx["n"], 4, fill=0.0)
+            fr = S.alloc_field(bx["n"], 4, fill=0.0)
+            S.interior(fu, 4).copy_(torch.from_numpy(np.ascontiguousarray(lw["u"][sl])))
+            S.interior(fr, 4).copy_(torch.from_numpy(np.ascontiguousarray(lw["rho"][sl])))
+            wus.append(fu)
+            wrs.append(fr)
+            wboxes.append(S.box_of(fu, 4, lw["dx"]))
+        levw = S.s4_level_create(wboxes, [bx["lo"] for bx in lw["boxes"]], lw["domain"], 4, "full")
+        infow = S.s4_level_info(levw)
+        if not args.no_tune:
+            S.s4_tune(ctx, S.S4_OP_RK4, wboxes, flags=1)
+        wsw = S.workspace(S.s4_level_workspace_size(levw, S.S4_OP_RK4))
+        resw = {}
+        for mode in ("perbox", "batched", "graph"):
+            S.s4_level_rk4(ctx, levw, wus, wrs, None, lw["dt"], 4, mode, ws=wsw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            S.s4_level_rk4(ctx, levw, wus, wrs, None, lw["dt"], kl, mode, ws=wsw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            w_ = time.perf_counter() - t0
+            resw[mode] = {"ms_per_step": round(w_ * 1e3 / kl, 4),
+                          "gpoint_steps_per_s": round(lpts * kl / w_ / 1e9, 2),
+                          "event_ms_per_step": round(e0.elapsed_time(e1) / kl, 4)}
+        chw = S.s4_level_choice(ctx, levw)
+        wide = {"workload": "level60 with 4 ghost layers, full exchange of width 4 before every RK4 step",
+                "modes": resw, "schedule_pieces": infow["pieces"],
+                "ghost_points_per_exchange": infow["filled"], "exchange_bytes": 2 * 16 * infow["filled"],
+                "level_graph_over_single_box": round(resw["graph"]["ms_per_step"] / one_ms, 3),
+                "tile": [chw["tile_x"], chw["tile_y"], chw["z_chunk"], chw["threads"]],
+                "kernel_set": kernel_set(chw), "launches_per_step": kernels_per_step(chw, len(wboxes), level=True)}
+        del wus, wrs, wsw
         out["level"] = {"workload": "level60: 60 boxes, sides U[16,96], g=3, tiling a 280x224x168 periodic domain, "
                                     "face exchange of width 2 before every RK4 stage",
                         "interior_points": lpts, "steps": kl, "modes": res,
@@ -523,7 +562,8 @@ def main():
                         "single_box_same_domain_ms_per_step": round(one_ms, 4),
                         "level_graph_over_single_box": round(res["graph"]["ms_per_step"] / one_ms, 3),
                         "tile": [ch["tile_x"], ch["tile_y"], ch["z_chunk"], ch["threads"]], "kernel_set": kernel_set(ch),
-                        "launches_per_step": kernels_per_step(ch, len(lboxes), level=True)}
+                        "launches_per_step": kernels_per_step(ch, len(lboxes), level=True),
+                        "wide": wide}
         log(f"[bench] level: {out['level']}")
 
     # ------------------------------------------------------------------ adjoint

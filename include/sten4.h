@@ -119,7 +119,7 @@ typedef struct {
  * choices that is read here and rewritten by s4_tune: one object mapping a
  * loop-setup key to the parameters of the chosen candidate,
  *   "op<op>|<device>|<nbox>|<nx>,<ny>,<nz>,g<ghost>,s<stride1>,<stride2>
- *    (one such group per box)[|c2][|level]": "v<variant> x<tx> w<waves>
+ *    (one such group per box)[|c2][|level or |level4]": "v<variant> x<tx> w<waves>
  *    z<z chunk> r<rows>".
  * Entries that name no candidate of this build, or a candidate the setup's
  * op cannot run on its boxes, are ignored (the heuristic applies). */
@@ -325,8 +325,9 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
  * *candidate = the candidate index a context on device `device` (its
  * architecture name, e.g. "gfx950") would take from that file for `op`
  * (with S4_WITH_C2 for RK4 calls that pass c^2) on these boxes, as a level
- * if level != 0, or -1 when the file holds no usable entry for that setup.
- * S4_EINVAL if the file cannot be read.  No device call. */
+ * (level 1; level 2: a wide level, see s4_level_rk4) or not (level 0), or
+ * -1 when the file holds no usable entry for that setup.  S4_EINVAL if the
+ * file cannot be read.  No device call. */
 int s4_tune_cache_lookup(const char *path, const char *device, int op, const s4_box *b, int nbox, int level,
                          int *candidate);
 
@@ -505,17 +506,25 @@ int s4_level_sync(s4_ctx *ctx, const s4_level *L, double *const *f, void *worksp
  * ghost points of u and rho are overwritten by the exchanges (the stage-pair
  * kernel set exchanges both before its first pass); everything else as for
  * s4_rk4 (modes, c2, in-place update, graph cache keyed additionally by
- * the schedule). */
+ * the schedule).  On a wide level -- a schedule of shape S4_SYNC_FULL and
+ * width >= 4 over boxes with ghost >= 4 -- the whole-step kernel set also
+ * runs: one exchange of u and rho per step fills the ghost shell, from
+ * which a step reads its radius-4 neighbourhood (ghost zones deep enough to
+ * skip the exchanges between stages; Sec. II fills ghost zones by
+ * communication within a level, Sec. III-C proposes the loop fusion). */
 int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const *rho, const double *const *c2,
                  double dt, int nsteps, int mode, void *workspace, size_t ws_bytes, void *stream);
 
 /* The tile choice s4_level_rk4 uses on this level, laid out as
  * s4_get_choice's out[] (out[7]: the candidates RK4 may use on these
- * boxes).  A level runs only kernel sets whose stencils read radius-2 ghost
- * zones: a forced or tuned choice for the boxes that needs more (the
- * widened-tile sets, out[0] 100 or 102) is replaced by the fastest
- * level-capable candidate s4_tune found, else by the heuristic start.
- * Sec. III-B (a loop setup's execution parameters). */
+ * boxes).  A level runs only kernel sets whose stencils read what its
+ * exchange fills: radius-2 ghost zones, or on a wide level (see
+ * s4_level_rk4) the radius-4 neighbourhood of the whole steps.  A forced or
+ * tuned choice for the boxes that needs more (the widened-tile stage pairs,
+ * out[0] 100, always; the whole steps, 102, on other levels) is replaced by
+ * the fastest level-capable candidate s4_tune found, else by the heuristic
+ * start, which is the whole steps on a wide level.  Sec. III-B (a loop
+ * setup's execution parameters). */
 int s4_level_choice(s4_ctx *ctx, const s4_level *L, int out[8]);
 
 /* Plain device copy of `bytes` bytes (a multiple of 16, 16-byte aligned,

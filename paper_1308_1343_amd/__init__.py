@@ -386,12 +386,13 @@ def s4_set_choice(ctx, op, boxes, candidate):
     _check(lib().s4_set_choice(ctx.handle, op, arr, n, int(candidate)))
 
 
-def s4_tune_cache_lookup(path, device, op, boxes, level=False) -> int:
+def s4_tune_cache_lookup(path, device, op, boxes, level=0) -> int:
     """Candidate a context on `device` would take from the cache file at
-    `path` for this loop setup, or -1 (host only)."""
+    `path` for this loop setup (level 0: the boxes, 1: a level, 2: a wide
+    level), or -1 (host only)."""
     arr, n = _boxes(boxes)
     out = ctypes.c_int()
-    _check(lib().s4_tune_cache_lookup(os.fsencode(path), device.encode(), int(op), arr, n, int(bool(level)),
+    _check(lib().s4_tune_cache_lookup(os.fsencode(path), device.encode(), int(op), arr, n, int(level),
                                       ctypes.byref(out)))
     return out.value
 

@@ -178,11 +178,18 @@ static bool cand_fits(const Cand &c, const s4_box *b, int nbox)
     return true;
 }
 
-// whether candidate c can run RK4 on a level (ghost-addressed stencils of
-// radius 2; the widened-tile sets need radius 4 or wrap around one box)
-static bool level_capable(const Cand &c)
+// Levels: 1 = a level whose exchanges fill ghost zones of width 2 or 3
+// (ghost-addressed stencils of radius 2), 2 = a wide level (exchanges of
+// the full ghost shell of width 4 or more, every box with 4 or more ghost
+// layers), on which a whole RK4 step reads its radius-4 neighbourhood from
+// the ghost zones after one exchange per step.
+static const int LEVEL_NARROW = 1, LEVEL_WIDE = 2;
+
+// whether candidate c can run RK4 on a level of that kind: the widened-tile
+// stage pairs wrap around one box; the whole steps need a wide level
+static bool level_capable(const Cand &c, int level)
 {
-    return c.variant != 1 && c.variant != 4;
+    return c.variant != 1 && (c.variant != 4 || level == LEVEL_WIDE);
 }
 
 static int kernel_op(int op)
@@ -535,7 +542,7 @@ static int mixed_heuristic(const s4_ctx *ctx, const s4_box &b)
     return cand_index(tx, nw, 8);
 }
 
-static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool level = false)
+static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, int level = 0)
 {
     if (op == S4_OP_DERIV_MIXED)
         return mixed_heuristic(ctx, b[0]);
@@ -552,7 +559,7 @@ static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, bool 
     if (op != S4_OP_RK4)
         return tile_heuristic(ctx, b, nbox);
     const int whole = cand_index(32, 8, 32, 4);
-    if (!level && cand_fits(cands()[whole], b, nbox))
+    if (level != LEVEL_NARROW && cand_fits(cands()[whole], b, nbox))
         return nbox == 1 ? step4_single(ctx, b[0]) : whole;
     double pts = 0, lanes = 0;
     for (int i = 0; i < nbox; ++i) {
@@ -595,29 +602,35 @@ std::vector<int> Hill::neighbours(int c) const
     return out;
 }
 
-static std::vector<int> allowed_cands(int op, const s4_box *b, int nbox, bool level = false)
+static std::vector<int> allowed_cands(int op, const s4_box *b, int nbox, int level = 0)
 {
     std::vector<int> v;
     for (int i = 0; i < (int)cands().size(); ++i)
         if (cand_allowed(cands()[i], op, nbox) && cand_fits(cands()[i], b, nbox) &&
-            (!level || level_capable(cands()[i])))
+            (!level || level_capable(cands()[i], level)))
             v.push_back(i);
     return v;
 }
 
 // whether a tuned or loaded choice ci can serve op on these boxes (as a
 // level: level-capable candidates only)
-static bool cand_valid(int ci, int op, const s4_box *b, int nbox, bool level)
+static bool cand_valid(int ci, int op, const s4_box *b, int nbox, int level)
 {
     if (ci < 0 || ci >= (int)cands().size())
         return false;
     const Cand &c = cands()[ci];
-    return cand_allowed(c, op, nbox) && cand_fits(c, b, nbox) && (!level || level_capable(c));
+    return cand_allowed(c, op, nbox) && cand_fits(c, b, nbox) && (!level || level_capable(c, level));
 }
 
 // setup key of the RK4 steps of a level: the boxes' key, marked, so that a
 // level keeps its own choice among the level-capable candidates
 static const char *const LEVEL_SUFFIX = "|level";
+static const char *const WIDE_LEVEL_SUFFIX = "|level4";
+
+static std::string level_key(const std::string &bkey, int level)
+{
+    return level == LEVEL_WIDE ? bkey + WIDE_LEVEL_SUFFIX : level ? bkey + LEVEL_SUFFIX : bkey;
+}
 
 struct Choice {
     int cand;
@@ -629,7 +642,7 @@ static void online_harvest(OnlineSetup &st);
 
 // caller holds ctx->mu
 static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox,
-                                 bool level)
+                                 int level)
 {
     auto it = ctx->online_state.find(key);
     if (it != ctx->online_state.end())
@@ -646,17 +659,18 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
 }
 
 // peek: report the choice without advancing the on-line tuner.  level: the
-// RK4 steps of a level (its own setup key; level-capable candidates only,
-// a forced or tuned choice of the boxes is taken if it is one)
+// RK4 steps of a level (LEVEL_NARROW or LEVEL_WIDE: its own setup key;
+// candidates capable of that level only, a forced or tuned choice of the
+// boxes is taken if it is one)
 // c2: the call passes c^2 (its own setup; a choice forced without c^2
 // applies to it too, a tuned one does not)
-static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false, bool level = false,
+static Choice choose(s4_ctx *ctx, int op, const s4_box *b, int nbox, bool peek = false, int level = 0,
                      bool c2 = false)
 {
     std::lock_guard<std::mutex> lk(ctx->mu);
     const std::string bkey = setup_key(ctx, op, b, nbox, c2);
-    const std::string key = level ? bkey + LEVEL_SUFFIX : bkey;
-    auto ok = [&](int c) { return !level || level_capable(cands()[c]); };
+    const std::string key = level_key(bkey, level);
+    auto ok = [&](int c) { return !level || level_capable(cands()[c], level); };
     for (const std::string &k : {bkey, setup_key(ctx, op, b, nbox)}) {
         auto f = ctx->forced.find(k);
         if (f != ctx->forced.end() && ok(f->second))
@@ -1197,6 +1211,19 @@ void s4_destroy(s4_ctx *ctx)
 static void fill_choice(int op, int nbox, const Choice &ch, int out[8]);
 static int level_check(const s4_level *L);
 
+// LEVEL_WIDE when the level's exchange fills the full ghost shell of width
+// 4 or more and every box has 4 or more ghost layers and z planes below
+// 2 GiB (whole RK4 steps then run on it), else LEVEL_NARROW
+static int level_kind(const s4_level *L)
+{
+    if (L->width < 4 || L->shape != S4_SYNC_FULL)
+        return LEVEL_NARROW;
+    for (const s4_box &b : L->boxes)
+        if (b.ghost < 4 || b.stride[2] * 8 >= (int64_t)0x80000000)
+            return LEVEL_NARROW;
+    return LEVEL_WIDE;
+}
+
 int s4_get_choice(s4_ctx *ctx, int op, const s4_box *b, int nbox, int out[8])
 {
     if (!ctx || !out)
@@ -1217,7 +1244,7 @@ int s4_level_choice(s4_ctx *ctx, const s4_level *L, int out[8])
     if (r)
         return r;
     const int nbox = (int)L->boxes.size();
-    fill_choice(S4_OP_RK4, nbox, choose(ctx, S4_OP_RK4, L->boxes.data(), nbox, true, true), out);
+    fill_choice(S4_OP_RK4, nbox, choose(ctx, S4_OP_RK4, L->boxes.data(), nbox, true, level_kind(L)), out);
     return S4_OK;
 }
 
@@ -2356,28 +2383,35 @@ static int pair_step(s4_ctx *ctx, const Cand &c, const std::vector<DevBox> &tab,
                      const SyncArgs *sy)
 {
     const bool gh = sy != nullptr;
-    if (c.variant == 4) { // one whole-step launch (periodic boxes only)
-        if (gh)
-            return fail(S4_ENOTSUP, "whole RK4 steps do not run on levels");
+    if (c.variant == 4) {
+        // one whole-step launch: periodic boxes, or a wide level after one
+        // exchange of (u, rho) of width 4 or more
         const StageCoef K[4] = {rk4_coef(0, dt), rk4_coef(1, dt), rk4_coef(2, dt), rk4_coef(3, dt)};
         const DevBox *T = tab.data() + (size_t)(2 * parity) * nbox;
         bool hasc2 = false;
         for (int i = 0; i < nbox; ++i) {
             if (T[i].sz * 8 >= (int64_t)0x80000000)
                 return fail(S4_ENOTSUP, "whole RK4 steps need z planes below 2 GiB (box %d)", i);
+            if (gh && T[i].g < 4)
+                return fail(S4_ENOTSUP, "whole RK4 steps on a level need 4 ghost layers (box %d)", i);
             hasc2 = hasc2 || T[i].p[5] != nullptr;
         }
         hipError_t e = hipSuccess;
+        if (gh) {
+            e = launch_sync(sy->P, sy->W, sy->F + (size_t)(2 * parity) * 2 * nbox, 2, nbox, sy->nblocks, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "ghost exchange launch");
+        }
         if (batched) {
             int per = max_blocks_step4(c.tx, c.nw);
             if (per <= 0)
                 per = 1;
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nitems, (int64_t)per * ctx->ncu));
             e = launch_rk4_step4_batched(c.tx, c.nw, hasc2, dtab + (size_t)(2 * parity) * nbox, nbox,
-                                         step_queue(ctx, counters, parity, nitems), grid, K, s);
+                                         step_queue(ctx, counters, parity, nitems), grid, K, s, gh);
         } else {
             for (int i = 0; i < nbox && e == hipSuccess; ++i)
-                e = launch_rk4_step4(c.tx, c.nw, T[i], K, step4_run(ctx, c, T[i]), ctx->nxcd, s);
+                e = launch_rk4_step4(c.tx, c.nw, T[i], K, step4_run(ctx, c, T[i]), ctx->nxcd, s, gh);
         }
         return e == hipSuccess ? S4_OK : hip_fail(e, "whole-step launch");
     }
@@ -2496,8 +2530,8 @@ int s4_level_rk4(s4_ctx *ctx, const s4_level *L, double *const *u, double *const
     if ((r = rk4_check(ctx, b, nbox, u, rho, c2, dt, nsteps, mode, workspace, ws_bytes, need)) || nsteps == 0)
         return r;
     hipStream_t s = (hipStream_t)stream;
-    const int ci = choose(ctx, S4_OP_RK4, b, nbox, true, true).cand;
-    if (cands()[ci].variant != 3)
+    const int ci = choose(ctx, S4_OP_RK4, b, nbox, true, level_kind(L)).cand;
+    if (cands()[ci].variant != 3 && cands()[ci].variant != 4)
         return level_stage_run(ctx, L, ci, u, rho, c2, dt, nsteps, mode, workspace, s);
     if ((r = pair_run(ctx, ci, b, nbox, u, rho, c2, dt, nsteps / 2 * 2, mode, workspace, s, L)) || nsteps % 2 == 0)
         return r;
@@ -2731,7 +2765,7 @@ int s4_tune(s4_ctx *ctx, int op, const s4_box *b, int nbox, int flags, void *scr
             continue;
         if (best < 0 || t[(size_t)ci] < t[(size_t)best])
             best = ci;
-        if (level_capable(cands()[ci]) && (best_level < 0 || t[(size_t)ci] < t[(size_t)best_level]))
+        if (level_capable(cands()[ci], LEVEL_NARROW) && (best_level < 0 || t[(size_t)ci] < t[(size_t)best_level]))
             best_level = ci;
     }
     (void)hipEventDestroy(e0);
@@ -2855,13 +2889,15 @@ int s4_tune_cache_lookup(const char *path, const char *device, int op, const s4_
         return r;
     if (level && op != S4_OP_RK4)
         return fail(S4_EINVAL, "levels keep RK4 choices only");
+    if (level < 0 || level > LEVEL_WIDE)
+        return fail(S4_EINVAL, "level %d is not 0, 1 or 2", level);
     std::string t;
     if (!read_file(path, t))
         return fail(S4_EINVAL, "cannot read %s", path);
     const auto m = parse_cache(t);
-    const std::string key = setup_key_on(device, op, b, nbox, c2) + (level ? LEVEL_SUFFIX : "");
+    const std::string key = level_key(setup_key_on(device, op, b, nbox, c2), level);
     auto it = m.find(key);
-    if (it != m.end() && cand_valid(it->second, op, b, nbox, level != 0))
+    if (it != m.end() && cand_valid(it->second, op, b, nbox, level))
         *candidate = it->second;
     return S4_OK;
 }

@@ -798,8 +798,12 @@ struct Step4Coef {
 };
 
 // one tile and z range of a whole step (C2PD2: with c^2, load two planes
-// ahead too where the workgroup has 1024 lanes)
-template <int TXE, int NW, bool HASC2, bool Y3, bool C2PD2 = false>
+// ahead too where the workgroup has 1024 lanes).  WRAP: the box is its own
+// periodic neighbour (stencil neighbours at wrapped indices); otherwise
+// ghost addressing, for the boxes of a level whose ghost zones of width 4
+// hold the neighbours' values (a step reaches 4 points beyond the output
+// tile: indices -4 .. n + 3, read clamped to n + 3 by lanes past the box)
+template <int TXE, int NW, bool HASC2, bool Y3, bool C2PD2 = false, bool WRAP = true>
 __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, const Step4Coef &K, double *lds)
 {
     using T = Tile<TXE, NW>;
@@ -847,7 +851,8 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     // plane).
     const int nt = P.z1 - P.z0 + 8, tz = P.z1 - P.z0;
     const int nz = B.n[2];
-    int kz = readable(P.z0 - 4, nz, true, false); // wrapped index of the plane fetched next
+    // index of the plane fetched next (wrapped, or -4 .. nz + 3 with ghosts)
+    int kz = WRAP ? readable(P.z0 - 4, nz, true, false) : P.z0 - 4;
     // The loads of a plane are issued PD steps before it is taken: PD = 2,
     // from two buffers used by alternate steps, so that no register a load
     // is still filling is ever copied (a copy would wait for the load).
@@ -864,11 +869,25 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     Fetched F0, F1;
     F0.c = F1.c = 1.0;
     // byte offsets within a plane of the lane's column and halo slots
-    const unsigned col8 = (unsigned)w.col * 8u;
-    unsigned h8[T::HS];
+    unsigned col8, h8[T::HS];
+    if constexpr (WRAP) {
+        col8 = (unsigned)w.col * 8u;
 #pragma unroll
-    for (int s = 0; s < T::HS; ++s)
-        h8[s] = (unsigned)w.hcol[s] * 8u;
+        for (int s = 0; s < T::HS; ++s)
+            h8[s] = (unsigned)w.hcol[s] * 8u;
+    } else {
+        auto gi = [](int p, int n) { return p < n + 3 ? p : n + 3; };
+        const int nx = B.n[0], ny = B.n[1];
+        col8 = (unsigned)((gi(Pe.x0 + lx, nx) + w.g) + (int64_t)(gi(Pe.y0 + ly, ny) + w.g) * B.sy) * 8u;
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s) {
+            const int h = (int)threadIdx.x + s * T::NT;
+            int lrow = 0, lcol = 0, dx = 0, dy = 0;
+            if (h < T::NH)
+                halo_slot<TXE, NW>(h, lrow, lcol, dx, dy);
+            h8[s] = (unsigned)((gi(Pe.x0 + dx, nx) + w.g) + (int64_t)(gi(Pe.y0 + dy, ny) + w.g) * B.sy) * 8u;
+        }
+    }
     auto fetch = [&](Fetched &F) {
         const int64_t zo = (int64_t)(kz + w.g) * w.sz;
         const double *pu = uf + zo, *pr = rf + zo;
@@ -882,7 +901,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
                 F.hu[s] = ld_plane<0>(pu, plane_bytes, h8[s]);
                 F.hr[s] = ld_plane<0>(pr, plane_bytes, h8[s]);
             }
-        kz = kz + 1 == nz ? 0 : kz + 1;
+        kz = WRAP && kz + 1 == nz ? 0 : kz + 1;
     };
     // step t = t0 + J with t0 a multiple of 10: queue slot of plane f - 4 + m
     // (m = 0 .. 4) is (J + 1 + m) mod 5
@@ -1011,7 +1030,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
 
 // persistent form over the per-XCD work queue of a table of periodic boxes
 // (items: box, tile, z chunk of B.tz planes), as k_tiles_batched
-template <int TXE, int NW, bool HASC2>
+template <int TXE, int NW, bool HASC2, bool WRAP = true>
 __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_batched(const DevBox *__restrict__ tab, int nbox,
                                                                ItemQueue Q, Step4Coef K)
 {
@@ -1028,7 +1047,7 @@ __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_batched(const DevBox *
         if (item >= Q.nitems)
             break;
         const DevBox B = tab[box_of(tab, nbox, item)];
-        run_step4<TXE, NW, HASC2, false>(B, item_pos(B, item - B.item0, TXE - 4, TYE - 4), K, lds);
+        run_step4<TXE, NW, HASC2, false, false, WRAP>(B, item_pos(B, item - B.item0, TXE - 4, TYE - 4), K, lds);
     }
     if (threadIdx.x == 0)
         queue_finish(Q);
@@ -1039,13 +1058,13 @@ __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_batched(const DevBox *
 // workgroups of one XCD march a compact patch of tiles through the same
 // planes and share their halo lines in its L2 -- or, with run > 0, planes
 // [g * run, (g + 1) * run) of the box's tile-plane sequence.
-template <int TXE, int NW, bool HASC2, bool Y3>
+template <int TXE, int NW, bool HASC2, bool Y3, bool WRAP = true>
 __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, int run, int nxcd, double *lds)
 {
     constexpr int TYE = Tile<TXE, NW>::TY;
     const int g = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     if (run == 0) {
-        run_step4<TXE, NW, HASC2, Y3, !Y3>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
+        run_step4<TXE, NW, HASC2, Y3, !Y3, WRAP>(B, item_pos(B, g, TXE - 4, TYE - 4), K, lds);
         return;
     }
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
@@ -1053,18 +1072,18 @@ __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, 
     const int64_t e = s + run < total ? s + run : total;
     ItemPos P;
     while (run_piece(B, TXE - 4, TYE - 4, s, e, P)) {
-        run_step4<TXE, NW, HASC2, Y3, !Y3>(B, P, K, lds);
+        run_step4<TXE, NW, HASC2, Y3, !Y3, WRAP>(B, P, K, lds);
         __syncthreads(); // the next piece rewrites the LDS rings
     }
 }
 
 // (the launch bound asks for four wavefronts per SIMD: two 512-lane or one
 // 1024-lane workgroup per CU, as many as the LDS rings allow)
-template <int TXE, int NW, bool HASC2>
+template <int TXE, int NW, bool HASC2, bool WRAP = true>
 __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
 {
     __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
-    step4_grid<TXE, NW, HASC2, false>(B, K, run, nxcd, lds);
+    step4_grid<TXE, NW, HASC2, false, WRAP>(B, K, run, nxcd, lds);
 }
 
 // the same step, also storing the third stage state (u_3, rho_3)
@@ -1835,21 +1854,29 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 }
 
 hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
-                            hipStream_t s)
+                            hipStream_t s, bool ghosted)
 {
     const int64_t total = (int64_t)B.tiles[0] * B.tiles[1] * B.n[2];
     // the output stores address one z plane with 31-bit byte offsets; y_3
     // goes to q[2] and q[3] when both are given
     const bool y3 = B.q[2] != nullptr;
-    if (run < 0 || total <= 0 || B.sz * 8 >= (int64_t)NO_STORE || y3 != (B.q[3] != nullptr))
+    if (run < 0 || total <= 0 || B.sz * 8 >= (int64_t)NO_STORE || y3 != (B.q[3] != nullptr) ||
+        (ghosted && (y3 || B.g < 4)))
         return hipErrorInvalidValue;
     const int64_t grid = run == 0 ? (int64_t)B.tiles[0] * B.tiles[1] * B.tiles[2] : (total + run - 1) / run;
     const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};
 #define Y(K_, TXE_, NW_, C_)                                                                           \
     hipLaunchKernelGGL((K_<TXE_, NW_, C_>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, B, C, run, nxcd)
+#define G(TXE_, NW_, C_)                                                                               \
+    hipLaunchKernelGGL((k_rk4_step4<TXE_, NW_, C_, false>), dim3((unsigned)grid), dim3(NW_ * 64), 0, s, B, C, \
+                       run, nxcd)
 #define X(TXE_, NW_)                                                                                   \
     if (txe == TXE_ && nw == NW_) {                                                                    \
-        if (y3 && B.p[5] != nullptr)                                                                   \
+        if (ghosted && B.p[5] != nullptr)                                                              \
+            G(TXE_, NW_, true);                                                                        \
+        else if (ghosted)                                                                              \
+            G(TXE_, NW_, false);                                                                       \
+        else if (y3 && B.p[5] != nullptr)                                                              \
             Y(k_rk4_step4_y3, TXE_, NW_, true);                                                        \
         else if (y3)                                                                                   \
             Y(k_rk4_step4_y3, TXE_, NW_, false);                                                       \
@@ -1862,21 +1889,26 @@ hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[
     X(32, 8) X(64, 16) X(32, 16)
 #undef X
 #undef Y
+#undef G
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_rk4_step4_batched(int txe, int nw, bool hasc2, const DevBox *tab, int nbox, const ItemQueue &Q,
-                                    int grid, const StageCoef K[4], hipStream_t s)
+                                    int grid, const StageCoef K[4], hipStream_t s, bool ghosted)
 {
     const Step4Coef C{K[0].a, K[1].a, K[1].b, K[2].a, K[2].b, K[3].b};
-#define Y(TXE_, NW_, C_)                                                                               \
-    hipLaunchKernelGGL((k_rk4_step4_batched<TXE_, NW_, C_>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, Q, C)
+#define Y(TXE_, NW_, C_, W_)                                                                           \
+    hipLaunchKernelGGL((k_rk4_step4_batched<TXE_, NW_, C_, W_>), dim3(grid), dim3(NW_ * 64), 0, s, tab, nbox, Q, C)
 #define X(TXE_, NW_)                                                                                   \
     if (txe == TXE_ && nw == NW_) {                                                                    \
-        if (hasc2)                                                                                     \
-            Y(TXE_, NW_, true);                                                                        \
+        if (hasc2 && ghosted)                                                                          \
+            Y(TXE_, NW_, true, false);                                                                 \
+        else if (hasc2)                                                                                \
+            Y(TXE_, NW_, true, true);                                                                  \
+        else if (ghosted)                                                                              \
+            Y(TXE_, NW_, false, false);                                                                \
         else                                                                                           \
-            Y(TXE_, NW_, false);                                                                       \
+            Y(TXE_, NW_, false, true);                                                                 \
         return hipGetLastError();                                                                      \
     }
     X(32, 8) X(64, 16) X(32, 16)

@@ -51,14 +51,17 @@ hipError_t launch_rk4_pair(int pair, int txe, int nw, const DevBox &B, const Sta
 // tile-plane sequence (run_piece).  B.in, p[0], p[5]: u_n, rho_n, c^2
 // (optional); q[0], q[1]: u_{n+1}, rho_{n+1}, which must not alias the
 // inputs.  K: the coefficients of stages 1..4.  hipErrorInvalidValue for
-// z planes of 2 GiB or more.
+// z planes of 2 GiB or more.  ghosted: stencil neighbours from the ghost
+// zones (a level after an exchange of width 4; needs B.g >= 4, no y_3)
+// instead of wrapped indices.
 hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[4], int run, int nxcd,
-                            hipStream_t s);
-// persistent form over a table of periodic boxes (queue as launch_tiles_batched);
+                            hipStream_t s, bool ghosted = false);
+// persistent form over a table of boxes (queue as launch_tiles_batched);
 // hasc2: some box may have c^2 (p[5], null for the others).  The caller
-// checks that no box has a z plane of 2 GiB or more.
+// checks that no box has a z plane of 2 GiB or more, and with ghosted that
+// every box has ghost width 4 or more.
 hipError_t launch_rk4_step4_batched(int txe, int nw, bool hasc2, const DevBox *tab, int nbox, const ItemQueue &Q,
-                                    int grid, const StageCoef K[4], hipStream_t s);
+                                    int grid, const StageCoef K[4], hipStream_t s, bool ghosted = false);
 // resident workgroups per CU of the whole-step kernels (0 if unknown)
 int max_blocks_step4(int txe, int nw);
 

@@ -267,3 +267,76 @@ def test_level_rk4_kernel_sets_bitwise(ctx, mode, kind, nsteps):
         for a, b_ in zip([host(t) for t in u] + [host(t) for t in r], ref_u + ref_r):
             np.testing.assert_array_equal(a[3:-3, 3:-3, 3:-3], b_[3:-3, 3:-3, 3:-3], err_msg=f"candidate {cand}")
         S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
+
+
+# ---------------------------------------------------------------------------
+# wide levels: a full-shell exchange of width 4 over boxes with 4 ghost layers
+# lets a whole RK4 step read its radius-4 neighbourhood from the ghost zones
+
+def wide_level_case(ctx, d, nsteps, mode, cand=None, c2glob=None):
+    fields = (d["u"], d["rho"]) + ((c2glob,) if c2glob is not None else ())
+    L, boxes, fl, recs = level_of(d, width=4, shape="full", fields=fields)
+    if cand is not None:
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, cand)
+    ch = S.s4_level_choice(ctx, L)
+    S.s4_level_rk4(ctx, L, fl[0], fl[1], fl[2] if c2glob is not None else None, d["dt"], nsteps, mode)
+    if cand is not None:
+        S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
+    return [host(t) for t in fl[0]], [host(t) for t in fl[1]], recs, ch
+
+
+@pytest.mark.parametrize("mode", ["perbox", "batched", "graph"])
+@pytest.mark.parametrize("nsteps", [3, 4])
+def test_wide_level_whole_steps(ctx, mode, nsteps):
+    """Whole steps (the default on a wide level) against the oracle, and bit for
+    bit against the per-stage kernels on the same level; an odd count ends with
+    one per-stage step."""
+    d = W.level_tiling(**SMALL, ghost=4)
+    lu, lr, recs, ch = wide_level_case(ctx, d, nsteps, mode)
+    assert ch["kernel_op"] == 102
+    ou, orho = oracle_level(d, nsteps)
+    eu, er = compare(lu, lr, recs, ou, orho, gl=4)
+    assert eu <= TOL and er <= TOL, (eu, er)
+    su, sr, _, ch2 = wide_level_case(ctx, d, nsteps, mode, cand=2)
+    assert ch2["candidate"] == 2
+    for a, b_ in zip(lu + lr, su + sr):
+        np.testing.assert_array_equal(a[4:-4, 4:-4, 4:-4], b_[4:-4, 4:-4, 4:-4])
+
+
+def test_wide_level_every_whole_step_shape(ctx):
+    from _gpu import cands_by_kind
+    d = W.level_tiling(**SMALL, ghost=4)
+    L, boxes, _, _ = level_of(d, width=4, shape="full", fields=(d["u"],))
+    whole = [c for c in cands_by_kind(ctx, S.S4_OP_RK4, boxes)["fused"]
+             if (S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, c) or True)
+             and S.s4_get_choice(ctx, S.S4_OP_RK4, boxes)["kernel_op"] == 102]
+    S.s4_set_choice(ctx, S.S4_OP_RK4, boxes, -1)
+    ref = None
+    for c in whole:
+        lu, lr, _, ch = wide_level_case(ctx, d, 2, "batched", cand=c)
+        assert ch["candidate"] == c
+        if ref is None:
+            ref = (lu, lr)
+        for a, b_ in zip(lu + lr, ref[0] + ref[1]):
+            np.testing.assert_array_equal(a[4:-4, 4:-4, 4:-4], b_[4:-4, 4:-4, 4:-4], err_msg=f"candidate {c}")
+
+
+def test_wide_level_variable_c2(ctx):
+    d = W.level_tiling(**SMALL, ghost=4)
+    c2 = 0.5 + W.uniform01(d["seed"], 9, d["u"].shape)
+    lu, lr, recs, ch = wide_level_case(ctx, d, 4, "graph", c2glob=c2)
+    assert ch["kernel_op"] == 102
+    ou, orho = oracle_level(d, 4, c2glob=c2)
+    eu, er = compare(lu, lr, recs, ou, orho, gl=4)
+    assert eu <= TOL and er <= TOL, (eu, er)
+
+
+def test_level60_wide_whole_steps_vs_oracle(ctx):
+    """The 60-box level with 4 ghost layers and a full exchange of width 4, in
+    the benchmark's graph mode, against the oracle."""
+    d = W.level_tiling(ghost=4)
+    lu, lr, recs, ch = wide_level_case(ctx, d, 2, "graph")
+    assert ch["kernel_op"] == 102
+    ou, orho = oracle_level(d, 2)
+    eu, er = compare(lu, lr, recs, ou, orho, gl=4)
+    assert eu <= TOL and er <= TOL, (eu, er)

@@ -377,8 +377,9 @@ def test_fused_candidates_only_for_single_box_rk4(ctx):
 def test_heuristic_kernel_sets(ctx):
     """Untuned RK4 starts on whole steps (one box or a set), and on the per-tap
     stage pairs where a z plane reaches 2 GiB (the whole-step stores address a
-    plane with 31-bit byte offsets); the multi-field kernel on small
-    workgroups.  Descriptors only: nothing is allocated."""
+    plane with 31-bit byte offsets); the RHS on pair-lane tiles where they fit
+    and fill the device; the multi-field kernel on small workgroups.
+    Descriptors only: nothing is allocated."""
     fresh = S.Context(0)
     b = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, b)["kernel_op"] == 102
@@ -393,7 +394,13 @@ def test_heuristic_kernel_sets(ctx):
     big = S.make_box((16384, 16384, 4), 2, (1, 16400, 16400 * 16388), 1.0)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, big)["kernel_op"] == 101
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, big])["kernel_op"] == 101
-    assert S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, b)["kernel_op"] == 0
+    # the RHS on pair-lane tiles where rows and strides are even, else one point per lane
+    ch = S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, b)
+    assert (ch["kernel_op"], ch["tile_x"], ch["tile_y"], ch["z_chunk"]) == (300, 128, 8, 32), ch
+    odd = S.make_box((255, 256, 256), 2, (1, 259, 259 * 260), 1 / 256)
+    assert S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, odd)["kernel_op"] == 0
+    small = S.make_box((32, 32, 32), 2, (1, 48, 48 * 36), 1 / 32)
+    assert S.s4_get_choice(fresh, S.S4_OP_WAVE_RHS, small)["kernel_op"] == 0
     # the multi-field kernel: 32 x 8 lanes, the longest z chunk giving each CU one item per field
     m = S.make_box((192, 192, 192), 2, (1, 208, 208 * 196), 1 / 192)
     ch = S.s4_get_choice(fresh, S.S4_OP_DERIV_MIXED, m)

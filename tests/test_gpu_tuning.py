@@ -110,3 +110,43 @@ def test_c2_calls_have_their_own_setup():
     assert S.s4_get_choice(f, S.S4_OP_RK4, b)["candidate"] == S.s4_get_choice(S.Context(0), S.S4_OP_RK4, b)["candidate"]
     with pytest.raises(S.Sten4Error):
         S.s4_get_choice(f, S.S4_OP_WAVE_RHS | S.S4_WITH_C2, b)
+
+
+def test_online_search_cost_stays_bounded():
+    """The on-line search's own cost (Sec. III-B: bad excursions are
+    abandoned after one call): over 100 calls of 2 RK4 steps on a 128^3 box
+    (kernel launches, no graphs), with random restarts, the calls' total
+    device time stays within 1.5x of the same calls at the setting the
+    search ends on, and that of the last 50 calls within 1.35x (the search
+    settles; a restart's excursion costs a call or two)."""
+    n, g = (128, 128, 128), 2
+    u, r = S.alloc_field(n, g, fill=0.25), S.alloc_field(n, g, fill=0.5)
+    b = S.box_of(u, g, 1 / 128)
+    ws = S.workspace(S.s4_workspace_size(b, S.S4_OP_RK4, S.S4_BATCHED))
+    on = S.Context(0)
+    S.s4_set_online_tuning(on, True, 0.02, 5)
+    ncall, spc = 100, 2
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(ncall + 1)]
+    ev[0].record()
+    for k in range(ncall):
+        S.s4_rk4(on, b, [u], [r], None, 1e-6, spc, "batched", ws=ws)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    calls = [ev[k].elapsed_time(ev[k + 1]) for k in range(ncall)]
+    best = S.s4_get_choice(on, S.S4_OP_RK4, b)["candidate"]
+    off = S.Context(0)
+    S.s4_set_choice(off, S.S4_OP_RK4, b, best)
+    for _ in range(3):
+        S.s4_rk4(off, b, [u], [r], None, 1e-6, spc, "batched", ws=ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        S.s4_rk4(off, b, [u], [r], None, 1e-6, spc, "batched", ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    t_best = e0.elapsed_time(e1) / 20
+    total, late = sum(calls), sum(calls[ncall // 2:])
+    print(f"on-line search: {ncall} calls {total:.3f} ms, last half {late:.3f} ms, at the final setting "
+          f"{ncall * t_best:.3f} ms; slowest calls {sorted(calls)[-5:]}")
+    assert total <= 1.5 * ncall * t_best, (total, ncall * t_best, sorted(calls)[-10:])
+    assert late <= 1.35 * (ncall - ncall // 2) * t_best, (late, t_best, calls[ncall // 2:])

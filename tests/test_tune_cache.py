@@ -16,15 +16,15 @@ def box(n, g=2):
     return S.make_box(n, g, (1, sy, sy * (ny + 2 * g)), 1.0 / nx)
 
 
-def key(op, boxes, c2=False, level=False):
+def key(op, boxes, c2=False, level=0):
     """The loop-setup key format documented beside S4_TUNE_CACHE."""
     k = f"op{op}|{DEV}|{len(boxes)}"
     for b in boxes:
         k += f"|{b.n[0]},{b.n[1]},{b.n[2]},g{b.ghost},s{b.stride[1]},{b.stride[2]}"
-    return k + ("|c2" if c2 else "") + ("|level" if level else "")
+    return k + ("|c2" if c2 else "") + {0: "", 1: "|level", 2: "|level4"}[level]
 
 
-def lookup(tmp_path, entries, op, boxes, level=False):
+def lookup(tmp_path, entries, op, boxes, level=0):
     p = tmp_path / "tune.json"
     p.write_text(entries if isinstance(entries, str) else json.dumps(entries))
     return S.s4_tune_cache_lookup(str(p), DEV, op, boxes, level)
@@ -67,9 +67,14 @@ def test_candidate_the_op_cannot_run_is_ignored(tmp_path):
     assert lookup(tmp_path, {key(S.S4_OP_RK4, two): PAIR1}, S.S4_OP_RK4, two) == -1
     assert lookup(tmp_path, {key(S.S4_OP_RK4, two): WHOLE}, S.S4_OP_RK4, two) >= 0
     # a level runs only kernel sets that read radius-2 ghost zones
-    lk = key(S.S4_OP_RK4, two, level=True)
-    assert lookup(tmp_path, {lk: WHOLE}, S.S4_OP_RK4, two, level=True) == -1
-    assert lookup(tmp_path, {lk: TILES}, S.S4_OP_RK4, two, level=True) >= 0
+    lk = key(S.S4_OP_RK4, two, level=1)
+    assert lookup(tmp_path, {lk: WHOLE}, S.S4_OP_RK4, two, level=1) == -1
+    assert lookup(tmp_path, {lk: TILES}, S.S4_OP_RK4, two, level=1) >= 0
+    # a wide level (exchanges of width 4) runs whole steps, never the widened-tile pairs
+    wk = key(S.S4_OP_RK4, two, level=2)
+    assert lookup(tmp_path, {wk: WHOLE}, S.S4_OP_RK4, two, level=2) >= 0
+    assert lookup(tmp_path, {wk: PAIR1}, S.S4_OP_RK4, two, level=2) == -1
+    assert lookup(tmp_path, {lk: WHOLE}, S.S4_OP_RK4, two, level=2) == -1  # keys differ
 
 
 def test_whole_steps_need_z_planes_below_2gib(tmp_path):
