@@ -346,6 +346,7 @@ struct s4_ctx {
     std::map<std::string, int> forced;
     std::map<std::string, GraphEntry> graphs;
     uint64_t graph_tick = 0;
+    std::mutex cap_mu; // one capture at a time on the private stream
     bool online = false; // on-line hill climbing of every loop setup
     double restart_prob = 0.02;
     uint64_t seed = 1;
@@ -1658,10 +1659,12 @@ static int graph_run(s4_ctx *ctx, const std::string &key, const std::function<in
     if (ctx->graphs.find(key) == ctx->graphs.end()) {
         lk.unlock();
         GraphEntry ge;
+        std::unique_lock<std::mutex> cl(ctx->cap_mu);
         S4_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
         int r = record(ctx->cap);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+        cl.unlock();
         if (r) {
             if (g)
                 (void)hipGraphDestroy(g);
