@@ -90,16 +90,21 @@ def kernels_per_step(ch, nbox, level=False):
 
 def traffic_from_profile(kernel_key, tile):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source with the same tile choice; else None."""
+    on the current kernel source with the same tile choice; else None.  An
+    entry is one record, or a list of records (one per tile the sweep
+    ran)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         t = json.load(open(path))
     except (OSError, ValueError):
         return None
-    e = t.get(kernel_key)
-    if not e or e.get("source_hash") != kernel_source_hash() or list(e.get("tile", [])) != list(tile):
-        return None
-    return e.get("bytes_per_launch")
+    entries = t.get(kernel_key)
+    if isinstance(entries, dict):
+        entries = [entries]
+    for e in entries or []:
+        if e.get("source_hash") == kernel_source_hash() and list(e.get("tile") or []) == list(tile):
+            return e.get("bytes_per_launch")
+    return None
 
 
 def main():
