@@ -482,3 +482,49 @@ def test_mixed192_full_size(ctx):
         got = host(outs[k])
         assert rel(got, O.deriv_mixed(f, g, d["dx"], d["A"]), g) <= TOL, k
         assert ghosts_untouched(got, g)
+
+
+@pytest.mark.parametrize("with_c2", [False, True])
+def test_pair_lane_rhs_candidates(ctx, with_c2):
+    """The pair-lane RHS tiles (two x points per lane) on a box with even rows:
+    every shape against the oracle, with and without c^2, and bit for bit
+    against the one-point tiles; fields whose interior rows are not 16-byte
+    aligned run the same shape on the one-point tiles."""
+    n, g = (64, 40, 24), 2
+    dx = (1 / 64, 1 / 40, 1 / 24)
+    a = O.fill_ghosts_periodic(rand_box(n, g, 12, 1), g)
+    c2 = O.embed(1.0 + 0.5 * W.uniform_pm1(12, 2, n[::-1]), g) if with_c2 else None
+    u = dev_full(a, g)
+    c2d = dev(c2, g) if with_c2 else None
+    b = S.box_of(u, g, dx)
+    want = O.wave_rhs(a, g, dx, c2)
+    kinds = cands_by_kind(ctx, S.S4_OP_WAVE_RHS, b)
+    assert len(kinds["pairs"]) == 12
+    ref = None
+    for cand in [kinds["tiles"][1]] + kinds["pairs"]:
+        out = S.alloc_field(n, g, fill=NAN)
+        S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, cand)
+        S.s4_wave_rhs(ctx, b, [u], None if c2d is None else [c2d], [out])
+        got = host(out)
+        assert rel(got, want, g) <= TOL, f"candidate {cand}"
+        assert ghosts_untouched(got, g)
+        if ref is None:
+            ref = got
+        np.testing.assert_array_equal(inner(got, g), inner(ref, g), err_msg=f"candidate {cand}")
+    # misaligned fields: views shifted by one element (8-byte aligned, not 16)
+    span = u.stride()[0] * u.shape[0]
+    flat = torch.empty(span + 64, dtype=torch.float64, device="cuda")
+    shifted = flat[1:].as_strided(u.shape, u.stride())
+    shifted.copy_(u)
+    outs = torch.full_like(flat, NAN)[1:].as_strided(u.shape, u.stride())
+    bs = S.box_of(shifted, g, dx)
+    S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, bs, kinds["pairs"][0])
+    c2s = None
+    if with_c2:
+        cflat = torch.full_like(flat, NAN)
+        c2s = cflat[1:].as_strided(u.shape, u.stride())
+        c2s.copy_(c2d)
+    S.s4_wave_rhs(ctx, bs, [shifted], None if c2s is None else [c2s], [outs])
+    np.testing.assert_array_equal(inner(host(outs), g), inner(ref, g))
+    S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, -1)
+    S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, bs, -1)
