@@ -680,6 +680,11 @@ def main():
                                               f"{model}, {el1:.1f} s"}
         log(f"[bench] cpu single thread: {out['cpu_single_thread']}")
 
+    # the single-box RHS against the copy probe of the same run (SURVEY's "% of a STREAM-copy probe")
+    if "rhs" in out and "copy" in out:
+        out["rhs"]["frac_of_copy"] = round(out["rhs"]["achieved_GBs"] / out["copy"]["GBs"], 4)
+        if out["rhs"].get("traffic"):
+            out["rhs"]["traffic_GBs"] = round(out["rhs"]["traffic"] / (out["rhs"]["us_per_rhs"] * 1e3), 1)
     rec = {"metric": METRIC, "value": round(value, 3), "unit": "Gpoint-updates/s", "n_gpus": 1, "steps": K,
            "warmup": WU, "ms_per_step": round(wall * 1e3 / K, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
