@@ -94,9 +94,9 @@ static int hip_fail(hipError_t e, const char *where)
 // tx x (nw*64/tx) with output tile (tx-4) x (nw*64/tx - 4), variant 3 forms
 // the second stage's stencil input at each tap on the plain tile
 // tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (any
-// number of periodic boxes, no levels) runs a whole RK4 step per pass on the
-// widened tile of variant 1, stages 1-2 on all lanes and 3-4 on the output
-// tile; variant 5 (the wave RHS on boxes with an even n[0] and even
+// number of periodic boxes, or a wide level) runs a whole RK4 step per pass
+// on the widened tile of variant 1 (tx 68: 68 x 15 on 1020 of 1024 lanes),
+// stages 1-2 on all lanes and 3-4 on the output tile; variant 5 (the wave RHS on boxes with an even n[0] and even
 // strides) is the tile traversal with two x points per lane, tile
 // 2 tx x (nw*64/tx).  tz is the z chunk (0 = whole box; for variant 4 on one
 // box, equal shares of the tile-plane sequence).  Candidate indices are
@@ -122,7 +122,9 @@ static const std::vector<Cand> &cands()
         for (auto tn : {std::pair<int, int>{64, 4}, {64, 8}, {32, 8}, {32, 4}, {16, 8}, {16, 4}})
             for (int tz : {64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 3, 0});
-        for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}}) // 64 x 8 wastes half its lanes
+        // (64 x 8 wastes half its lanes; 68 x 15 covers a 256-point row in
+        // four output tiles)
+        for (auto tn : {std::pair<int, int>{64, 16}, {32, 16}, {32, 8}, {68, 16}})
             for (int tz : {0, 128, 64, 32, 16})
                 c.push_back({tn.first, tn.second, tz, 4, 0});
         for (auto tn : {std::pair<int, int>{32, 8}, {64, 8}, {64, 16}, {32, 16}})
@@ -236,7 +238,7 @@ static void graph_free(GraphEntry &ge)
 // excursions stay cheap: the aim is a short total run time, not the optimum.
 
 // position of a candidate's parameters in their value orders
-static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : tx == 64 ? 2 : tx == 128 ? 3 : 4; }
+static int ord_tx(int tx) { return tx == 16 ? 0 : tx == 32 ? 1 : tx == 64 || tx == 68 ? 2 : tx == 128 ? 3 : 4; }
 static int ord_ry(int ry) { return ry == 4 ? 1 : 0; }
 static int ord_nw(int nw) { return nw == 4 ? 0 : nw == 8 ? 1 : 2; }
 static int ord_tz(int tz) { return tz == 8 ? 0 : tz == 16 ? 1 : tz == 32 ? 2 : tz == 64 ? 3 : tz == 128 ? 4 : 5; }
@@ -334,9 +336,10 @@ struct s4_ctx {
     int device = 0;
     int ncu = 256;
     int nxcd = 8;
-    // resident workgroups per CU of the whole-step shapes 32 x 16, 64 x 16
-    // and 32 x 32 lanes (LDS-bound; queried from the device at creation)
-    int step4_per[3] = {2, 1, 1};
+    // resident workgroups per CU of the whole-step shapes 32 x 16, 64 x 16,
+    // 32 x 32 and 68 x 15 lanes (LDS-bound; queried from the device at
+    // creation)
+    int step4_per[4] = {2, 1, 1, 1};
     std::string name;
     std::string cache_path;
     hipStream_t cap = nullptr; // private stream used only to capture graphs
@@ -467,21 +470,24 @@ static int64_t step4_run_length(int64_t total, int64_t slots, int ncu)
 // streams (its chunk plus the 8-plane start-up of the pipeline).  Equal runs
 // (tz 0): the planes of the busiest run plus 8 for every tile column it
 // touches, in one round.  Each shape and order has its own cost per plane,
-// measured on whole-step runs over periodic cubes of side 128 to 512
-// (relative to 32 x 16 lanes in z chunks): equal runs lose L2 locality, and a
-// 1024-lane workgroup alone on its CU hides less latency per lane.
-// 16-plane chunks count only where all their items fit one round (on 128^3
-// they beat 32-plane chunks, which leave CUs idle, by 6 %; over several rounds
-// the start-up term prices them far below what they measure).
+// the geometric mean over periodic cubes of side 192 to 512 (relative to
+// 32 x 16 lanes in 32-plane chunks; the model then picks within 0.5 % of
+// the fastest setting on each of those cubes and on 128^3): equal runs lose
+// L2 locality, a 1024-lane workgroup alone on its CU hides less latency per
+// lane, and 68 x 15 lanes trade idle lanes for whole output rows on boxes
+// 64 points wide in x.
 static int step4_single(const s4_ctx *ctx, const s4_box &b)
 {
     struct Opt {
         int tx, nw, tz, shape;
         double per_plane;
     };
-    static const Opt opts[] = {{32, 8, 32, 0, 1.0},    {32, 8, 0, 0, 1.184},    {64, 16, 128, 1, 1.006},
-                               {64, 16, 64, 1, 1.006}, {64, 16, 0, 1, 1.110}, {32, 16, 0, 2, 1.270},
-                               {32, 8, 16, 0, 1.0}};
+    static const Opt opts[] = {
+        {32, 8, 0, 0, 1.449},   {32, 8, 128, 0, 1.033},  {32, 8, 64, 0, 1.098},  {32, 8, 32, 0, 1.0},
+        {32, 8, 16, 0, 1.010},  {64, 16, 0, 1, 1.267},   {64, 16, 128, 1, 1.059}, {64, 16, 64, 1, 1.034},
+        {64, 16, 32, 1, 0.995}, {64, 16, 16, 1, 0.986},  {32, 16, 0, 2, 1.545},  {32, 16, 128, 2, 1.215},
+        {32, 16, 64, 2, 1.244}, {32, 16, 32, 2, 1.126},  {32, 16, 16, 2, 1.073}, {68, 16, 0, 3, 1.339},
+        {68, 16, 128, 3, 1.109}, {68, 16, 64, 3, 1.134}, {68, 16, 32, 3, 1.086}, {68, 16, 16, 3, 1.030}};
     int best = cand_index(32, 8, 32, 4);
     {
         // too few tile-planes to give every resident 512-lane workgroup 8
@@ -505,8 +511,6 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
         if (o.tz > 0) {
             const int64_t tz = std::min<int64_t>(o.tz, nz);
             const int64_t items = tiles * ((nz + tz - 1) / tz);
-            if (o.tz == 16 && items > slots)
-                continue;
             planes = (double)((items + slots - 1) / slots) * (double)(tz + 8);
         } else {
             // the runs step4_run hands out: R planes each (the last one shorter)
@@ -584,9 +588,11 @@ static int heuristic(const s4_ctx *ctx, int op, const s4_box *b, int nbox, int l
 std::vector<int> Hill::neighbours(int c) const
 {
     const Cand &a = cands()[c];
+    // (68-point rows sit one step from 64-point ones)
     auto dist = [&](const Cand &e) {
         return std::abs(ord_tx(e.tx) - ord_tx(a.tx)) + std::abs(ord_nw(e.nw) - ord_nw(a.nw)) +
-               std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry));
+               std::abs(ord_tz(e.tz) - ord_tz(a.tz)) + std::abs(ord_ry(e.ry) - ord_ry(a.ry)) +
+               ((e.tx == 68) != (a.tx == 68));
     };
     std::vector<int> out;
     int nearest[6] = {1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30, 1 << 30}; // per other kernel set
@@ -642,6 +648,36 @@ struct Choice {
 static void online_harvest(OnlineSetup &st);
 
 // caller holds ctx->mu
+// The settings the on-line search may visit: those the op can run, less
+// those whose launches hand fewer work items than a quarter of the CUs
+// while another setting gives every CU one (with most of the device idle
+// they cannot win, and one call on them costs many: on a 128^3 box a
+// whole-box z chunk of 64 x 8 tiles runs 32 workgroups and takes ten times
+// the best setting's time).  Whole steps in equal runs spread over every CU.
+static std::vector<int> online_allowed(const s4_ctx *ctx, int op, const s4_box *b, int nbox, int level)
+{
+    const std::vector<int> all = allowed_cands(op, b, nbox, level);
+    auto work = [&](int ci) {
+        const Cand &c = cands()[ci];
+        if (c.variant == 4 && c.tz == 0 && nbox == 1)
+            return (int64_t)ctx->ncu;
+        int64_t n = 0;
+        for (int i = 0; i < nbox; ++i)
+            n += items_of(b[i], c);
+        return n;
+    };
+    int64_t most = 0;
+    for (int ci : all)
+        most = std::max(most, work(ci));
+    if (most < ctx->ncu)
+        return all;
+    std::vector<int> v;
+    for (int ci : all)
+        if (4 * work(ci) >= ctx->ncu)
+            v.push_back(ci);
+    return v;
+}
+
 static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox,
                                  int level)
 {
@@ -649,7 +685,7 @@ static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, co
     if (it != ctx->online_state.end())
         return it->second;
     OnlineSetup &st = ctx->online_state[key];
-    st.hill.allowed = allowed_cands(op, b, nbox, level);
+    st.hill.allowed = online_allowed(ctx, op, b, nbox, level);
     auto t = ctx->tuned.find(key);
     st.hill.start = t != ctx->tuned.end() && cand_valid(t->second, op, b, nbox, level)
                         ? t->second
@@ -1104,8 +1140,8 @@ int s4_create(int device, s4_ctx **out)
             c->name = c->name.substr(0, cut);
     }
     {
-        const int shapes[3][2] = {{32, 8}, {64, 16}, {32, 16}};
-        for (int k = 0; k < 3; ++k) {
+        const int shapes[4][2] = {{32, 8}, {64, 16}, {32, 16}, {68, 16}};
+        for (int k = 0; k < 4; ++k) {
             const int per = max_blocks_step4(shapes[k][0], shapes[k][1]);
             if (per > 0)
                 c->step4_per[k] = per;
@@ -1171,7 +1207,7 @@ int s4_online_simulate(int op, const s4_box *b, int nbox, const double *cost, in
         return fail(S4_EINVAL, "noise in [0, 1) and restart_prob in [0, 1]");
     s4_ctx sim; // host-only: the heuristic needs the CU count only
     Hill h;
-    h.allowed = allowed_cands(op, b, nbox);
+    h.allowed = online_allowed(&sim, op, b, nbox, 0);
     h.start = heuristic(&sim, op, b, nbox);
     h.restart_prob = restart_prob;
     h.rng ^= seed * 0xD1342543DE82EF95ull;

@@ -76,17 +76,29 @@ struct StageCoef {
     double a_next;
 };
 
+// A workgroup tile of TX x TY points, one per thread.  TX = 68 (whole RK4
+// steps on 1024 threads only): rows of 68 points, whose 64-point output rows
+// cover a 256-point extent in four tiles; its 15 rows take 1020 threads, and
+// the last four threads repeat thread 1019's loads, LDS writes and results.
 template <int TX, int NW>
 struct Tile {
     static constexpr int NT = NW * 64;         // threads per workgroup
     static constexpr int TY = NT / TX;         // rows per tile
+    static constexpr int NTL = TX * TY;        // threads on tile points
     static constexpr int LX = TX + 4;          // LDS plane row length (2-point halo each side)
     static constexpr int LY = TY + 4;
     static constexpr int NH = 4 * (TX + TY);   // halo points per plane
-    static constexpr int HS = (NH + NT - 1) / NT; // halo slots per thread
-    static_assert(TX == 16 || TX == 32 || TX == 64, "tile x extent");
-    static_assert(NT % TX == 0, "rows");
+    static constexpr int HS = (NH + NTL - 1) / NTL; // halo slots per thread
+    static_assert(TX == 16 || TX == 32 || TX == 64 || (TX == 68 && NW == 16), "tile x extent");
+    static_assert(NT % TX == 0 || TX == 68, "rows");
 };
+
+// the tile point of thread t (threads past the tile's whole rows take the last one)
+template <int TX, int NW>
+S4_HD inline int tile_thread(int t)
+{
+    return t < Tile<TX, NW>::NTL ? t : Tile<TX, NW>::NTL - 1;
+}
 
 // Position p along an axis of n interior points mapped to an index that may
 // be read.  Callers never go below -2.  With `clamp`, points past n+1, which
@@ -204,7 +216,7 @@ struct Walker {
         active = i < nx && j < ny;
         col = (int64_t)(readable(i, nx, WRAP, CLAMP) + g) + (int64_t)(readable(j, ny, WRAP, CLAMP) + g) * B.sy;
         for (int s = 0; s < T::HS; ++s) {
-            const int h = t + s * T::NT;
+            const int h = t + s * T::NTL;
             int lrow = 0, lcol = 0, dx = 0, dy = 0;
             if (h < T::NH)
                 halo_slot<TX, NW>(h, lrow, lcol, dx, dy);

@@ -39,6 +39,21 @@ __device__ __forceinline__ double lap4(const DevBox &B, double c, double xm2, do
     return r;
 }
 
+// lap4 in parts, with the same roundings: one axis's tap sum, then the sum
+// over the axes
+__device__ __forceinline__ double axis4(double m2, double m1, double p1, double p2)
+{
+    return fma(16.0, m1 + p1, -(m2 + p2));
+}
+__device__ __forceinline__ double lap4s(const DevBox &B, double c, double sx, double sy, double sz)
+{
+    double r = B.c0 * c;
+    r = fma(B.cx, sx, r);
+    r = fma(B.cy, sy, r);
+    r = fma(B.cz, sz, r);
+    return r;
+}
+
 // Workgroup barrier that orders LDS only.  __syncthreads() also drains the
 // wave's global loads and stores before the barrier; a kernel whose
 // threads never read global memory written in the same launch needs only
@@ -785,10 +800,13 @@ __global__ __launch_bounds__(NW * 64) void k_rk4_pair(DevBox B, StageCoef K1, St
 // state y_3 = (u_3, rho_3) of phase A's plane on the output tile (B.q[2],
 // B.q[3]), which the backward step reads.
 
+// The rings hold each point's two fields side by side, (u_n, u_2) and
+// (u_3, u_4), so that one 16-byte LDS access moves a tap of both: 16-byte
+// LDS reads deliver about 1.5 times the bytes per clock of 8-byte ones.
 template <int TXE, int NW>
 struct Step4Lds {
-    static constexpr int P1 = Tile<TXE, NW>::LY * Tile<TXE, NW>::LX; // u_n and u_2 with halo
-    static constexpr int P2 = TXE * Tile<TXE, NW>::TY;                // u_3 and u_4
+    static constexpr int P1 = Tile<TXE, NW>::LY * Tile<TXE, NW>::LX; // (u_n, u_2) with halo
+    static constexpr int P2 = TXE * Tile<TXE, NW>::TY;                // (u_3, u_4)
     static constexpr int SIZE = 4 * 2 * P1 + 4 * 2 * P2;              // doubles
 };
 
@@ -810,13 +828,14 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
     using S = Step4Lds<TXE, NW>;
     constexpr int TYE = T::TY;
     constexpr int P1 = S::P1, P2 = S::P2;
-    double *const ring1 = lds;              // 4 slots of [u_n | u_2]
-    double *const ring2 = lds + 4 * 2 * P1; // 4 slots of [u_3 | u_4]
+    dvec2 *const ring1 = (dvec2 *)lds;      // 4 slots of (u_n, u_2) pairs
+    dvec2 *const ring2 = ring1 + 4 * P1;    // 4 slots of (u_3, u_4) pairs
     ItemPos Pe = P;
     Pe.x0 -= 2;
     Pe.y0 -= 2;
-    const Walker<TXE, NW, true, false> w(B, Pe, threadIdx.x);
-    const int lx = threadIdx.x % TXE, ly = threadIdx.x / TXE;
+    const int tl = tile_thread<TXE, NW>(threadIdx.x);
+    const Walker<TXE, NW, true, false> w(B, Pe, tl);
+    const int lx = tl % TXE, ly = tl / TXE;
     const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < B.n[0] && w.j < B.n[1];
     const int l2 = ly * TXE + lx;
     // byte offset of the lane's output point within a z plane
@@ -881,7 +900,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         col8 = (unsigned)((gi(Pe.x0 + lx, nx) + w.g) + (int64_t)(gi(Pe.y0 + ly, ny) + w.g) * B.sy) * 8u;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s) {
-            const int h = (int)threadIdx.x + s * T::NT;
+            const int h = tl + s * T::NTL;
             int lrow = 0, lcol = 0, dx = 0, dy = 0;
             if (h < T::NH)
                 halo_slot<TXE, NW>(h, lrow, lcol, dx, dy);
@@ -915,15 +934,12 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         qr[S4] = nr;
         if (HASC2)
             qc[S4] = F.c;
-        double *R1 = ring1 + k * 2 * P1;
-        R1[w.lc] = nu;
-        R1[P1 + w.lc] = fma(a1, nr, nu);
+        dvec2 *R1 = ring1 + k * P1;
+        R1[w.lc] = dvec2{nu, fma(a1, nr, nu)};
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
-            if (w.hl[s] >= 0) {
-                R1[w.hl[s]] = F.hu[s];
-                R1[P1 + w.hl[s]] = fma(a1, F.hr[s], F.hu[s]);
-            }
+            if (w.hl[s] >= 0)
+                R1[w.hl[s]] = dvec2{F.hu[s], fma(a1, F.hr[s], F.hu[s])};
         // the loads of the plane taken PD steps on fly across the barrier
         // (this buffer's registers were consumed just above), as do the
         // stores of the last plane
@@ -932,16 +948,26 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
         lds_barrier();
         if (t >= 4) {
             // phase A (stages 1 and 2) at plane f - 2, every lane
-            const double *L = ring1 + ((k + 2) & 3) * 2 * P1; // taken at step t - 2
-            const double *V = L + P1;
+            // (x taps, then y taps: four 16-byte taps in registers at a time)
+            const dvec2 *L = ring1 + ((k + 2) & 3) * P1; // taken at step t - 2
             const int lc = w.lc;
-            const double la = lap4(B, qa[S2], L[lc - 2], L[lc - 1], L[lc + 1], L[lc + 2], L[lc - 2 * T::LX],
-                                   L[lc - T::LX], L[lc + T::LX], L[lc + 2 * T::LX], qa[S0], qa[S1], qa[S3],
-                                   qa[S4]);
+            double sxa, sxv, sya, syv;
+            {
+                const dvec2 m2 = L[lc - 2], m1 = L[lc - 1], p1 = L[lc + 1], p2 = L[lc + 2];
+                sxa = axis4(m2.x, m1.x, p1.x, p2.x);
+                sxv = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                const dvec2 m2 = L[lc - 2 * T::LX], m1 = L[lc - T::LX], p1 = L[lc + T::LX], p2 = L[lc + 2 * T::LX];
+                sya = axis4(m2.x, m1.x, p1.x, p2.x);
+                syv = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
+            const double la = lap4s(B, qa[S2], sxa, sya, axis4(qa[S0], qa[S1], qa[S3], qa[S4]));
             const double un = qa[S2], rn = qr[S2], u2 = fma(a1, qr[S2], qa[S2]);
-            const double lv = lap4(B, u2, V[lc - 2], V[lc - 1], V[lc + 1], V[lc + 2], V[lc - 2 * T::LX],
-                                   V[lc - T::LX], V[lc + T::LX], V[lc + 2 * T::LX], fma(a1, qr[S0], qa[S0]),
-                                   fma(a1, qr[S1], qa[S1]), fma(a1, qr[S3], qa[S3]), fma(a1, qr[S4], qa[S4]));
+            const double lv = lap4s(B, u2, sxv, syv,
+                                    axis4(fma(a1, qr[S0], qa[S0]), fma(a1, qr[S1], qa[S1]),
+                                          fma(a1, qr[S3], qa[S3]), fma(a1, qr[S4], qa[S4])));
             const double kr1 = HASC2 ? qc[S2] * la : la;
             const double kr2 = HASC2 ? qc[S2] * lv : lv;
             const double r2 = fma(a1, kr1, rn);
@@ -954,9 +980,7 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             }
             du0 = fma(b3, r3, fma(b2, r2, fma(1.0 / 3.0, u2 - un, un)));
             dr0 = fma(b2, kr2, fma(1.0 / 3.0, r2 - rn, rn));
-            double *R2 = ring2 + k * 2 * P2;
-            R2[l2] = u3;
-            R2[P2 + l2] = u4;
+            ring2[k * P2 + l2] = dvec2{u3, u4};
             qb[S4] = u3;
             qd[S4] = u4;
         }
@@ -966,12 +990,21 @@ __device__ __forceinline__ void run_step4(const DevBox &B, const ItemPos &P, con
             // phase B (stages 3 and 4) at plane f - 4, the output tile; u_3
             // and u_4 of planes f - 6 .. f - 2 sit in the slots of steps
             // t - 4 .. t, rho_n and c^2 of plane f - 4 in slot S0
-            const double *L = ring2 + ((k + 2) & 3) * 2 * P2; // written at step t - 2
-            const double *V = L + P2;
-            const double l3 = lap4(B, qb[S2], L[l2 - 2], L[l2 - 1], L[l2 + 1], L[l2 + 2], L[l2 - 2 * TXE],
-                                   L[l2 - TXE], L[l2 + TXE], L[l2 + 2 * TXE], qb[S0], qb[S1], qb[S3], qb[S4]);
-            const double l4 = lap4(B, qd[S2], V[l2 - 2], V[l2 - 1], V[l2 + 1], V[l2 + 2], V[l2 - 2 * TXE],
-                                   V[l2 - TXE], V[l2 + TXE], V[l2 + 2 * TXE], qd[S0], qd[S1], qd[S3], qd[S4]);
+            const dvec2 *L = ring2 + ((k + 2) & 3) * P2; // written at step t - 2
+            double sx3, sx4, sy3, sy4;
+            {
+                const dvec2 m2 = L[l2 - 2], m1 = L[l2 - 1], p1 = L[l2 + 1], p2 = L[l2 + 2];
+                sx3 = axis4(m2.x, m1.x, p1.x, p2.x);
+                sx4 = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                const dvec2 m2 = L[l2 - 2 * TXE], m1 = L[l2 - TXE], p1 = L[l2 + TXE], p2 = L[l2 + 2 * TXE];
+                sy3 = axis4(m2.x, m1.x, p1.x, p2.x);
+                sy4 = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
+            const double l3 = lap4s(B, qb[S2], sx3, sy3, axis4(qb[S0], qb[S1], qb[S3], qb[S4]));
+            const double l4 = lap4s(B, qd[S2], sx4, sy4, axis4(qd[S0], qd[S1], qd[S3], qd[S4]));
             const double kr3 = HASC2 ? qc[S0] * l3 : l3;
             const double kr4 = HASC2 ? qc[S0] * l4 : l4;
             const double r4 = fma(a3, kr3, qr[S0]);
@@ -1034,7 +1067,7 @@ template <int TXE, int NW, bool HASC2, bool WRAP = true>
 __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_batched(const DevBox *__restrict__ tab, int nbox,
                                                                ItemQueue Q, Step4Coef K)
 {
-    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    __shared__ __attribute__((aligned(16))) double lds[Step4Lds<TXE, NW>::SIZE];
     __shared__ int s_item;
     constexpr int TYE = Tile<TXE, NW>::TY;
     int q = blockIdx.x % Q.nq, left = Q.nq;
@@ -1082,7 +1115,7 @@ __device__ __forceinline__ void step4_grid(const DevBox &B, const Step4Coef &K, 
 template <int TXE, int NW, bool HASC2, bool WRAP = true>
 __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4(DevBox B, Step4Coef K, int run, int nxcd)
 {
-    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    __shared__ __attribute__((aligned(16))) double lds[Step4Lds<TXE, NW>::SIZE];
     step4_grid<TXE, NW, HASC2, false, WRAP>(B, K, run, nxcd, lds);
 }
 
@@ -1090,7 +1123,7 @@ __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4(DevBox B, Step4Coef K,
 template <int TXE, int NW, bool HASC2>
 __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_y3(DevBox B, Step4Coef K, int run, int nxcd)
 {
-    __shared__ double lds[Step4Lds<TXE, NW>::SIZE];
+    __shared__ __attribute__((aligned(16))) double lds[Step4Lds<TXE, NW>::SIZE];
     step4_grid<TXE, NW, HASC2, true>(B, K, run, nxcd, lds);
 }
 
@@ -1108,17 +1141,19 @@ __global__ __launch_bounds__(NW * 64, 4) void k_rk4_step4_y3(DevBox B, Step4Coef
 // results are bit for bit those of the per-stage kernels.  The traversal is
 // the tile traversal's (radius-2 halo; periodic addressing, or ghost
 // addressing on a level whose ghost zones are exchanged) over NF stencil
-// fields: each field's current plane sits in LDS (double buffered) and its
-// column's five z values in registers.  Reads and writes per point: pair 0
+// fields: each field's column's five z values sit in registers, and the
+// current plane of the two stencil inputs, (u_n, u_2) or (u_3, u_4), in LDS
+// as 16-byte pairs (double buffered), each pair formed once by the lane that
+// loaded the point.  Reads and writes per point: pair 0
 // reads u_n, rho_n and writes u_3, rho_3, acc_u, acc_rho; pair 1 reads u_3,
 // rho_3, u_n, rho_n, acc_u, acc_rho and writes u_{n+1}, rho_{n+1} (to
 // another buffer than u_n, which neighbouring tiles still read).
 
 template <int TX, int NW, int PAIR>
 struct Pair2Lds {
-    static constexpr int NF = PAIR == 0 ? 2 : 3;
+    static constexpr int NF = PAIR == 0 ? 2 : 3; // fields loaded per tap
     static constexpr int PLANE = Tile<TX, NW>::LY * Tile<TX, NW>::LX;
-    static constexpr int SIZE = 2 * NF * PLANE; // doubles
+    static constexpr int SIZE = 2 * 2 * PLANE; // doubles: two planes of pairs
 };
 
 // one work item of a stage pair; c^2 (B.p[5]) is optional per box: without
@@ -1177,8 +1212,13 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         F0.pw[v] = F1.pw[v] = v == 0 ? 1.0 : 0.0;
+    // the second stencil input at a point: u_2 = u_n + a rho_n (pair 0),
+    // u_4 = u_n + a rho_3 (pair 1), from that point's loaded fields
+    constexpr int FU = PAIR == 0 ? 0 : 2; // field of u_n
+    const double a1 = K1.a;
+    auto second = [&](const double *v) { return fma(a1, v[1], v[FU]); };
     auto step = [&](const int k, Fetched &X) {
-        double *L = lds + ((k - P.z0) & 1) * NF * PLANE;
+        dvec2 *L = (dvec2 *)lds + ((k - P.z0) & 1) * PLANE;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             q[f][0] = q[f][1];
@@ -1186,12 +1226,17 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
             q[f][2] = q[f][3];
             q[f][3] = q[f][4];
             q[f][4] = X.q4[f];
-            L[f * PLANE + lc] = q[f][2];
-#pragma unroll
-            for (int s = 0; s < T::HS; ++s)
-                if (w.hl[s] >= 0)
-                    L[f * PLANE + w.hl[s]] = X.hv[f][s];
         }
+        {
+            const double v[3] = {q[0][2], q[1][2], q[NF - 1][2]};
+            L[lc] = dvec2{v[0], second(v)};
+        }
+#pragma unroll
+        for (int s = 0; s < T::HS; ++s)
+            if (w.hl[s] >= 0) {
+                const double v[3] = {X.hv[0][s], X.hv[1][s], X.hv[NF - 1][s]};
+                L[w.hl[s]] = dvec2{v[0], second(v)};
+            }
         double pwc[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -1200,23 +1245,32 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
             fetch(k + 2, X);
         lds_barrier();
         if (w.active) {
-            const double *L0 = L, *L1 = L + PLANE;
-            const double a1 = K1.a, a2 = K2.a;
-            const int X1 = 1, X2 = 2, Y1 = T::LX, Y2 = 2 * T::LX;
+            const double a2 = K2.a;
             const double c2 = pwc[0];
+            // x and y tap sums of both stencil inputs (four 16-byte taps in
+            // registers at a time)
+            double sx0, sx1, sy0, sy1;
+            {
+                const dvec2 m2 = L[lc - 2], m1 = L[lc - 1], p1 = L[lc + 1], p2 = L[lc + 2];
+                sx0 = axis4(m2.x, m1.x, p1.x, p2.x);
+                sx1 = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                const dvec2 m2 = L[lc - 2 * T::LX], m1 = L[lc - T::LX], p1 = L[lc + T::LX], p2 = L[lc + 2 * T::LX];
+                sy0 = axis4(m2.x, m1.x, p1.x, p2.x);
+                sy1 = axis4(m2.y, m1.y, p1.y, p2.y);
+            }
             if constexpr (PAIR == 0) {
                 // stage 1: L u_n
                 const double un = q[0][2], rn = q[1][2];
-                const double lap1 = lap4(B, un, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
-                                         L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
+                const double lap1 = lap4s(B, un, sx0, sy0, axis4(q[0][0], q[0][1], q[0][3], q[0][4]));
                 const double kr1 = c2 * lap1;
                 const double u2 = fma(a1, rn, un);
                 const double r2 = fma(a1, kr1, rn);
                 // stage 2: L u_2 with u_2 = u_n + a1 rho_n at every tap
-                auto t = [&](int o) { return fma(a1, L1[lc + o], L0[lc + o]); };
                 auto tz = [&](int d) { return fma(a1, q[1][d], q[0][d]); };
-                const double lap2 = lap4(B, u2, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
-                                         tz(1), tz(3), tz(4));
+                const double lap2 = lap4s(B, u2, sx1, sy1, axis4(tz(0), tz(1), tz(3), tz(4)));
                 const double kr2 = c2 * lap2;
                 const int64_t c = w.point(B, k);
                 st(B.q[0] + c, fma(a2, r2, un));
@@ -1226,22 +1280,18 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
                     st(B.q[3] + c, fma(K2.b, kr2, fma(1.0 / 3.0, r2 - rn, rn)));
                 }
             } else {
-                const double *L2 = L + 2 * PLANE;
                 // stage 3: L u_3
                 const double u3 = q[0][2], r3 = q[1][2], un = q[2][2];
                 const double rn = pwc[1], au = pwc[2], ar = pwc[3];
-                const double lap3 = lap4(B, u3, L0[lc - X2], L0[lc - X1], L0[lc + X1], L0[lc + X2], L0[lc - Y2],
-                                         L0[lc - Y1], L0[lc + Y1], L0[lc + Y2], q[0][0], q[0][1], q[0][3], q[0][4]);
+                const double lap3 = lap4s(B, u3, sx0, sy0, axis4(q[0][0], q[0][1], q[0][3], q[0][4]));
                 const double kr3 = c2 * lap3;
                 const double u4 = fma(a1, r3, un);
                 const double r4 = fma(a1, kr3, rn);
                 const double au4 = fma(K1.b, r3, au);
                 const double ar4 = fma(K1.b, kr3, ar);
                 // stage 4: L u_4 with u_4 = u_n + a3 rho_3 at every tap
-                auto t = [&](int o) { return fma(a1, L1[lc + o], L2[lc + o]); };
                 auto tz = [&](int d) { return fma(a1, q[1][d], q[2][d]); };
-                const double lap4v = lap4(B, u4, t(-X2), t(-X1), t(X1), t(X2), t(-Y2), t(-Y1), t(Y1), t(Y2), tz(0),
-                                          tz(1), tz(3), tz(4));
+                const double lap4v = lap4s(B, u4, sx1, sy1, axis4(tz(0), tz(1), tz(3), tz(4)));
                 const double kr4 = c2 * lap4v;
                 const int64_t c = w.point(B, k);
                 st(B.q[0] + c, fma(K2.b, r4, au4));
@@ -1263,7 +1313,7 @@ __device__ __forceinline__ void run_pair2(const DevBox &B, const ItemPos &P, con
 template <int TX, int NW, int PAIR, bool WRAP>
 __global__ __launch_bounds__(NW * 64, 4) void k_pair2(DevBox B, StageCoef K1, StageCoef K2, int nxcd)
 {
-    __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
+    __shared__ __attribute__((aligned(16))) double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
     const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     const ItemPos P = item_pos(B, item, TX, Tile<TX, NW>::TY);
     run_pair2<TX, NW, PAIR, WRAP>(B, P, K1, K2, lds);
@@ -1274,7 +1324,7 @@ template <int TX, int NW, int PAIR, bool WRAP>
 __global__ __launch_bounds__(NW * 64, 4) void k_pair2_batched(const DevBox *__restrict__ tab, int nbox, ItemQueue Q,
                                                           StageCoef K1, StageCoef K2)
 {
-    __shared__ double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
+    __shared__ __attribute__((aligned(16))) double lds[Pair2Lds<TX, NW, PAIR>::SIZE];
     __shared__ int s_item;
     int q = blockIdx.x % Q.nq, left = Q.nq;
     for (;;) {
@@ -1310,8 +1360,9 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pair2_batched(const DevBox *__re
 // only at the point).  With c2bar, pass A also applies L to u_3 and to
 // u_4 = u_n + dt rho_3 (formed per tap; u_3, rho_3 from the forward
 // stage-pair kernel) and pass B to u_1 = u_n and u_2 = u_n + dt/2 rho_n.
-// The LDS and the z queues hold the transformed values t (NL fields); the
-// raw values two planes ahead are loaded into registers first.
+// The LDS and the z queues hold the transformed values t (NL fields, in
+// LDS as 16-byte pairs of fields 0, 1 and 2, 3); the raw values two planes
+// ahead are loaded into registers first.
 //   pass A:  in lu, p0 lr, p1 u_3, p2 u_n, p3 rho_3, p5 c^2, p6 c2bar;
 //            out q0 kr2, q1 kr1, q2 acc_u, q3 acc_rho, q4 c2bar
 //   pass B:  in kr2, p0 kr1, p1 u_n, p2 rho_n, p3 acc_u, p4 acc_rho, p5 c^2,
@@ -1372,7 +1423,8 @@ __global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxc
     using A = AdjPass<PASS, C2BAR>;
     constexpr int NL = A::NL, NR = A::NR;
     constexpr int PLANE = T::LY * T::LX;
-    __shared__ double lds[2 * NL * PLANE];
+    constexpr int NP = NL / 2; // LDS planes of field pairs
+    __shared__ __attribute__((aligned(16))) double lds[2 * NL * PLANE];
     const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     const ItemPos P = item_pos(B, item, TX, T::TY);
     const Walker<TX, NW, true> w(B, P, threadIdx.x);
@@ -1409,14 +1461,14 @@ __global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxc
     }
     int buf = 0;
     for (int k = P.z0; k < P.z1; ++k) {
-        double *L = lds + buf * NL * PLANE;
+        dvec2 *L = (dvec2 *)lds + buf * NP * PLANE;
 #pragma unroll
-        for (int f = 0; f < NL; ++f) {
-            L[f * PLANE + lc] = q[f][2];
+        for (int p = 0; p < NP; ++p) {
+            L[p * PLANE + lc] = dvec2{q[2 * p][2], q[2 * p + 1][2]};
 #pragma unroll
             for (int s = 0; s < T::HS; ++s)
                 if (w.hl[s] >= 0)
-                    L[f * PLANE + w.hl[s]] = hv[f][s];
+                    L[p * PLANE + w.hl[s]] = dvec2{hv[2 * p][s], hv[2 * p + 1][s]};
         }
         lds_barrier();
         const bool more = k + 1 < P.z1;
@@ -1430,15 +1482,32 @@ __global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxc
         }
         if (w.active) {
             const int64_t c = w.point(B, k);
-            auto lapf = [&](int f) {
-                const double *Lf = L + f * PLANE;
-                return lap4(B, q[f][2], Lf[lc - 2], Lf[lc - 1], Lf[lc + 1], Lf[lc + 2], Lf[lc - 2 * T::LX],
-                            Lf[lc - T::LX], Lf[lc + T::LX], Lf[lc + 2 * T::LX], q[f][0], q[f][1], q[f][3], q[f][4]);
+            // L of fields 2p and 2p+1 (x taps, then y taps: four 16-byte
+            // taps in registers at a time)
+            auto lapp = [&](int p, double &la, double &lb) {
+                const dvec2 *Lp = L + p * PLANE;
+                double sxa, sxb, sya, syb;
+                {
+                    const dvec2 m2 = Lp[lc - 2], m1 = Lp[lc - 1], p1 = Lp[lc + 1], p2 = Lp[lc + 2];
+                    sxa = axis4(m2.x, m1.x, p1.x, p2.x);
+                    sxb = axis4(m2.y, m1.y, p1.y, p2.y);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                {
+                    const dvec2 m2 = Lp[lc - 2 * T::LX], m1 = Lp[lc - T::LX], p1 = Lp[lc + T::LX],
+                                p2 = Lp[lc + 2 * T::LX];
+                    sya = axis4(m2.x, m1.x, p1.x, p2.x);
+                    syb = axis4(m2.y, m1.y, p1.y, p2.y);
+                }
+                const int fa = 2 * p, fb = 2 * p + 1;
+                la = lap4s(B, q[fa][2], sxa, sya, axis4(q[fa][0], q[fa][1], q[fa][3], q[fa][4]));
+                lb = lap4s(B, q[fb][2], sxb, syb, axis4(q[fb][0], q[fb][1], q[fb][3], q[fb][4]));
             };
             const double dt = K.a, d6 = K.b, d3 = K.a_next, d2 = K.b_next;
             if constexpr (PASS == 0) {
                 const double lu = rq[0][0], lr = rq[1][0];
-                const double Y4 = lapf(0), Y3 = lapf(1);
+                double Y4, Y3;
+                lapp(0, Y4, Y3);
                 const double ku4 = d6 * lu, kr4 = d6 * lr;
                 const double kr3 = fma(dt, ku4, d3 * lr);
                 const double ku3 = fma(dt, Y4, d3 * lu);
@@ -1450,18 +1519,21 @@ __global__ __launch_bounds__(NW * 64) void k_adj2(DevBox B, StageCoef K, int nxc
                 st(B.q[2] + c, lu + Y4 + Y3);
                 st(B.q[3] + c, lr + ku4 + ku3 + ku2);
                 if constexpr (C2BAR) {
-                    const double Lu3 = lapf(2), Lu4 = lapf(3);
+                    double Lu3, Lu4;
+                    lapp(1, Lu3, Lu4);
                     st(B.q[4] + c, fma(kr4, Lu4, fma(kr3, Lu3, ldp(B.p[6] + c))));
                 }
             } else {
                 const double kr2 = rq[0][0], kr1 = rq[1][0];
-                const double Y2 = lapf(0), Y1 = lapf(1);
+                double Y2, Y1;
+                lapp(0, Y2, Y1);
                 const double lu = ldp(B.q[0] + c);
                 const double ku1 = fma(d2, Y2, d6 * lu);
                 st(B.q[0] + c, ldp(B.p[3] + c) + Y2 + Y1);
                 st(B.q[1] + c, ldp(B.p[4] + c) + ku1);
                 if constexpr (C2BAR) {
-                    const double Lu1 = lapf(2), Lu2 = lapf(3);
+                    double Lu1, Lu2;
+                    lapp(1, Lu1, Lu2);
                     st(B.q[4] + c, fma(kr2, Lu2, fma(kr1, Lu1, ldp(B.p[6] + c))));
                 }
             }
@@ -1886,7 +1958,7 @@ hipError_t launch_rk4_step4(int txe, int nw, const DevBox &B, const StageCoef K[
             Y(k_rk4_step4, TXE_, NW_, false);                                                          \
         return hipGetLastError();                                                                      \
     }
-    X(32, 8) X(64, 16) X(32, 16)
+    X(32, 8) X(64, 16) X(32, 16) X(68, 16)
 #undef X
 #undef Y
 #undef G
@@ -1911,7 +1983,7 @@ hipError_t launch_rk4_step4_batched(int txe, int nw, bool hasc2, const DevBox *t
             Y(TXE_, NW_, false, true);                                                                 \
         return hipGetLastError();                                                                      \
     }
-    X(32, 8) X(64, 16) X(32, 16)
+    X(32, 8) X(64, 16) X(32, 16) X(68, 16)
 #undef X
 #undef Y
     return hipErrorInvalidValue;
@@ -1924,7 +1996,7 @@ int max_blocks_step4(int txe, int nw)
 #define X(TXE_, NW_)                                                                                   \
     if (txe == TXE_ && nw == NW_)                                                                      \
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_step4<TXE_, NW_, true>, NW_ * 64, 0);
-    X(32, 8) X(64, 16) X(32, 16)
+    X(32, 8) X(64, 16) X(32, 16) X(68, 16)
 #undef X
     return e == hipSuccess ? nb : 0;
 }

@@ -246,7 +246,9 @@ static void run_mixed(int nx, int ny, int nz, int g, int padx, int tz_req)
 // the fused stage-pair traversal (k_rk4_pair): first stage on the whole
 // TXE x TYE region from a 4-plane ring, second stage two planes behind on
 // the inner tile from a 3-plane ring, periodic addressing.  Tags encode a
-// point (wrapped into the box) and the stage that produced it.
+// point (wrapped into the box) and the stage that produced it.  The whole
+// RK4 step (k_rk4_step4) walks the same widened tile, also with 68-point
+// rows, where the threads past the tile's 15 rows repeat its last point.
 static int mod3h(int p)
 {
     const int r = p % 3;
@@ -285,7 +287,7 @@ static void run_pair(int nx, int ny, int nz, int g, int padx, int tz_req)
         Pe.y0 -= 2;
         std::vector<Walker<TXE, NW, true, false>> W;
         for (int t = 0; t < T::NT; ++t)
-            W.emplace_back(B, Pe, t);
+            W.emplace_back(B, Pe, tile_thread<TXE, NW>(t));
         std::vector<int64_t> qa(T::NT * 5, -1), qb(T::NT * 5, -1);
         std::fill(ring1.begin(), ring1.end(), -1);
         std::fill(ring2.begin(), ring2.end(), -1);
@@ -320,7 +322,8 @@ static void run_pair(int nx, int ny, int nz, int g, int padx, int tz_req)
                         CHECK(L[w.lc + d * T::LX] == tag(w.i, w.j + d, p1, 0), "pair stage-1 y tap");
                         CHECK(qa[t * 5 + 2 + d] == tag(w.i, w.j, p1 + d, 0), "pair stage-1 z tap");
                     }
-                    const int lx = t % TXE, ly = t / TXE;
+                    const int tl = tile_thread<TXE, NW>(t), lx = tl % TXE, ly = tl / TXE;
+                    CHECK(ly * TXE + lx < P2, "pair ring-2 slot out of range");
                     ring2[mod3h(p1) * P2 + ly * TXE + lx] = tag(w.i, w.j, p1, 1);
                     for (int d = 0; d < 4; ++d)
                         qb[t * 5 + d] = qb[t * 5 + d + 1];
@@ -330,7 +333,7 @@ static void run_pair(int nx, int ny, int nz, int g, int padx, int tz_req)
             // second stage at p2, output lanes
             for (int t = 0; t < T::NT; ++t) {
                 const auto &w = W[t];
-                const int lx = t % TXE, ly = t / TXE;
+                const int tl = tile_thread<TXE, NW>(t), lx = tl % TXE, ly = tl / TXE;
                 const bool out = lx >= 2 && lx < TXE - 2 && ly >= 2 && ly < TYE - 2 && w.i < nx && w.j < ny;
                 if (!(out && p2 >= P.z0 && p2 < P.z1))
                     continue;
@@ -651,7 +654,8 @@ int main()
 {
     const int RS[][6] = {{256, 256, 256, 60, 12, 110}, {256, 256, 256, 28, 12, 64}, {5, 7, 3, 60, 12, 2},
                          {70, 9, 5, 28, 28, 1},         {1, 1, 1, 60, 4, 16},       {97, 33, 41, 60, 4, 1000},
-                         {32, 32, 32, 28, 12, 1},       {48, 48, 48, 28, 12, 2},    {96, 96, 96, 28, 12, 6}};
+                         {32, 32, 32, 28, 12, 1},       {48, 48, 48, 28, 12, 2},    {96, 96, 96, 28, 12, 6},
+                         {256, 256, 256, 64, 11, 96},   {70, 33, 17, 64, 11, 5}};
     for (auto &r : RS)
         runs_check(r[0], r[1], r[2], r[3], r[4], r[5]);
     const int QS[][3] = {{1000, 8, 64}, {7, 8, 3}, {0, 8, 4}, {1, 8, 16}, {5000, 8, 1}, {123, 1, 9}, {97, 15, 40}};
@@ -668,7 +672,10 @@ int main()
         run_pair<64, 8>(s[0], s[1], s[2], s[3], s[4], s[5]);
         run_pair<64, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
         run_pair<32, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
+        run_pair<68, 16>(s[0], s[1], s[2], s[3], s[4], s[5]);
     }
+    run_pair<68, 16>(256, 24, 9, 2, 0, 4);
+    run_pair<68, 16>(131, 23, 6, 2, 5, 0);
     row_shapes<4, 4>();
     row_shapes<4, 2>();
     row_shapes<2, 4>();

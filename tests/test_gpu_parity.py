@@ -389,8 +389,10 @@ def test_heuristic_kernel_sets(ctx):
     c128 = S.make_box((128, 128, 128), 2, (1, 144, 144 * 132), 1 / 128)
     ch = S.s4_get_choice(fresh, S.S4_OP_RK4, c128)
     assert (ch["kernel_op"], ch["tile_x"], ch["tile_y"], ch["z_chunk"]) == (102, 32, 16, 16), ch
+    # 256^3: 68 x 15 lanes, whose 64-point output rows cover x in four tiles,
+    # in 32-plane chunks (96 tiles x 8 chunks: three rounds of one workgroup per CU)
     ch = S.s4_get_choice(fresh, S.S4_OP_RK4, b)
-    assert ch["z_chunk"] != 16, ch
+    assert (ch["kernel_op"], ch["tile_x"], ch["tile_y"], ch["z_chunk"]) == (102, 68, 15, 32), ch
     big = S.make_box((16384, 16384, 4), 2, (1, 16400, 16400 * 16388), 1.0)
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, big)["kernel_op"] == 101
     assert S.s4_get_choice(fresh, S.S4_OP_RK4, [b, big])["kernel_op"] == 101

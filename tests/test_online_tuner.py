@@ -14,10 +14,10 @@ CANDS = [(0, tx, nw, tz, 0) for tx in (64, 32, 16) for nw in (8, 4) for tz in (0
         [(2, tx, 4, tz, ry) for tx in (256, 128, 64) for ry in (4, 2) for tz in (64, 32, 16)] + \
         [(3, tx, nw, tz, 0) for tx, nw in ((64, 4), (64, 8), (32, 8), (32, 4), (16, 8), (16, 4))
          for tz in (64, 32, 16)] + \
-        [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8)) for tz in (0, 128, 64, 32, 16)] + \
+        [(4, tx, nw, tz, 0) for tx, nw in ((64, 16), (32, 16), (32, 8), (68, 16)) for tz in (0, 128, 64, 32, 16)] + \
         [(1, tx, nw, tz, 0) for tx, nw in ((32, 8), (64, 8), (64, 16), (32, 16)) for tz in (64, 32, 16)] + \
         [(5, tx, nw, tz, 0) for tx in (64, 32) for nw in (8, 4) for tz in (64, 32, 16)]
-ORD_TX = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}
+ORD_TX = {16: 0, 32: 1, 64: 2, 68: 2, 128: 3, 256: 4}
 ORD_NW = {4: 0, 8: 1, 16: 2}
 ORD_TZ = {8: 0, 16: 1, 32: 2, 64: 3, 128: 4, 0: 5}
 ORD_RY = {0: 0, 2: 0, 4: 1}
@@ -26,7 +26,7 @@ BOX = S.make_box((256, 256, 256), 2, (1, 272, 272 * 260), 1 / 256)
 
 def dist(a, b):
     return (abs(ORD_TX[a[1]] - ORD_TX[b[1]]) + abs(ORD_NW[a[2]] - ORD_NW[b[2]]) + abs(ORD_TZ[a[3]] - ORD_TZ[b[3]]) +
-            abs(ORD_RY[a[4]] - ORD_RY[b[4]]))
+            abs(ORD_RY[a[4]] - ORD_RY[b[4]]) + ((a[1] == 68) != (b[1] == 68)))
 
 
 def bowl(center, slope=0.05, other_variant=2.0):
@@ -141,7 +141,8 @@ def test_whole_steps_skipped_for_huge_planes():
     tr = S.s4_online_simulate(S.S4_OP_RK4, huge, cost, restart_prob=0.3, ncalls=400)
     assert all(CANDS[t][0] != 4 for t in tr)
     tr = S.s4_online_simulate(S.S4_OP_RK4, BOX, cost, restart_prob=0.3, ncalls=400)
-    assert CANDS[tr[-1]][0] == 4
+    # (restarts take 30 % of the calls here: the search's home is what counts)
+    assert sum(CANDS[t][0] == 4 for t in tr[-100:]) > 50
 
 
 def cube(n):
@@ -156,10 +157,14 @@ def test_whole_step_start_follows_the_cost_model():
     """The untuned whole-step setting of one periodic box (the search's start):
     equal 8-plane runs on 32 x 16 lanes for boxes too small to fill the GPU,
     else the shape and work order the cost model rates cheapest -- 28 x 28
-    output tiles where the box divides into them (224^3, 448^3), 60 x 12
-    tiles on most large cubes."""
-    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 16, 0), 160: (4, 32, 8, 32, 0), 192: (4, 64, 16, 0, 0),
-            224: (4, 32, 16, 0, 0), 256: (4, 64, 16, 128, 0), 384: (4, 64, 16, 0, 0), 448: (4, 32, 16, 0, 0)}
+    output tiles where the box divides into them (224^3, 448^3), 64 x 11
+    tiles of 68-point rows where 64 divides the side (256^3, 320^3, 384^3,
+    512^3), 60 x 12 tiles on 160^3 and 192^3 (the model's picks are within
+    0.5 % of the fastest measured setting on the cubes of side 128 to 512
+    that step by 64)."""
+    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 16, 0), 160: (4, 64, 16, 32, 0), 192: (4, 64, 16, 0, 0),
+            224: (4, 32, 16, 64, 0), 256: (4, 68, 16, 32, 0), 320: (4, 68, 16, 64, 0), 384: (4, 68, 16, 64, 0),
+            448: (4, 32, 16, 64, 0), 512: (4, 68, 16, 128, 0)}
     for n, w in want.items():
         assert start_of(S.S4_OP_RK4, cube(n)) == w, n
     # a set of boxes keeps 32-plane chunks on 32 x 16 lanes
