@@ -1599,26 +1599,44 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
     const double d1x = M.d1[0], d1y = M.d1[1], d1z = M.d1[2];
     const double d2x = M.d2[0], d2y = M.d2[1], d2z = M.d2[2];
 
-    double fq0 = 0, fq1 = 0, fq2 = 0, fq3 = 0, fq4 = 0; // f at planes kk-4 .. kk
-    double xq0 = 0, xq1 = 0, xq2 = 0, xq3 = 0, xq4 = 0; // D1_x f
-    double yq0 = 0, yq1 = 0, yq2 = 0, yq3 = 0, yq4 = 0; // D1_y f
-    double pq0 = 0, pq1 = 0, pq2 = 0;                   // D2_x + D2_y + D_xy at kk-2 .. kk
-    int buf = 0;
-    for (int kk = P.z0 - 2; kk <= P.z1 + 1; ++kk) {
+    // Column queues of f, D1_x f and D1_y f at planes kk-4 .. kk: plane step
+    // t writes the newest plane to slot t mod 5, so the planes rotate through
+    // fixed registers (the loop below is unrolled ten-fold: five slots times
+    // two fetch buffers; every slot index is a compile-time constant).
+    double fq[5] = {0, 0, 0, 0, 0}, xq[5] = {0, 0, 0, 0, 0}, yq[5] = {0, 0, 0, 0, 0};
+    double pq0 = 0, pq1 = 0, pq2 = 0; // D2_x + D2_y + D_xy at kk-2 .. kk
+    // The loads of plane kk+1 are issued as plane kk starts, into the one of
+    // two buffers that alternate planes (so no register a load is still
+    // filling is copied), and fly across the plane's two barriers.
+    struct Fetched {
+        double fv, hv[MT::HS];
+    };
+    auto fetch = [&](int kk, Fetched &X) {
         const int64_t zo = w.zoff(kk);
-        const double fv = f[w.col + zo];
-        double hv[MT::HS];
+        X.fv = f[w.col + zo];
 #pragma unroll
         for (int s = 0; s < MT::HS; ++s)
             if (w.hl[s] >= 0)
-                hv[s] = f[w.hcol[s] + zo];
-        double *F = sf + buf * MT::PF;
-        double *D = sd + buf * MT::PD;
+                X.hv[s] = f[w.hcol[s] + zo];
+    };
+    const int kfirst = P.z0 - 2, klast = P.z1 + 1;
+    Fetched F0, F1;
+    // plane step t = kk - kfirst = t0 + J with t0 a multiple of 10
+    auto plane = [&](auto Jc, const int kk) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int S0 = (J + 1) % 5, S1 = (J + 2) % 5, S2 = (J + 3) % 5, S3 = (J + 4) % 5, S4 = J % 5;
+        const Fetched &X = (J & 1) ? F1 : F0;
+        Fetched &Y = (J & 1) ? F0 : F1;
+        if (kk < klast)
+            fetch(kk + 1, Y);
+        const double fv = X.fv;
+        double *F = sf + (J & 1) * MT::PF;
+        double *D = sd + (J & 1) * MT::PD;
         F[w.lf] = fv;
 #pragma unroll
         for (int s = 0; s < MT::HS; ++s)
             if (w.hl[s] >= 0)
-                F[w.hl[s]] = hv[s];
+                F[w.hl[s]] = X.hv[s];
         lds_barrier();
         const int c = w.lf;
         const double xm2 = F[c - 2], xm1 = F[c - 1], xp1 = F[c + 1], xp2 = F[c + 2];
@@ -1638,16 +1656,18 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
         const int dd = w.ld;
         const double gxy = d1y * fma(8.0, D[dd + TX] - D[dd - TX], -(D[dd + 2 * TX] - D[dd - 2 * TX]));
         const double pin = fma(d2x, fma(-30.0, fv, sx), fma(d2y, fma(-30.0, fv, sy), gxy));
-        fq0 = fq1; fq1 = fq2; fq2 = fq3; fq3 = fq4; fq4 = fv;
-        xq0 = xq1; xq1 = xq2; xq2 = xq3; xq3 = xq4; xq4 = gx;
-        yq0 = yq1; yq1 = yq2; yq2 = yq3; yq3 = yq4; yq4 = gy;
-        pq0 = pq1; pq1 = pq2; pq2 = pin;
+        fq[S4] = fv;
+        xq[S4] = gx;
+        yq[S4] = gy;
+        pq0 = pq1;
+        pq1 = pq2;
+        pq2 = pin;
         if (kk >= P.z0 + 2 && w.active) {
-            const double gz = d1z * fma(8.0, fq3 - fq1, -(fq4 - fq0));
-            const double d2zv = d2z * fma(-30.0, fq2, fma(16.0, fq1 + fq3, -(fq0 + fq4)));
-            const double gxz = d1z * fma(8.0, xq3 - xq1, -(xq4 - xq0));
-            const double gyz = d1z * fma(8.0, yq3 - yq1, -(yq4 - yq0));
-            const double ex = xq2, ey = yq2;
+            const double gz = d1z * fma(8.0, fq[S3] - fq[S1], -(fq[S4] - fq[S0]));
+            const double d2zv = d2z * fma(-30.0, fq[S2], fma(16.0, fq[S1] + fq[S3], -(fq[S0] + fq[S4])));
+            const double gxz = d1z * fma(8.0, xq[S3] - xq[S1], -(xq[S4] - xq[S0]));
+            const double gyz = d1z * fma(8.0, yq[S3] - yq[S1], -(yq[S4] - yq[S0]));
+            const double ex = xq[S2], ey = yq[S2];
             double q = M.a[0] * ex * ex;
             q = fma(M.a[1] * ey, ey, q);
             q = fma(M.a[2] * gz, gz, q);
@@ -1657,7 +1677,29 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
             const double lin2 = pq0 + d2zv + gxz + gyz;
             st(out + w.point(B, kk - 2), lin2 + q);
         }
-        buf ^= 1;
+    };
+    fetch(kfirst, F0);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    using I6 = std::integral_constant<int, 6>;
+    using I7 = std::integral_constant<int, 7>;
+    using I8 = std::integral_constant<int, 8>;
+    using I9 = std::integral_constant<int, 9>;
+    for (int kk = kfirst; kk <= klast; kk += 10) {
+        plane(I0{}, kk);
+        if (kk + 1 <= klast) plane(I1{}, kk + 1);
+        if (kk + 2 <= klast) plane(I2{}, kk + 2);
+        if (kk + 3 <= klast) plane(I3{}, kk + 3);
+        if (kk + 4 <= klast) plane(I4{}, kk + 4);
+        if (kk + 5 <= klast) plane(I5{}, kk + 5);
+        if (kk + 6 <= klast) plane(I6{}, kk + 6);
+        if (kk + 7 <= klast) plane(I7{}, kk + 7);
+        if (kk + 8 <= klast) plane(I8{}, kk + 8);
+        if (kk + 9 <= klast) plane(I9{}, kk + 9);
     }
 }
 
