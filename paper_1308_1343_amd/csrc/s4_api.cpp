@@ -469,13 +469,14 @@ static int64_t step4_run_length(int64_t total, int64_t slots, int ncu)
 // orders.  z chunks: rounds of resident workgroups times the planes one item
 // streams (its chunk plus the 8-plane start-up of the pipeline).  Equal runs
 // (tz 0): the planes of the busiest run plus 8 for every tile column it
-// touches, in one round.  Each shape and order has its own cost per plane,
-// the geometric mean over periodic cubes of side 192 to 512 (relative to
-// 32 x 16 lanes in 32-plane chunks; the model then picks within 0.5 % of
-// the fastest setting on each of those cubes and on 128^3): equal runs lose
-// L2 locality, a 1024-lane workgroup alone on its CU hides less latency per
-// lane, and 68 x 15 lanes trade idle lanes for whole output rows on boxes
-// 64 points wide in x.
+// touches, in one round.  Each shape and order has its own cost per plane
+// (relative to 32 x 16 lanes in 32-plane chunks), fitted to the measured
+// step times of all 20 settings on periodic cubes of side 128, 192, 224,
+// 256, 320, 384, 448 and 512: each within 12 % of its mean ratio of time to
+// modelled planes, and with them the model picks the fastest measured
+// setting on each of those cubes.  Equal runs lose L2 locality, a 1024-lane
+// workgroup alone on its CU hides less latency per lane, and 68 x 15 lanes
+// trade idle lanes for whole output rows on boxes 64 points wide in x.
 static int step4_single(const s4_ctx *ctx, const s4_box &b)
 {
     struct Opt {
@@ -483,11 +484,11 @@ static int step4_single(const s4_ctx *ctx, const s4_box &b)
         double per_plane;
     };
     static const Opt opts[] = {
-        {32, 8, 0, 0, 1.449},   {32, 8, 128, 0, 1.033},  {32, 8, 64, 0, 1.098},  {32, 8, 32, 0, 1.0},
-        {32, 8, 16, 0, 1.010},  {64, 16, 0, 1, 1.267},   {64, 16, 128, 1, 1.059}, {64, 16, 64, 1, 1.034},
-        {64, 16, 32, 1, 0.995}, {64, 16, 16, 1, 0.986},  {32, 16, 0, 2, 1.545},  {32, 16, 128, 2, 1.215},
-        {32, 16, 64, 2, 1.244}, {32, 16, 32, 2, 1.126},  {32, 16, 16, 2, 1.073}, {68, 16, 0, 3, 1.339},
-        {68, 16, 128, 3, 1.109}, {68, 16, 64, 3, 1.134}, {68, 16, 32, 3, 1.086}, {68, 16, 16, 3, 1.030}};
+        {32, 8, 0, 0, 1.368},   {32, 8, 128, 0, 1.004},  {32, 8, 64, 0, 1.028},  {32, 8, 32, 0, 1.015},
+        {32, 8, 16, 0, 0.984},  {64, 16, 0, 1, 1.196},   {64, 16, 128, 1, 1.152}, {64, 16, 64, 1, 1.087},
+        {64, 16, 32, 1, 1.035}, {64, 16, 16, 1, 1.060},  {32, 16, 0, 2, 1.371},  {32, 16, 128, 2, 1.288},
+        {32, 16, 64, 2, 1.361}, {32, 16, 32, 2, 1.166},  {32, 16, 16, 2, 1.125}, {68, 16, 0, 3, 1.295},
+        {68, 16, 128, 3, 1.252}, {68, 16, 64, 3, 1.102}, {68, 16, 32, 3, 1.101}, {68, 16, 16, 3, 1.139}};
     int best = cand_index(32, 8, 32, 4);
     {
         // too few tile-planes to give every resident 512-lane workgroup 8

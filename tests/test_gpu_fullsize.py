@@ -195,10 +195,10 @@ def test_bboxset60_step_all_modes_vs_oracle(ctx, nsteps):
 @pytest.mark.parametrize("n,shape", [(224, (32, 32)), (272, (64, 16)), (320, (68, 15))])
 def test_large_cubes_default_setting_vs_oracle(n, shape):
     """Two steps on single periodic cubes whose untuned whole-step setting is a
-    1024-lane shape (28 x 28 output tiles dividing 224^3 exactly; 60 x 12
-    tiles in equal runs at 272^3; 64 x 11 tiles of 68-point rows, four
-    idle lanes per workgroup, in 64-plane chunks at 320^3), against the
-    oracle."""
+    1024-lane shape (28 x 28 output tiles dividing 224^3 exactly, in equal
+    runs; 60 x 12 tiles in equal runs at 272^3; 64 x 11 tiles of 68-point
+    rows, four idle lanes per workgroup, in 64-plane chunks at 320^3),
+    against the oracle."""
     fresh = S.Context(0)
     g, nn = 2, (n, n, n)
     u0, r0 = W.uniform_pm1(7, 1, nn), W.uniform_pm1(7, 2, nn)

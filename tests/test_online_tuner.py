@@ -157,14 +157,14 @@ def test_whole_step_start_follows_the_cost_model():
     """The untuned whole-step setting of one periodic box (the search's start):
     equal 8-plane runs on 32 x 16 lanes for boxes too small to fill the GPU,
     else the shape and work order the cost model rates cheapest -- 28 x 28
-    output tiles where the box divides into them (224^3, 448^3), 64 x 11
-    tiles of 68-point rows where 64 divides the side (256^3, 320^3, 384^3,
-    512^3), 60 x 12 tiles on 160^3 and 192^3 (the model's picks are within
-    0.5 % of the fastest measured setting on the cubes of side 128 to 512
-    that step by 64)."""
-    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 16, 0), 160: (4, 64, 16, 32, 0), 192: (4, 64, 16, 0, 0),
-            224: (4, 32, 16, 64, 0), 256: (4, 68, 16, 32, 0), 320: (4, 68, 16, 64, 0), 384: (4, 68, 16, 64, 0),
-            448: (4, 32, 16, 64, 0), 512: (4, 68, 16, 128, 0)}
+    output tiles in equal runs where the box divides into them (224^3,
+    448^3), 64 x 11 tiles of 68-point rows where 64 divides the side (256^3,
+    320^3, 384^3, 512^3), 60 x 12 tiles in equal runs on 192^3 and 272^3 (on
+    the cubes of side 128, 192, 224, 256, 320, 384, 448 and 512 these are the
+    fastest measured settings)."""
+    want = {64: (4, 32, 8, 0, 0), 128: (4, 32, 8, 16, 0), 160: (4, 32, 8, 32, 0), 192: (4, 64, 16, 0, 0),
+            224: (4, 32, 16, 0, 0), 256: (4, 68, 16, 32, 0), 272: (4, 64, 16, 0, 0), 320: (4, 68, 16, 64, 0),
+            384: (4, 68, 16, 64, 0), 448: (4, 32, 16, 0, 0), 512: (4, 68, 16, 64, 0)}
     for n, w in want.items():
         assert start_of(S.S4_OP_RK4, cube(n)) == w, n
     # a set of boxes keeps 32-plane chunks on 32 x 16 lanes
