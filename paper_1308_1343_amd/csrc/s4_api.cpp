@@ -654,14 +654,20 @@ static void online_harvest(OnlineSetup &st);
 // while another setting gives every CU one (with most of the device idle
 // they cannot win, and one call on them costs many: on a 128^3 box a
 // whole-box z chunk of 64 x 8 tiles runs 32 workgroups and takes ten times
-// the best setting's time).  Whole steps in equal runs spread over every CU.
+// the best setting's time).  Whole steps in equal runs count their runs.
 static std::vector<int> online_allowed(const s4_ctx *ctx, int op, const s4_box *b, int nbox, int level)
 {
     const std::vector<int> all = allowed_cands(op, b, nbox, level);
     auto work = [&](int ci) {
         const Cand &c = cands()[ci];
-        if (c.variant == 4 && c.tz == 0 && nbox == 1)
-            return (int64_t)ctx->ncu;
+        if (c.variant == 4 && c.tz == 0 && nbox == 1) {
+            const int64_t total = items_of(b[0], c); // tile columns x one whole-box chunk
+            const int64_t planes = total * b[0].n[2];
+            const int shape = c.tx == 32 ? (c.nw == 8 ? 0 : 2) : c.tx == 64 ? 1 : 3;
+            const int64_t per = std::max(1, ctx->step4_per[shape]);
+            const int64_t R = step4_run_length(planes, per * ctx->ncu, ctx->ncu);
+            return (planes + R - 1) / R;
+        }
         int64_t n = 0;
         for (int i = 0; i < nbox; ++i)
             n += items_of(b[i], c);

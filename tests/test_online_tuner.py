@@ -181,3 +181,19 @@ def test_mixed_kernel_start():
     assert start_of(S.S4_OP_DERIV_MIXED, cube(112)) == (0, 32, 4, 16, 0)
     assert start_of(S.S4_OP_DERIV_MIXED, cube(64)) == (0, 32, 4, 8, 0)
     assert start_of(S.S4_OP_DERIV_MIXED, cube(20)) == (0, 16, 4, 8, 0)
+
+
+def test_search_skips_settings_that_starve_the_device():
+    """On a 128^3 box the search never visits a setting whose launch hands
+    fewer work items than a quarter of the CUs (e.g. per-stage kernels with
+    whole-box z chunks of 64 x 8 tiles: 32 items) while other settings give
+    every CU one, even where it would be the cheapest and restarts are
+    frequent; such settings stay reachable on boxes that no setting fills."""
+    b = cube(128)
+    starving = CANDS.index((0, 64, 8, 0, 0))
+    cost = [0.5 if i == starving else 1.0 + 0.001 * i for i in range(len(CANDS))]
+    tr = S.s4_online_simulate(S.S4_OP_RK4, b, cost, restart_prob=0.5, ncalls=600)
+    assert starving not in tr
+    tiny = cube(16)  # 1 tile: no setting fills the device
+    tr = S.s4_online_simulate(S.S4_OP_RK4, tiny, cost, restart_prob=0.5, ncalls=600)
+    assert starving in tr
