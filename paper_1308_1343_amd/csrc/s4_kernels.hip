@@ -1598,13 +1598,16 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
     double *__restrict__ out = M.out[field];
     const double d1x = M.d1[0], d1y = M.d1[1], d1z = M.d1[2];
     const double d2x = M.d2[0], d2y = M.d2[1], d2z = M.d2[2];
+    const double cc = -30.0 * (d2x + d2y + d2z); // centre weight of the three D2
 
-    // Column queues of f, D1_x f and D1_y f at planes kk-4 .. kk: plane step
-    // t writes the newest plane to slot t mod 5, so the planes rotate through
-    // fixed registers (the loop below is unrolled ten-fold: five slots times
-    // two fetch buffers; every slot index is a compile-time constant).
+    // Column queues of f, D1_x f, D1_y f and D1_x f + D1_y f at planes kk-4
+    // .. kk: plane step t writes the newest plane to slot t mod 5, so the
+    // planes rotate through fixed registers (the loop below is unrolled
+    // ten-fold: five slots times two fetch buffers; every slot index is a
+    // compile-time constant).  D_xz + D_yz is D1_z of the sum queue.
     double fq[5] = {0, 0, 0, 0, 0}, xq[5] = {0, 0, 0, 0, 0}, yq[5] = {0, 0, 0, 0, 0};
-    double pq0 = 0, pq1 = 0, pq2 = 0; // D2_x + D2_y + D_xy at kk-2 .. kk
+    double sq[5] = {0, 0, 0, 0, 0};
+    double pq0 = 0, pq1 = 0, pq2 = 0; // off-centre D2_x + D2_y taps plus D_xy, at kk-2 .. kk
     // The loads of plane kk+1 are issued as plane kk starts, into the one of
     // two buffers that alternate planes (so no register a load is still
     // filling is copied), and fly across the plane's two barriers.
@@ -1655,27 +1658,26 @@ __global__ __launch_bounds__(NW * 64) void k_mixed(MixArgs M, int nxcd)
         lds_barrier();
         const int dd = w.ld;
         const double gxy = d1y * fma(8.0, D[dd + TX] - D[dd - TX], -(D[dd + 2 * TX] - D[dd - 2 * TX]));
-        const double pin = fma(d2x, fma(-30.0, fv, sx), fma(d2y, fma(-30.0, fv, sy), gxy));
+        const double pin = fma(d2x, sx, fma(d2y, sy, gxy));
         fq[S4] = fv;
         xq[S4] = gx;
         yq[S4] = gy;
+        sq[S4] = gx + gy;
         pq0 = pq1;
         pq1 = pq2;
         pq2 = pin;
         if (kk >= P.z0 + 2 && w.active) {
             const double gz = d1z * fma(8.0, fq[S3] - fq[S1], -(fq[S4] - fq[S0]));
-            const double d2zv = d2z * fma(-30.0, fq[S2], fma(16.0, fq[S1] + fq[S3], -(fq[S0] + fq[S4])));
-            const double gxz = d1z * fma(8.0, xq[S3] - xq[S1], -(xq[S4] - xq[S0]));
-            const double gyz = d1z * fma(8.0, yq[S3] - yq[S1], -(yq[S4] - yq[S0]));
+            // the centre taps of D2_x, D2_y and D2_z, and D2_z's others
+            const double d2c = fma(cc, fq[S2], d2z * fma(16.0, fq[S1] + fq[S3], -(fq[S0] + fq[S4])));
+            const double gxyz = d1z * fma(8.0, sq[S3] - sq[S1], -(sq[S4] - sq[S0]));
             const double ex = xq[S2], ey = yq[S2];
-            double q = M.a[0] * ex * ex;
-            q = fma(M.a[1] * ey, ey, q);
-            q = fma(M.a[2] * gz, gz, q);
-            q = fma(M.a[3] * ex, ey, q);
-            q = fma(M.a[4] * ex, gz, q);
-            q = fma(M.a[5] * ey, gz, q);
-            const double lin2 = pq0 + d2zv + gxz + gyz;
-            st(out + w.point(B, kk - 2), lin2 + q);
+            // the quadratic form in Horner-like groups:
+            // ex (A_xx ex + A_xy' ey + A_xz' gz) + ey (A_yy ey + A_yz' gz) + A_zz gz gz
+            double q = ex * fma(M.a[4], gz, fma(M.a[3], ey, M.a[0] * ex));
+            q = fma(ey, fma(M.a[5], gz, M.a[1] * ey), q);
+            q = fma(gz, M.a[2] * gz, q);
+            st(out + w.point(B, kk - 2), (pq0 + d2c + gxyz) + q);
         }
     };
     fetch(kfirst, F0);
