@@ -40,8 +40,8 @@ def test_wave256_rk4_100_steps_vs_oracle(ctx):
 
 def find_cand(ctx, op, b, kind, tile_x, threads, z_chunk):
     """Index of the candidate with these parameters (as s4_get_choice reports
-    them); kind "tiles" (the tile traversal: kernel op below 100) or "whole"
-    (the whole-step kernels: 102)."""
+    them); kind "tiles" (the tile traversal: kernel op below 100), "pairs"
+    (pair-lane tiles: 300 and up) or "whole" (the whole-step kernels: 102)."""
     nc = S.s4_get_choice(ctx, op, b)["ncandidates"]
     try:
         for c in range(nc):
@@ -51,7 +51,8 @@ def find_cand(ctx, op, b, kind, tile_x, threads, z_chunk):
                 continue  # a kernel set this op does not use
             ch = S.s4_get_choice(ctx, op, b)
             k = ch["kernel_op"]
-            if ((k < 100) if kind == "tiles" else (k == 102)) and \
+            want = k < 100 if kind == "tiles" else k >= 300 if kind == "pairs" else k == 102
+            if want and \
                     (ch["tile_x"], ch["threads"], ch["z_chunk"]) == (tile_x, threads, z_chunk):
                 return c
     finally:
@@ -60,9 +61,9 @@ def find_cand(ctx, op, b, kind, tile_x, threads, z_chunk):
 
 
 def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
-    """The 256^3 RHS in the tile the sweep picks for the benchmark (64 x 8
-    lanes, 64-plane chunks, on the tile traversal) and in every
-    other RHS candidate, against the oracle."""
+    """The 256^3 RHS in the tile the sweep picks for the benchmark (pair-lane
+    tiles of 64 x 8 points on 256 lanes, 64-plane chunks) and in every other
+    RHS candidate, against the oracle and bit for bit against each other."""
     d = W.wave256()
     g, n = d["ghost"], d["n"]
     uf = O.fill_ghosts_periodic(O.embed(d["u"], g), g)
@@ -70,7 +71,7 @@ def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
     u.copy_(torch.from_numpy(uf))
     b = S.box_of(u, g, d["dx"])
     want = O.wave_rhs(uf, g, d["dx"])
-    tuned = find_cand(ctx, S.S4_OP_WAVE_RHS, b, "tiles", 64, 512, 64)
+    tuned = find_cand(ctx, S.S4_OP_WAVE_RHS, b, "pairs", 64, 256, 64)
     k = cands_by_kind(ctx, S.S4_OP_WAVE_RHS, b)
     ref = None
     for cand in [tuned] + [c for c in k["tiles"] + k["rows"] + k["pairs"] if c != tuned]:
@@ -86,11 +87,12 @@ def test_wave256_rhs_benchmarked_tile_vs_oracle(ctx):
     S.s4_set_choice(ctx, S.S4_OP_WAVE_RHS, b, -1)
 
 
-def test_wave256_rk4_c2_benchmarked_setting_vs_oracle(ctx):
-    """The 256^3 RK4 with variable c^2 in the setting its sweep picks for the
-    benchmark: whole steps on 64 x 16 lanes (1024-lane workgroups, loads two
-    planes ahead) in 128-plane chunks, 20 steps against the oracle and bit for
-    bit against the per-stage kernels."""
+@pytest.mark.parametrize("tile_x,z_chunk", [(68, 32), (64, 128)])
+def test_wave256_rk4_c2_benchmarked_setting_vs_oracle(ctx, tile_x, z_chunk):
+    """The 256^3 RK4 with variable c^2 in the settings its sweep picks for the
+    benchmark: whole steps on 68 x 15 lanes in 32-plane chunks, and on 64 x 16
+    lanes (loads two planes ahead) in 128-plane chunks; 20 steps against the
+    oracle and bit for bit against the per-stage kernels."""
     d = W.wave256()
     g, n = d["ghost"], d["n"]
     c2h = 1.0 + 0.5 * W.uniform_pm1(d["seed"], 99, tuple(n[::-1]))
@@ -98,7 +100,7 @@ def test_wave256_rk4_c2_benchmarked_setting_vs_oracle(ctx):
     c2 = to_dev(c2h, n, g, fill=float("nan"))  # read at interior points only
     b = S.box_of(u, g, d["dx"])
     op = S.S4_OP_RK4 | S.S4_WITH_C2
-    whole = find_cand(ctx, op, b, "whole", 64, 1024, 128)
+    whole = find_cand(ctx, op, b, "whole", tile_x, 1024, z_chunk)
     S.s4_set_choice(ctx, op, b, whole)
     S.s4_rk4(ctx, b, [u], [r], [c2], d["dt"], 20, "graph")
     S.s4_set_choice(ctx, op, b, -1)
