@@ -273,8 +273,9 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_single(DevBox B, StageCoef K,
 // start 16-byte aligned.  Every lane moves 16-byte vectors (its column, the
 // halo pairs, the c^2 pair, the output pair) and reads its x taps as two
 // 16-byte LDS words, so a wavefront covers 128 contiguous points of a row;
-// the loads of a plane are issued PD steps ahead (6, or 4 with c^2 or two
-// halo slots per lane), from PD buffers used in turn.  Per point the arithmetic is that of run_item, so both give the
+// the loads of a plane are issued PD planes ahead (6, or 4 with c^2 or two
+// halo slots per lane), from PD buffers used in turn, and two planes share
+// one barrier.  Per point the arithmetic is that of run_item, so both give the
 // same values bit for bit.  Tile: 2 TXL x TY points, TY = NW * 64 / TXL; the
 // halo is two full rows below and above (corner pairs included) and one pair
 // on each side of every tile row.
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
     // six planes of loads in flight; four where the c^2 pairs or a second
     // halo slot would otherwise spill registers at four waves per SIMD
     constexpr int PLANE = T::LY * T::LX, PD = HASC2 || T::HS > 1 ? 4 : 6;
-    __shared__ __attribute__((aligned(16))) double lds[2 * PLANE];
+    __shared__ __attribute__((aligned(16))) double lds[4 * PLANE];
     const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     const ItemPos P = item_pos(B, item, T::TXP, T::TY);
     const int t = threadIdx.x, lx = t % TXL, ly = t / TXL;
@@ -358,41 +359,62 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
         if (P.z0 + p < P.z1)
             fetch(P.z0 + p, F[p]);
     }
-    auto step = [&](const int k, Fetched &X) {
-        q0 = q1;
-        q1 = q2;
-        q2 = q3;
-        q3 = q4;
-        q4 = X.q4;
-        double *L = lds + ((k - P.z0) & 1) * PLANE;
-        *(dvec2 *)(L + lc) = q2;
+    // the stencil of one plane from its LDS plane L and its column's five z
+    // values a0 .. a4, stored
+    auto plane = [&](const int k, const double *L, dvec2 a0, dvec2 a1, dvec2 a2, dvec2 a3, dvec2 a4, dvec2 cc) {
+        const dvec2 xm = *(const dvec2 *)(L + lc - 2), xp = *(const dvec2 *)(L + lc + 2);
+        const dvec2 ym2 = *(const dvec2 *)(L + lc - 2 * T::LX), ym1 = *(const dvec2 *)(L + lc - T::LX);
+        const dvec2 yp1 = *(const dvec2 *)(L + lc + T::LX), yp2 = *(const dvec2 *)(L + lc + 2 * T::LX);
+        dvec2 r;
+        r.x = lap4(B, a2.x, xm.x, xm.y, a2.y, xp.x, ym2.x, ym1.x, yp1.x, yp2.x, a0.x, a1.x, a3.x, a4.x);
+        r.y = lap4(B, a2.y, xm.y, a2.x, xp.x, xp.y, ym2.y, ym1.y, yp1.y, yp2.y, a0.y, a1.y, a3.y, a4.y);
+        if (HASC2) {
+            r.x = cc.x * r.x;
+            r.y = cc.y * r.y;
+        }
+        __builtin_nontemporal_store(r, (dvec2 *)(B.q[0] + col + zo(k)));
+    };
+    // Two planes per barrier: planes k and k + 1 (from buffers X and Y) go to
+    // the two LDS planes of one half of the double buffer, so a workgroup
+    // synchronises once per two planes.
+    auto step2 = [&](const int k, Fetched &X, Fetched &Y) {
+        const bool has1 = k + 1 < P.z1;
+        const dvec2 a0 = q1, a1 = q2, a2 = q3, a3 = q4, a4 = X.q4, b4 = Y.q4;
+        double *L0 = lds + (((k - P.z0) >> 1) & 1) * 2 * PLANE, *L1 = L0 + PLANE;
+        *(dvec2 *)(L0 + lc) = a2;
 #pragma unroll
         for (int s = 0; s < T::HS; ++s)
             if (hl[s] >= 0)
-                *(dvec2 *)(L + hl[s]) = X.h[s];
-        const dvec2 cc = X.c;
+                *(dvec2 *)(L0 + hl[s]) = X.h[s];
+        if (has1) {
+            *(dvec2 *)(L1 + lc) = a3;
+#pragma unroll
+            for (int s = 0; s < T::HS; ++s)
+                if (hl[s] >= 0)
+                    *(dvec2 *)(L1 + hl[s]) = Y.h[s];
+        }
+        const dvec2 cx = X.c, cy = Y.c;
         if (k + PD < P.z1)
             fetch(k + PD, X);
+        if (k + 1 + PD < P.z1)
+            fetch(k + 1 + PD, Y);
         lds_barrier();
         if (active) {
-            const dvec2 xm = *(const dvec2 *)(L + lc - 2), xp = *(const dvec2 *)(L + lc + 2);
-            const dvec2 ym2 = *(const dvec2 *)(L + lc - 2 * T::LX), ym1 = *(const dvec2 *)(L + lc - T::LX);
-            const dvec2 yp1 = *(const dvec2 *)(L + lc + T::LX), yp2 = *(const dvec2 *)(L + lc + 2 * T::LX);
-            dvec2 r;
-            r.x = lap4(B, q2.x, xm.x, xm.y, q2.y, xp.x, ym2.x, ym1.x, yp1.x, yp2.x, q0.x, q1.x, q3.x, q4.x);
-            r.y = lap4(B, q2.y, xm.y, q2.x, xp.x, xp.y, ym2.y, ym1.y, yp1.y, yp2.y, q0.y, q1.y, q3.y, q4.y);
-            if (HASC2) {
-                r.x = cc.x * r.x;
-                r.y = cc.y * r.y;
-            }
-            __builtin_nontemporal_store(r, (dvec2 *)(B.q[0] + col + zo(k)));
+            plane(k, L0, a0, a1, a2, a3, a4, cx);
+            if (has1)
+                plane(k + 1, L1, a1, a2, a3, a4, b4, cy);
         }
+        q0 = a1;
+        q1 = a2;
+        q2 = a3;
+        q3 = a4;
+        q4 = b4;
     };
     for (int k = P.z0; k < P.z1; k += PD) {
 #pragma unroll
-        for (int p = 0; p < PD; ++p)
+        for (int p = 0; p < PD; p += 2)
             if (k + p < P.z1)
-                step(k + p, F[p]);
+                step2(k + p, F[p], F[p + 1]);
     }
 }
 
