@@ -274,8 +274,8 @@ __global__ __launch_bounds__(NW * 64) void k_tiles_single(DevBox B, StageCoef K,
 // halo pairs, the c^2 pair, the output pair) and reads its x taps as two
 // 16-byte LDS words, so a wavefront covers 128 contiguous points of a row;
 // the loads of a plane are issued PD planes ahead (6, or 4 with c^2 or two
-// halo slots per lane), from PD buffers used in turn, and two planes share
-// one barrier.  Per point the arithmetic is that of run_item, so both give the
+// halo slots per lane), from PD buffers used in turn, and G planes share one
+// barrier (3, or 2 where PD is 4).  Per point the arithmetic is that of run_item, so both give the
 // same values bit for bit.  Tile: 2 TXL x TY points, TY = NW * 64 / TXL; the
 // halo is two full rows below and above (corner pairs included) and one pair
 // on each side of every tile row.
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
     // six planes of loads in flight; four where the c^2 pairs or a second
     // halo slot would otherwise spill registers at four waves per SIMD
     constexpr int PLANE = T::LY * T::LX, PD = HASC2 || T::HS > 1 ? 4 : 6;
-    __shared__ __attribute__((aligned(16))) double lds[4 * PLANE];
+    __shared__ __attribute__((aligned(16))) double lds[(PD % 3 == 0 ? 6 : 4) * PLANE];
     const int item = xcd_remap(blockIdx.x, gridDim.x, nxcd);
     const ItemPos P = item_pos(B, item, T::TXP, T::TY);
     const int t = threadIdx.x, lx = t % TXL, ly = t / TXL;
@@ -350,8 +350,9 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
         if (HASC2 && active)
             X.c = __builtin_nontemporal_load((const dvec2 *)(c2 + col + z));
     };
-    dvec2 q0 = 0.0, q1 = ld2(in + col + zo(P.z0 - 2)), q2 = ld2(in + col + zo(P.z0 - 1)),
-          q3 = ld2(in + col + zo(P.z0)), q4 = ld2(in + col + zo(P.z0 + 1));
+    // the column at planes k - 2 .. k + 1 before plane k (k + 2 arrives with its fetch)
+    dvec2 q1 = ld2(in + col + zo(P.z0 - 2)), q2 = ld2(in + col + zo(P.z0 - 1)), q3 = ld2(in + col + zo(P.z0)),
+          q4 = ld2(in + col + zo(P.z0 + 1));
     Fetched F[PD];
 #pragma unroll
     for (int p = 0; p < PD; ++p) {
@@ -374,47 +375,54 @@ __global__ __launch_bounds__(NW * 64, 4) void k_pairs_rhs(DevBox B, int nxcd)
         }
         __builtin_nontemporal_store(r, (dvec2 *)(B.q[0] + col + zo(k)));
     };
-    // Two planes per barrier: planes k and k + 1 (from buffers X and Y) go to
-    // the two LDS planes of one half of the double buffer, so a workgroup
-    // synchronises once per two planes.
-    auto step2 = [&](const int k, Fetched &X, Fetched &Y) {
-        const bool has1 = k + 1 < P.z1;
-        const dvec2 a0 = q1, a1 = q2, a2 = q3, a3 = q4, a4 = X.q4, b4 = Y.q4;
-        double *L0 = lds + (((k - P.z0) >> 1) & 1) * 2 * PLANE, *L1 = L0 + PLANE;
-        *(dvec2 *)(L0 + lc) = a2;
+    // G planes per barrier: planes k .. k + G - 1 (from buffers p .. p + G - 1)
+    // go to the G LDS planes of one half of the double buffer, so a
+    // workgroup synchronises once per G planes.
+    constexpr int G = PD % 3 == 0 ? 3 : 2; // planes per barrier
+    auto stepg = [&](const int k, const int p) {
+        // column values at planes k - 2 .. k + G + 1
+        dvec2 a[G + 4];
+        a[0] = q1;
+        a[1] = q2;
+        a[2] = q3;
+        a[3] = q4;
 #pragma unroll
-        for (int s = 0; s < T::HS; ++s)
-            if (hl[s] >= 0)
-                *(dvec2 *)(L0 + hl[s]) = X.h[s];
-        if (has1) {
-            *(dvec2 *)(L1 + lc) = a3;
+        for (int m = 0; m < G; ++m)
+            a[4 + m] = F[p + m].q4;
+        double *L = lds + (((k - P.z0) / G) & 1) * G * PLANE;
+        dvec2 cc[G];
 #pragma unroll
-            for (int s = 0; s < T::HS; ++s)
-                if (hl[s] >= 0)
-                    *(dvec2 *)(L1 + hl[s]) = Y.h[s];
+        for (int m = 0; m < G; ++m) {
+            if (m == 0 || k + m < P.z1) {
+                *(dvec2 *)(L + m * PLANE + lc) = a[2 + m];
+#pragma unroll
+                for (int s = 0; s < T::HS; ++s)
+                    if (hl[s] >= 0)
+                        *(dvec2 *)(L + m * PLANE + hl[s]) = F[p + m].h[s];
+            }
+            cc[m] = F[p + m].c;
         }
-        const dvec2 cx = X.c, cy = Y.c;
-        if (k + PD < P.z1)
-            fetch(k + PD, X);
-        if (k + 1 + PD < P.z1)
-            fetch(k + 1 + PD, Y);
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+            if (k + m + PD < P.z1)
+                fetch(k + m + PD, F[p + m]);
         lds_barrier();
         if (active) {
-            plane(k, L0, a0, a1, a2, a3, a4, cx);
-            if (has1)
-                plane(k + 1, L1, a1, a2, a3, a4, b4, cy);
+#pragma unroll
+            for (int m = 0; m < G; ++m)
+                if (m == 0 || k + m < P.z1)
+                    plane(k + m, L + m * PLANE, a[m], a[m + 1], a[m + 2], a[m + 3], a[m + 4], cc[m]);
         }
-        q0 = a1;
-        q1 = a2;
-        q2 = a3;
-        q3 = a4;
-        q4 = b4;
+        q1 = a[G];
+        q2 = a[G + 1];
+        q3 = a[G + 2];
+        q4 = a[G + 3];
     };
     for (int k = P.z0; k < P.z1; k += PD) {
 #pragma unroll
-        for (int p = 0; p < PD; p += 2)
+        for (int p = 0; p < PD; p += G)
             if (k + p < P.z1)
-                step2(k + p, F[p], F[p + 1]);
+                stepg(k + p, p);
     }
 }
 
