@@ -96,9 +96,9 @@ static int hip_fail(hipError_t e, const char *where)
 // tx x (nw*64/tx) (any number of boxes, levels included); variant 4 (any
 // number of periodic boxes, or a wide level) runs a whole RK4 step per pass
 // on the widened tile of variant 1 (tx 68: 68 x 15 on 1020 of 1024 lanes),
-// stages 1-2 on all lanes and 3-4 on the output tile; variant 5 (the wave RHS on boxes with an even n[0] and even
-// strides) is the tile traversal with two x points per lane, tile
-// 2 tx x (nw*64/tx).  tz is the z chunk (0 = whole box; for variant 4 on one
+// stages 1-2 on all lanes and 3-4 on the output tile; variant 5 (the wave
+// RHS on boxes with an even n[0] and even strides) is the tile traversal
+// with two x points per lane, tile 2 tx x (nw*64/tx).  tz is the z chunk (0 = whole box; for variant 4 on one
 // box, equal shares of the tile-plane sequence).  Candidate indices are
 // stable across ops: an op skips the candidates it cannot use.
 struct Cand {
@@ -648,7 +648,6 @@ struct Choice {
 
 static void online_harvest(OnlineSetup &st);
 
-// caller holds ctx->mu
 // The settings the on-line search may visit: those the op can run, less
 // those whose launches hand fewer work items than a quarter of the CUs
 // while another setting gives every CU one (with most of the device idle
@@ -685,6 +684,7 @@ static std::vector<int> online_allowed(const s4_ctx *ctx, int op, const s4_box *
     return v;
 }
 
+// caller holds ctx->mu
 static OnlineSetup &online_setup(s4_ctx *ctx, const std::string &key, int op, const s4_box *b, int nbox,
                                  int level)
 {
